@@ -1,0 +1,127 @@
+"""Pins of the oracle's batch path (section 8, Table 2, Algorithm 6): the paper's net-update
+and similar-sink examples, Inc-bSR equal to recompute on random mixed batches, and the
+memory-efficient column mode (Algorithm 7) equal to recompute."""
+import json
+import os
+
+import numpy as np
+
+import workloads as W
+from oracle import graph as Gr
+from oracle import incremental as I
+from oracle import simrank as O
+
+C = 0.6
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "worked_examples.json")))
+
+
+def test_paper_net_update_and_partition():
+    g = GOLD["batch_example"]
+    names = list(g["nodes_existing"]) + ["q", "p", "r"]      # new ids by first appearance
+    idx = {x: p for p, x in enumerate(names)}
+    bi = [idx[a] for a, _, _ in g["updates"]]
+    bj = [idx[b] for _, b, _ in g["updates"]]
+    bo = [op for _, _, op in g["updates"]]
+    plus, minus = I.net_update(bi, bj, bo)
+    nm = lambda e: [names[e[0]], names[e[1]]]
+    assert sorted(map(nm, plus)) == sorted(g["net_plus"])
+    assert sorted(map(nm, minus)) == sorted(g["net_minus"])
+    # a graph on a..o that holds the deleted edge (f, b)
+    n = 15
+    src = [idx["f"], idx["a"], idx["c"]]
+    dst = [idx["b"], idx["i"], idx["f"]]
+    plan, n_new = I.plan_batch(n, src, dst, bi, bj, bo)
+    assert n_new == 18
+    got_plus = sorted(([names[x] for x in b["I"]], names[b["j"]]) for b in plan if b["op"] > 0)
+    exp_plus = sorted((sorted(I_), j) for I_, j in g["plus_blocks"])
+    assert got_plus == exp_plus
+    got_minus = [([names[x] for x in b["I"]], names[b["j"]]) for b in plan if b["op"] < 0]
+    assert got_minus == [(I_, j) for I_, j in g["minus_blocks"]]
+    cases = {(tuple(names[x] for x in b["I"]), names[b["j"]]): b["case"] for b in plan}
+    assert cases[(("q",), "i")] == 2           # new source into existing sink
+    assert cases[(("j", "k"), "i")] == 0       # existing sources
+    assert cases[(("p", "r"), "f")] == 2
+    # deletions are planned before insertions
+    assert plan[0]["op"] == -1
+
+
+def test_net_update_rejects_double_insert():
+    import pytest
+    with pytest.raises(ValueError):
+        I.net_update([0, 0], [1, 1], [1, 1])
+
+
+def test_inc_bsr_matches_recompute():
+    rng = np.random.default_rng(51)
+    worst = 0.0
+    for trial in range(25):
+        n = int(rng.integers(6, 10))
+        s, d = W.chung_lu(n, int(rng.integers(n, 2 * n)), seed=500 + trial)
+        Q = Gr.transition_matrix(n, s, d)
+        S = O.fixed_point(Q, C)
+        b, cnt = W.batch_stream(n, s, d, 1, 6, 600 + trial, min_batch=3)
+        bi, bj, bo = b[0]
+        for form in ("closed", "direct"):
+            Sn, plan = I.inc_bsr(n, s, d, S, bi, bj, bo, C, 80, form)
+            plus, minus = I.net_update(bi, bj, bo)
+            n2, s2, d2 = Gr.apply_edges(
+                n, s, d, [e[0] for e in plus + minus], [e[1] for e in plus + minus],
+                [1] * len(plus) + [-1] * len(minus), n_new=cnt[0])
+            S2 = O.fixed_point(Gr.transition_matrix(n2, s2, d2), C)
+            worst = max(worst, np.abs(Sn - S2).max())
+    assert worst < 1e-13
+
+
+def test_plan_blocks_cover_net_update_once():
+    n = 300
+    s, d = W.chung_lu(n, 1500, seed=61)
+    batches, counts = W.batch_stream(n, s, d, 3, 300, 62)
+    cur_s, cur_d, cur_n = s, d, n
+    for (bi, bj, bo), nn in zip(batches, counts):
+        plan, n_new = I.plan_batch(cur_n, cur_s, cur_d, bi, bj, bo)
+        assert n_new == nn
+        plus, minus = I.net_update(bi, bj, bo)
+        got = sorted((i, b["j"], b["op"]) for b in plan for i in b["I"])
+        exp = sorted([(i, j, 1) for i, j in plus] + [(i, j, -1) for i, j in minus])
+        assert got == exp
+        for b in plan:
+            assert b["I"] == sorted(b["I"])
+        cur_n, cur_s, cur_d = Gr.apply_edges(
+            cur_n, cur_s, cur_d, [e[0] for e in plus + minus], [e[1] for e in plus + minus],
+            [1] * len(plus) + [-1] * len(minus), n_new=nn)
+
+
+def test_column_mode_matches_recompute():
+    n = 60
+    s, d = W.chung_lu(n, 240, seed=71)
+    Q = Gr.transition_matrix(n, s, d)
+    S = O.fixed_point(Q, C)
+    i_s, j_s = W.insertion_stream(n, s, d, 3, seed=72)
+    cur_s, cur_d = s.astype(np.int64), d.astype(np.int64)
+    for i, j in zip(i_s.tolist(), j_s.tolist()):
+        cols = [0, 3, i, j, 59]
+        got = I.delta_columns_c0(n, cur_s, cur_d, i, j, cols, C, 70, 70)
+        n2, s2, d2 = Gr.apply_edges(n, cur_s, cur_d, [i], [j], [1])
+        S_new = O.fixed_point(Gr.transition_matrix(n2, s2, d2), C)
+        S_old = O.fixed_point(Gr.transition_matrix(n, cur_s, cur_d), C)
+        assert np.abs(got - (S_new - S_old)[:, cols]).max() < 1e-13
+        cur_s, cur_d = s2.astype(np.int64), d2.astype(np.int64)
+
+
+def test_algorithm7_column_all_cases():
+    """Algorithm 7 with node insertions (C0-C3) for one carried column x, deep K."""
+    n = 40
+    s, d = W.chung_lu(n, 150, seed=81)
+    Q = Gr.transition_matrix(n, s, d)
+    S = O.fixed_point(Q, C)
+    es = set(zip(s.tolist(), d.tolist()))
+    edges = [(1, 2) if (1, 2) not in es else (2, 1), (5, n), (n + 1, 7), (n + 2, n + 3)]
+    for x in (0, 7, n):
+        if x >= n:
+            continue
+        col = I.inc_sr_all_p_column(n, s, d, S[:, x], x, edges, C, 70)
+        n2, s2, d2 = Gr.apply_edges(n, s, d, [e[0] for e in edges], [e[1] for e in edges],
+                                    [1] * len(edges))
+        S2 = O.fixed_point(Gr.transition_matrix(n2, s2, d2), C)
+        assert np.abs(col - S2[:, x]).max() < 1e-13

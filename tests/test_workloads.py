@@ -1,0 +1,48 @@
+"""The seeded generators: determinism, simple-digraph properties, valid update streams."""
+import numpy as np
+
+import workloads as W
+
+
+def test_chung_lu_simple_and_deterministic():
+    s, d = W.chung_lu(1000, 5000, seed=1001)
+    assert len(s) == 5000
+    assert (s != d).all()
+    assert len(set(zip(s.tolist(), d.tolist()))) == 5000
+    s2, d2 = W.chung_lu(1000, 5000, seed=1001)
+    assert np.array_equal(s, s2) and np.array_equal(d, d2)
+    deg = np.bincount(d, minlength=1000)
+    assert deg.max() > 50          # power-law hubs
+    assert (deg == 0).mean() > 0.05
+
+
+def test_streams_are_valid():
+    s, d = W.chung_lu(500, 2500, seed=3)
+    es = set(zip(s.tolist(), d.tolist()))
+    i, j, o = W.mixed_stream(500, s, d, 300, 0.7, 4)
+    for a, b, op in zip(i.tolist(), j.tolist(), o.tolist()):
+        assert a != b
+        if op > 0:
+            assert (a, b) not in es
+            es.add((a, b))
+        else:
+            assert (a, b) in es
+            es.remove((a, b))
+    assert 0.55 < (o > 0).mean() < 0.85
+
+
+def test_batch_stream_new_ids_dense():
+    s, d = W.chung_lu(400, 2000, seed=5)
+    batches, counts = W.batch_stream(400, s, d, 4, 200, 6)
+    cur = 400
+    for (i, j, o), nn in zip(batches, counts):
+        ids = sorted({x for x in np.concatenate([i, j]).tolist() if x >= cur})
+        assert ids == list(range(cur, nn))
+        cur = nn
+
+
+def test_loss_pairs_unique():
+    a, b, t = W.loss_pairs(100, 500, 7)
+    assert (a < b).all()
+    assert len(set(zip(a.tolist(), b.tolist()))) == 500
+    assert (t >= 0).all() and (t < 0.2).all()
