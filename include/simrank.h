@@ -1,0 +1,222 @@
+/*
+ * libsimrank: incremental all-pairs SimRank on one MI355X (gfx950) GPU.
+ *
+ * Method: Yu, Lin, Zhang, McCann, "Dynamical SimRank Search on Time-Varying Networks".
+ * SimRank is the unique fixed point of  S = C Q S Q^T + (1 - C) I  (section 3.1, eq (03a)),
+ * Q the backward transition matrix (Q[a][x] = 1/indeg(a) for an edge x -> a). A link update
+ * changes Q by a rank-one term (Theorems 1 and 9) and S by Delta S = M + M^T, where M solves
+ * a rank-one Sylvester equation (Theorem 2, eq (14)); the library evaluates M by K sparse
+ * matrix-vector products (eq (16a)), restricts the work to the affected areas of Theorem 4,
+ * handles edges that bring new nodes (section 6, cases C1-C3), batches of edges grouped by
+ * shared sink (section 8, Table 2, Algorithm 6), and a column-by-column mode that never
+ * stores S (section 7, Algorithm 7).
+ *
+ * Conventions for every entry point:
+ *  - An edge (i, j) means i -> j; j is the sink whose row of Q changes.
+ *  - Node ids are int32 in [0, n). New nodes take the next ids n, n+1, ... (section 6 remark).
+ *  - Host arrays passed in are borrowed for the duration of the call only.
+ *  - Device pointers passed in are owned by the caller and must stay valid until the
+ *    context's stream has executed the work (synchronise the stream or call sr_synchronize).
+ *  - All work is enqueued on the HIP stream given to init_simrank and is asynchronous,
+ *    except where a call says it synchronises.
+ *  - Errors are status codes; nothing is thrown across the ABI. A validation error
+ *    (SR_EINVAL .. SR_EMODE) leaves the context unchanged. SR_EHIP (a HIP runtime error)
+ *    poisons the context: every later call except sr_destroy returns SR_EHIP.
+ *  - Matrices are row-major. S is symmetric, so row x of S is also column x.
+ */
+#ifndef LIBSIMRANK_SIMRANK_H
+#define LIBSIMRANK_SIMRANK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sr_ctx sr_ctx;
+
+typedef enum sr_status {
+  SR_OK = 0,
+  SR_EINVAL = -1,     /* malformed argument (null pointer, bad config, bad op)          */
+  SR_ERANGE = -2,     /* node id out of range, or new node ids not dense                */
+  SR_EEXIST = -3,     /* insertion of an edge that exists                               */
+  SR_ENOENT = -4,     /* deletion of an edge that does not exist                        */
+  SR_ESELF = -5,      /* self-loop                                                      */
+  SR_ECAPACITY = -6,  /* node or edge capacity, or scratch capacity, exceeded           */
+  SR_ENOMEM = -7,     /* device or host allocation failed                               */
+  SR_EMODE = -8,      /* call not available in this context's mode or precision        */
+  SR_EHIP = -9        /* HIP runtime error; the context is poisoned                     */
+} sr_status;
+
+/* Storage of the dense S. */
+enum {
+  SR_S_FP64 = 0,       /* float64                                                         */
+  SR_S_FP32_HILO = 1,  /* float32 value + float32 compensation; updates add in float64     */
+  SR_S_FP32 = 2        /* plain float32 (no compensation), for precision comparisons      */
+};
+/* Context mode. */
+enum { SR_DENSE = 0, SR_COLUMN = 1 };
+/* Which gamma formula a unit or block update uses (section 4). */
+enum {
+  SR_GAMMA_CLOSED = 0, /* Theorem 3 / Theorem 9 / Table 2 closed form (2 columns of S)     */
+  SR_GAMMA_DIRECT = 1  /* Theorem 2 direct form w = Q S v + (v^T S v / 2) u                */
+};
+/* What query_column returns. */
+enum { SR_COL_S = 0, SR_COL_DELTA = 1 };
+
+typedef struct sr_config {
+  double C;              /* damping factor, 0 < C < 1 (paper default 0.6)                  */
+  int32_t K;             /* iterations: the series keeps K + 1 terms, k = 0..K (Alg. 1)     */
+  int32_t K_ps;          /* PartialSim depth in column mode (section 7); 0 means K          */
+  int32_t s_prec;        /* SR_S_FP64 | SR_S_FP32_HILO | SR_S_FP32 (dense mode)             */
+  int32_t mode;          /* SR_DENSE | SR_COLUMN                                            */
+  int32_t gamma_form;    /* SR_GAMMA_CLOSED | SR_GAMMA_DIRECT                               */
+  int32_t prune;         /* 1: restrict the S update to the affected areas (Theorem 4)      */
+  int64_t node_cap;      /* maximum node count over the context's life (>= n); 0 means n    */
+  int64_t edge_cap;      /* maximum edge count (>= m); 0 means 2 m + 1024                   */
+  double init_tol;       /* fixed-point step tolerance of the initial S (max-abs)           */
+  int32_t init_max_iter; /* iteration cap of the initial fixed point                        */
+  int32_t batch_chunk;   /* low-rank blocks applied per fused pass of apply_batch (>= 1)   */
+  int32_t fused_batch;   /* 1: apply_batch defers low-rank blocks into fused passes;
+                            0: each block updates S on its own                              */
+  int32_t reserved;
+} sr_config;
+
+/* Per-update statistics (filled when a non-null pointer is passed; the call then
+ * synchronises the stream). */
+typedef struct sr_update_stats {
+  int32_t case_id;     /* 0 both ends existing, 1 new sink, 2 new source, 3 both new       */
+  int32_t op;          /* +1 insert, -1 delete                                             */
+  int64_t d_j;         /* in-degree of the sink before the update                          */
+  int64_t n_after;     /* node count after the update                                      */
+  int64_t aff_A;       /* |A_hat| (union of the A_k of Theorem 4)                          */
+  int64_t aff_B;       /* |B_hat|                                                          */
+  int64_t aff_AB;      /* |A_hat & B_hat|                                                  */
+  int64_t pairs;       /* S entries written: |A_hat x B_hat u B_hat x A_hat|, or n^2       */
+  double bound;        /* truncation bound 2 C^(K+2)/(1-C) |u|_inf |w|_inf of Delta S      */
+} sr_update_stats;
+
+typedef struct sr_batch_stats {
+  int64_t edges_in;       /* edges passed in                                               */
+  int64_t edges_net;      /* edges left after insert/delete cancellation                   */
+  int64_t blocks;         /* similar-sink blocks processed                                 */
+  int64_t blocks_case[4]; /* blocks per case C0..C3                                        */
+  int64_t lowrank_blocks; /* blocks that produced a low-rank Delta S (C0 and C2)           */
+  int64_t n_after;        /* node count after the batch                                    */
+  int64_t pairs;          /* S entries updated, summed over low-rank blocks, plus border
+                             and diagonal writes of C1 / C2 / C3 blocks                    */
+  int32_t fused_passes;   /* passes over S made by the fused apply                         */
+  int32_t reserved;
+} sr_batch_stats;
+
+/* Fills *cfg with defaults: C = 0.6, K = 15, K_ps = 30, SR_S_FP64, SR_DENSE,
+ * SR_GAMMA_CLOSED, prune = 1, capacities 0 (derived), init_tol = 1e-15, init_max_iter = 400,
+ * batch_chunk = 64, fused_batch = 1. */
+sr_status sr_default_config(sr_config* cfg);
+
+/* Creates a context for the digraph with n nodes and m edges src[e] -> dst[e] (host arrays,
+ * no self-loops, no duplicates). weight: host float64 per edge, or NULL for an unweighted
+ * graph (a weighted graph supports init, queries and backward; incremental updates of a
+ * weighted graph return SR_EMODE). S0: NULL to compute the initial S on the device by the
+ * fixed-point iteration of eq (03a) until the max-abs step is <= cfg->init_tol; otherwise a
+ * device pointer to an n x n float64 row-major S (leading dimension n), which is copied.
+ * In column mode S is never stored and S0 must be NULL. hip_stream: a hipStream_t (NULL for
+ * the null stream). Synchronises the stream before returning. On success *out owns every
+ * device allocation of the context. */
+sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                       const int32_t* dst, const double* weight, const sr_config* cfg,
+                       const void* S0, void* hip_stream);
+
+/* Applies one edge update, op = +1 insert or -1 delete (Algorithms 1 and 2, Theorem 9;
+ * node insertions: Algorithms 3, 4, 5 with the new ids i == n (C2), j == n (C1), or
+ * i == n, j == n + 1 (C3)). Dense mode updates S; column mode keeps the series vectors of
+ * this update for query_columns / query_column(SR_COL_DELTA) and supports insertions
+ * between existing nodes only. stats: NULL, or filled after synchronising. */
+sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
+                            sr_update_stats* stats);
+
+/* Applies a batch of cnt edge updates (host arrays; op[e] = +1 or -1) by Algorithm 6:
+ * cancellation of insert/delete pairs, similar-sink partition, deletion blocks, then
+ * insertion blocks split by whether their sources already exist, each by the Table 2
+ * formula of its case. New node ids in the batch must be exactly n .. n + N - 1.
+ * A net count outside {-1, 0, +1} for an edge, an insertion of an existing edge or a
+ * deletion of a missing one rejects the whole batch before any change. Dense mode only.
+ * stats: NULL, or filled after synchronising. */
+sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* src, const int32_t* dst,
+                      const int8_t* op, sr_batch_stats* stats);
+
+/* Writes column x as n float64 values to out_dev (device). what = SR_COL_S: the current
+ * S[:, x] (dense mode). what = SR_COL_DELTA: Delta S[:, x] of the last apply_edge_update
+ * (both modes; eq (71): M_K[:, x] + M_K[x, :]^T). */
+sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev);
+
+/* Writes ncols columns as float32 to out_dev (device), column c at out_dev + c * ld_out,
+ * ld_out >= n. cols: host array of node ids. Column mode: Delta S[:, cols] of the last
+ * apply_edge_update, by eq (71) for all columns at once. Dense mode: S[:, cols]. */
+sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* out_dev,
+                        int64_t ld_out);
+
+/* Gathers S[a[p], b[p]] for npairs pairs into out_dev (float64); a_dev, b_dev device int32.
+ * Dense mode. */
+sr_status sr_gather_pairs(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev,
+                          const int32_t* b_dev, double* out_dev);
+
+/* Reverse-mode derivative of a loss L(S) with respect to the edge weights of the initial
+ * graph (weighted or unweighted; an unweighted graph has all weights 1). Inputs: npairs
+ * pairs (a_dev[p], b_dev[p]) with dL/dS[a,b] = g_dev[p] (all device arrays). Solves the
+ * transposed Sylvester equation Lam = G + C Q^T Lam Q to the init tolerance and writes
+ * dL/dw for every edge, in the order of init_simrank's edge arrays, to dL_dw_dev (device,
+ * m float64). Requires a dense-mode context whose graph has not been updated since init
+ * (SR_EMODE otherwise). Allocates three n x n float64 work matrices for the call. */
+sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int32_t* b_dev,
+                   const double* g_dev, double* dL_dw_dev);
+
+/* Affected-area sets of the last dense apply_edge_update with pruning: level = -1 gives
+ * A_hat and B_hat, level k in 0..K gives A_k and B_k (Theorem 4, eq (41)), as ascending
+ * int32 lists written to A_dev / B_dev (device, capacity n each; NULL to only count).
+ * Synchronises; *nA, *nB receive the sizes. */
+sr_status sr_get_aff(sr_ctx* ctx, int32_t level, int32_t* A_dev, int64_t* nA, int32_t* B_dev,
+                     int64_t* nB);
+
+/* Copies S[0:n, 0:n] as float64 into out_dev (device) with leading dimension ld >= n.
+ * Dense mode. */
+sr_status sr_copy_S(sr_ctx* ctx, double* out_dev, int64_t ld);
+
+/* Current node and edge counts. */
+sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m);
+
+/* The block plan of the last apply_batch, as int32 records
+ * [case, op, j, d_j, delta, i_1, ..., i_delta] concatenated, into out (host, capacity cap).
+ * *len receives the number of int32 values (also when out is NULL or cap is too small). */
+sr_status sr_last_plan(sr_ctx* ctx, int32_t* out, int64_t cap, int64_t* len);
+
+/* Waits for all work enqueued by the context. */
+sr_status sr_synchronize(sr_ctx* ctx);
+
+/* Releases every allocation of the context; ctx may be NULL. */
+sr_status sr_destroy(sr_ctx* ctx);
+
+/* Static description of a status code. */
+const char* sr_strerror(sr_status status);
+
+/* Diagnostics: kernel timing of the S-update launches. enable = 1 records a pair of HIP events
+ * on the context's stream around every S-update launch (single-update and fused-batch
+ * kernels); 0 stops recording. */
+sr_status sr_profile(sr_ctx* ctx, int32_t enable);
+
+/* Synchronises, then returns the summed elapsed milliseconds of the recorded S-update
+ * launches (*ms) and their count (*launches); reset = 1 clears the record. */
+sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
+
+/* Diagnostics: runs one v_mfma_f64_16x16x4_f64 on a single wave with lane l supplying
+ * a_dev[l] and b_dev[l] (64 device doubles each) and writes the four accumulator values held
+ * by lane l to out_dev[4 l .. 4 l + 3] (256 device doubles). Used by the tests to confirm the
+ * operand and accumulator lane layout the update kernel assumes. Asynchronous on hip_stream. */
+sr_status sr_mfma_layout_probe(const double* a_dev, const double* b_dev, double* out_dev,
+                               void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBSIMRANK_SIMRANK_H */

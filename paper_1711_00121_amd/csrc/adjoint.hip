@@ -1,0 +1,143 @@
+// Edge-weight gradient of a loss on S (not in the paper; it follows from eq (03a)).
+//
+// With G = dL/dS at the loss pairs, Lam = G + C Q^T Lam Q is the adjoint of eq (03a) and
+// dL/dQ = C (Lam + Lam^T) Q S for symmetric S. Sig = Lam + Lam^T solves
+// Sig = (G + G^T) + C Q^T Sig Q, so only the symmetric Sig is iterated. Row normalisation
+// Q[x][y] = w(y -> x) / W_x gives dL/dw(y -> x) = (dL/dQ[x][y] - sum_y' Q[x][y'] dL/dQ[x][y'])/W_x.
+#include "kernels.h"
+
+namespace sr {
+
+namespace {
+
+constexpr int kB = 256;
+
+inline int64_t ldi_of(int64_t n) { return (n + 63) / 64 * 64; }
+
+__global__ __launch_bounds__(kB) void scatter_sym_kernel(double* G, int64_t ldi, int64_t np,
+                                                         const int32_t* __restrict__ pa,
+                                                         const int32_t* __restrict__ pb,
+                                                         const double* __restrict__ g) {
+  const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (p >= np) return;
+  const int64_t a = pa[p], b = pb[p];
+  atomicAdd(G + a * ldi + b, g[p]);
+  atomicAdd(G + b * ldi + a, g[p]);
+}
+
+__global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, int64_t n,
+                                                          int64_t ldi,
+                                                          const double* __restrict__ X,
+                                                          double* __restrict__ Y, double scale,
+                                                          const double* __restrict__ Gadd,
+                                                          const double* __restrict__ prev,
+                                                          unsigned long long* maxdiff) {
+  __shared__ double red[kB / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t c = ((int64_t)blockIdx.y * kB + threadIdx.x) * 2;
+  const int len = out.len[b];
+  const int st = out.start[b];
+  double2 acc = make_double2(0.0, 0.0);
+  if (c < n) {
+    for (int p = 0; p < len; ++p) {
+      const int64_t a = out.idx[st + p];
+      const double qa = q.W ? out.w[st + p] / q.W[a] : 1.0 / (double)q.in.len[a];
+      const double2 v = *reinterpret_cast<const double2*>(X + a * ldi + c);
+      acc.x += qa * v.x;
+      acc.y += qa * v.y;
+    }
+  }
+  double diff = 0.0;
+  if (c < n) {
+    double2 o = make_double2(scale * acc.x, scale * acc.y);
+    if (Gadd) {
+      const double2 gv = *reinterpret_cast<const double2*>(Gadd + b * ldi + c);
+      o.x += gv.x;
+      o.y += gv.y;
+    }
+    if (c + 1 >= n) o.y = 0.0;
+    *reinterpret_cast<double2*>(Y + b * ldi + c) = o;
+    if (prev) {
+      const double2 pv = *reinterpret_cast<const double2*>(prev + b * ldi + c);
+      diff = fmax(fabs(o.x - pv.x), (c + 1 < n) ? fabs(o.y - pv.y) : 0.0);
+    }
+  }
+  if (maxdiff) {
+    for (int o = 32; o > 0; o >>= 1) diff = fmax(diff, __shfl_xor(diff, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = diff;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = red[0];
+      for (int w = 1; w < kB / 64; ++w) m = fmax(m, red[w]);
+      atomicMax(maxdiff, (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kB / 64; ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(kB) void edge_grad_kernel(DevQ q, int64_t n, int64_t ldi,
+                                                       const double* __restrict__ Sig,
+                                                       const double* __restrict__ T, double C,
+                                                       const int32_t* __restrict__ slot_edge,
+                                                       double* __restrict__ dq,
+                                                       double* __restrict__ dw) {
+  __shared__ double red[kB / 64];
+  const int64_t x = blockIdx.x;
+  const int len = q.in.len[x];
+  if (len == 0) return;
+  const int st = q.in.start[x];
+  const double* sx = Sig + x * ldi;
+  double rowterm = 0.0;
+  for (int p = 0; p < len; ++p) {
+    const int64_t y = q.in.idx[st + p];
+    const double* ty = T + y * ldi;
+    double part = 0.0;
+    for (int64_t c = threadIdx.x; c < n; c += kB) part += sx[c] * ty[c];
+    const double d = C * block_sum(part, red);
+    if (threadIdx.x == 0) dq[st + p] = d;
+    const double qxy = q.W ? q.in.w[st + p] / q.W[x] : 1.0 / (double)len;
+    rowterm += qxy * d;
+  }
+  __syncthreads();
+  const double Wx = q.W ? q.W[x] : (double)len;
+  for (int p = threadIdx.x; p < len; p += kB) {
+    const int32_t e = slot_edge[st + p];
+    if (e >= 0) dw[e] = (dq[st + p] - rowterm) / Wx;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_scatter_pairs_sym(double* G, int64_t n, int64_t np, const int32_t* a,
+                                    const int32_t* b, const double* g, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  scatter_sym_kernel<<<(unsigned)((np + kB - 1) / kB), kB, 0, s>>>(G, ldi_of(n), np, a, b, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_qt_rows(const DevQ& q, const DevAdj& out, int64_t n, const double* X,
+                               double* Y, double scale, const double* Gadd, const double* prev,
+                               unsigned long long* maxdiff, hipStream_t s) {
+  dim3 grid((unsigned)n, (unsigned)((n + 2 * kB - 1) / (2 * kB)));
+  spmm_qt_rows_kernel<<<grid, kB, 0, s>>>(q, out, n, ldi_of(n), X, Y, scale, Gadd, prev,
+                                          maxdiff);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const double* T,
+                            double C, const int32_t* slot_edge, double* dq, double* dw,
+                            hipStream_t s) {
+  edge_grad_kernel<<<(unsigned)n, kB, 0, s>>>(q, n, ldi_of(n), Sig, T, C, slot_edge, dq, dw);
+  return hipGetLastError();
+}
+
+}  // namespace sr

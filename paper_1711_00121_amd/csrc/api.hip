@@ -1,0 +1,1350 @@
+// C-ABI entry points of libsimrank and the host orchestration behind them.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "hostgraph.h"
+#include "kernels.h"
+#include "simrank.h"
+
+using namespace sr;
+
+// Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
+// process them in chunks (see graph.hip).
+struct HeavySet {
+  std::set<int32_t> rows;
+  std::vector<int32_t> list;
+  int32_t maxc = 1;
+  bool dirty = true;
+  int32_t* d_rows = nullptr;
+  int64_t cap_rows = 0;
+  double* d_partial = nullptr;
+  int64_t cap_slots = 0;
+  uint32_t* d_counter = nullptr;
+};
+
+struct sr_ctx {
+  sr_config cfg{};
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  bool weighted = false;
+  bool updated = false;  // graph changed since init
+  int64_t node_cap = 0, edge_cap = 0, slot_cap = 0;
+  HostGraph g;
+  std::vector<int32_t> src0, dst0;  // initial edges (the order of backward's output)
+  std::vector<double> w0;
+  std::vector<int32_t> slot_edge0;  // in-list slot -> initial edge index
+
+  int32_t* d_adj[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* d_in_w = nullptr;
+  double* d_out_w = nullptr;
+  double* d_W = nullptr;
+
+  SView S{};
+  void* S_mem[2] = {nullptr, nullptr};
+
+  double *SI = nullptr, *Sj = nullptr, *QSI = nullptr, *zbuf = nullptr, *Qz = nullptr,
+         *zsum = nullptr, *ytmp = nullptr;
+  double* P = nullptr;
+  int pld = 0;  // doubles per panel row (one block)
+  double* Pb = nullptr;  // fused batch panel: node_cap x (pld * batch_chunk)
+  double* wts = nullptr;  // panel-correction weights: 2 * pld * batch_chunk
+  uint32_t *suppI = nullptr, *suppJ = nullptr, *Abits = nullptr, *Bbits = nullptr,
+           *Ahat = nullptr, *Bhat = nullptr;
+  int W = 0;
+  int32_t* rowlist = nullptr;
+  int32_t* d_ids = nullptr;  // staging for query ids (capacity ids_cap)
+  int64_t ids_cap = 0;
+  int64_t* d_cnt = nullptr;
+  unsigned long long* d_max = nullptr;
+  int64_t* h_cnt = nullptr;
+  unsigned long long* h_max = nullptr;
+
+  int last_r = 0;          // panel columns of the last unit update (0: none)
+  bool last_aff = false;   // AFF bitmaps hold the last update
+  std::vector<int32_t> last_plan;
+
+  double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) x node_cap
+
+  HeavySet hin, hout;      // heavy in-rows (Q) and out-rows (Q^T)
+
+  bool profiling = false;  // bracket S-update launches with events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+};
+
+namespace {
+
+sr_status fail_hip(sr_ctx* c) {
+  if (c) c->poisoned = true;
+  return SR_EHIP;
+}
+
+#define HC(expr)                                 \
+  do {                                           \
+    hipError_t e__ = (expr);                     \
+    if (e__ != hipSuccess) return fail_hip(ctx); \
+  } while (0)
+
+int round4(int x) { return (x + 3) / 4 * 4; }
+
+DevQ devq(const sr_ctx* c) {
+  DevQ q;
+  q.in.start = c->d_adj[0];
+  q.in.len = c->d_adj[1];
+  q.in.idx = c->d_adj[2];
+  q.in.w = c->weighted ? c->d_in_w : nullptr;
+  q.W = c->weighted ? c->d_W : nullptr;
+  return q;
+}
+
+DevAdj devout(const sr_ctx* c) {
+  DevAdj a;
+  a.start = c->d_adj[3];
+  a.len = c->d_adj[4];
+  a.idx = c->d_adj[5];
+  a.w = c->weighted ? c->d_out_w : nullptr;
+  return a;
+}
+
+AdjPtrs adjptrs(const sr_ctx* c) {
+  AdjPtrs t;
+  for (int k = 0; k < 6; ++k) t.p[k] = c->d_adj[k];
+  return t;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  return hipMalloc((void**)p, (size_t)count * sizeof(T));
+}
+
+void heavy_touch(HeavySet& H, const SlotList& L, int32_t r) {
+  const int32_t len = L.len[r];
+  const bool heavy = len > kLight;
+  const bool was = H.rows.count(r) != 0;
+  if (heavy != was) {
+    if (heavy) H.rows.insert(r); else H.rows.erase(r);
+    H.dirty = true;
+  }
+  if (heavy && (len + kChunk - 1) / kChunk > H.maxc) H.dirty = true;
+}
+
+void heavy_free(HeavySet& H) {
+  (void)hipFree(H.d_rows);
+  (void)hipFree(H.d_partial);
+  (void)hipFree(H.d_counter);
+  H.d_rows = nullptr;
+  H.d_partial = nullptr;
+  H.d_counter = nullptr;
+  H.cap_rows = H.cap_slots = 0;
+}
+
+// Uploads the heavy list when it changed. Counters are zero between launches, so they can be
+// reallocated (and zeroed) whenever the list grows.
+sr_status heavy_sync(sr_ctx* ctx, HeavySet& H, const SlotList& L) {
+  if (!H.dirty) return SR_OK;
+  HC(hipStreamSynchronize(ctx->stream));
+  H.list.assign(H.rows.begin(), H.rows.end());
+  int32_t maxc = 1;
+  for (int32_t r : H.list) maxc = std::max<int32_t>(maxc, (L.len[r] + kChunk - 1) / kChunk + 1);
+  H.maxc = maxc;
+  const int64_t nh = (int64_t)H.list.size();
+  if (nh > H.cap_rows) {
+    (void)hipFree(H.d_rows);
+    (void)hipFree(H.d_counter);
+    H.d_rows = nullptr;
+    H.d_counter = nullptr;
+    const int64_t cap = std::max<int64_t>(64, 2 * nh);
+    if (dalloc(&H.d_rows, cap) != hipSuccess || dalloc(&H.d_counter, cap) != hipSuccess)
+      return SR_ENOMEM;
+    HC(hipMemset(H.d_counter, 0, (size_t)cap * 4));
+    H.cap_rows = cap;
+  }
+  if (nh * maxc > H.cap_slots) {
+    (void)hipFree(H.d_partial);
+    H.d_partial = nullptr;
+    const int64_t cap = std::max<int64_t>(256, 2 * nh * maxc);
+    if (dalloc(&H.d_partial, 2 * cap) != hipSuccess) return SR_ENOMEM;
+    H.cap_slots = cap;
+  }
+  if (nh) HC(hipMemcpy(H.d_rows, H.list.data(), (size_t)nh * 4, hipMemcpyHostToDevice));
+  H.dirty = false;
+  return SR_OK;
+}
+
+HeavyArgs heavy_args(const HeavySet& H) {
+  HeavyArgs h;
+  h.rows = H.d_rows;
+  h.nh = (int32_t)H.list.size();
+  h.maxc = H.maxc;
+  h.partial = H.d_partial;
+  h.counter = H.d_counter;
+  return h;
+}
+
+sr_status heavy_refresh(sr_ctx* ctx) {
+  sr_status r = heavy_sync(ctx, ctx->hin, ctx->g.in);
+  if (r == SR_OK) r = heavy_sync(ctx, ctx->hout, ctx->g.out);
+  return r;
+}
+
+sr_status upload_graph(sr_ctx* ctx) {
+  const int64_t nc = ctx->node_cap;
+  const SlotList* L[2] = {&ctx->g.in, &ctx->g.out};
+  HC(hipStreamSynchronize(ctx->stream));
+  for (int l = 0; l < 2; ++l) {
+    HC(hipMemcpy(ctx->d_adj[3 * l + 0], L[l]->start.data(), nc * 4, hipMemcpyHostToDevice));
+    HC(hipMemcpy(ctx->d_adj[3 * l + 1], L[l]->len.data(), nc * 4, hipMemcpyHostToDevice));
+    HC(hipMemcpy(ctx->d_adj[3 * l + 2], L[l]->idx.data(), L[l]->idx.size() * 4,
+                 hipMemcpyHostToDevice));
+  }
+  if (ctx->weighted) {
+    HC(hipMemcpy(ctx->d_in_w, ctx->g.in.w.data(), ctx->g.in.w.size() * 8,
+                 hipMemcpyHostToDevice));
+    HC(hipMemcpy(ctx->d_out_w, ctx->g.out.w.data(), ctx->g.out.w.size() * 8,
+                 hipMemcpyHostToDevice));
+  }
+  return SR_OK;
+}
+
+// Applies edge insertions (op > 0) or deletions to the host mirror and the device copy.
+// The caller has validated every edge.
+sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>& e, int op) {
+  std::vector<Write> wi, wo;
+  std::vector<int32_t> mi, mo;
+  bool full = false, cap_err = false;
+  for (auto& ij : e) {
+    const int32_t i = ij.first, j = ij.second;
+    if (op > 0) {
+      const int r1 = ctx->g.in.insert(j, i, 1.0, wi, mi);
+      const int r2 = ctx->g.out.insert(i, j, 1.0, wo, mo);
+      full |= (r1 >= 2) || (r2 >= 2);
+      cap_err |= (r1 == 3) || (r2 == 3);
+      ctx->g.edges.insert(HostGraph::key(i, j));
+      ctx->g.m++;
+    } else {
+      ctx->g.in.remove(j, i, wi);
+      ctx->g.out.remove(i, j, wo);
+      ctx->g.edges.erase(HostGraph::key(i, j));
+      ctx->g.m--;
+    }
+    heavy_touch(ctx->hin, ctx->g.in, j);
+    heavy_touch(ctx->hout, ctx->g.out, i);
+  }
+  ctx->updated = true;
+  {
+    sr_status hs = heavy_refresh(ctx);
+    if (hs != SR_OK) return hs;
+  }
+  if (full) {
+    sr_status st = upload_graph(ctx);
+    if (st != SR_OK) return st;
+    return cap_err ? SR_ECAPACITY : SR_OK;
+  }
+  // Moved rows: upload their slots; then patch every touched (array, index) with the mirror's
+  // final value (unique addresses per launch, so the writes of one launch commute).
+  const SlotList* L[2] = {&ctx->g.in, &ctx->g.out};
+  std::vector<int32_t>* M[2] = {&mi, &mo};
+  std::vector<Write>* Wv[2] = {&wi, &wo};
+  bool synced = false;
+  for (int l = 0; l < 2; ++l) {
+    for (int32_t r : *M[l]) {
+      if (!synced) {
+        HC(hipStreamSynchronize(ctx->stream));
+        synced = true;
+      }
+      const int32_t st = L[l]->start[r], ln = L[l]->len[r];
+      HC(hipMemcpy(ctx->d_adj[3 * l + 2] + st, L[l]->idx.data() + st, (size_t)ln * 4,
+                   hipMemcpyHostToDevice));
+      Wv[l]->push_back({0, r, 0});
+      Wv[l]->push_back({1, r, 0});
+    }
+  }
+  std::set<std::pair<int32_t, int32_t>> touched;
+  for (int l = 0; l < 2; ++l)
+    for (auto& w : *Wv[l]) touched.insert({3 * l + w.array, w.index});
+  Patch p;
+  p.count = 0;
+  for (auto& t : touched) {
+    const int l = t.first / 3, a = t.first % 3;
+    const std::vector<int32_t>& src =
+        a == 0 ? L[l]->start : (a == 1 ? L[l]->len : L[l]->idx);
+    p.array[p.count] = t.first;
+    p.index[p.count] = t.second;
+    p.value[p.count] = src[t.second];
+    if (++p.count == Patch::MAX) {
+      HC(launch_patch(adjptrs(ctx), p, ctx->stream));
+      p.count = 0;
+    }
+  }
+  if (p.count) HC(launch_patch(adjptrs(ctx), p, ctx->stream));
+  return SR_OK;
+}
+
+// Launches the S update, bracketed by events when profiling is on.
+hipError_t run_lowrank(sr_ctx* ctx, const LowRankArgs& la) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profiling) {
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_lowrank(la, ctx->stream);
+  if (e == hipSuccess && ctx->profiling) {
+    e = hipEventRecord(e1, ctx->stream);
+    ctx->prof_events.push_back({e0, e1});
+  }
+  return e;
+}
+
+IdList idlist(const std::vector<int32_t>& v, size_t off, size_t cnt) {
+  IdList l;
+  l.count = (int32_t)cnt;
+  for (size_t t = 0; t < cnt; ++t) l.id[t] = v[off + t];
+  return l;
+}
+
+AffArgs aff_args(const sr_ctx* c, int64_t n) {
+  AffArgs a;
+  a.n = n;
+  a.W = c->W;
+  a.K = c->cfg.K;
+  a.A = c->Abits;
+  a.B = c->Bbits;
+  return a;
+}
+
+// Deferred application inside a fused batch: the block writes its (xi_k, eta_k) pairs into
+// panel columns [r_prev, r_prev + pld) of P (leading dimension pld_all), and S_t columns are
+// corrected by the r_prev deferred columns before gamma.
+struct FusedTarget {
+  double* P;
+  int pld_all;
+  int r_prev;
+};
+
+// One low-rank block (Table 2 rows C0 insert/delete, or C2): gamma from the old S and graph,
+// affected areas, graph edit, K series steps on the new graph, and the S update.
+//   case_id 0: sources I exist; case_id 2: sources I are new nodes (isolated until now).
+//   n_work: node count the kernels cover (includes new and not yet created nodes).
+sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int32_t>& I,
+                        int32_t j, int64_t n_work, sr_update_stats* st,
+                        const FusedTarget* ft = nullptr) {
+  const double C = ctx->cfg.C;
+  const int K = ctx->cfg.K;
+  const int delta = (int)I.size();
+  const int64_t dj = ctx->g.in.len[j];
+  const bool prune = ctx->cfg.prune != 0 && ft == nullptr;
+  double* P = ft ? ft->P + ft->r_prev : ctx->P;
+  const int pld = ft ? ft->pld_all : ctx->pld;
+  const bool direct = (case_id == 0) && ctx->cfg.gamma_form == SR_GAMMA_DIRECT;
+  hipStream_t s = ctx->stream;
+  const DevQ q = devq(ctx);
+
+  GammaArgs ga{};
+  ga.kind = case_id == 2 ? 2 : (direct ? 1 : 0);
+  ga.op = op;
+  ga.j = j;
+  ga.delta = delta;
+  ga.dj = dj;
+  ga.C = C;
+  ga.xi0 = case_id == 2 ? C * (double)delta / (double)(dj + delta) : C;
+  ga.I = idlist(I, 0, case_id == 0 ? I.size() : 0);
+
+  // S[:, I] (with supports) and S[:, j] from the old S.
+  const IdList src_rows = idlist(I, 0, case_id == 0 ? I.size() : 0);
+  HC(launch_gather_rows(ctx->S, n_work, src_rows, 0, j, ctx->SI, ctx->Sj, ctx->suppI,
+                        ctx->suppJ, s));
+  if (ft && ft->r_prev > 0)
+    HC(launch_panel_correct(ft->P, ft->pld_all, ft->r_prev, n_work, src_rows, j, ctx->wts,
+                            ctx->SI, ctx->Sj, s));
+  const AffArgs aa = aff_args(ctx, n_work);
+  const int64_t W = ctx->W;
+  uint32_t* A = ctx->Abits;
+  uint32_t* B = ctx->Bbits;
+  if (prune) {
+    HC(hipMemsetAsync(A, 0, (size_t)(K + 1) * W * 4, s));
+    HC(hipMemsetAsync(B, 0, (size_t)(K + 1) * W * 4, s));
+  }
+  const HeavyArgs hin = heavy_args(ctx->hin);
+  if (case_id == 0) {
+    // Q_old S[:, I]; in the same traversal F1 = out_old(supp S[I, :]) goes into B_0.
+    HC(launch_spmv_q(q, hin, n_work, ctx->SI, ctx->QSI, 1.0, s, nullptr, 1.0,
+                     prune ? ctx->suppI : nullptr, prune ? B : nullptr));
+    if (direct) {
+      if (dj > 0) HC(launch_gather_inrows(ctx->S, n_work, q, j, ctx->zsum, s));
+      HC(launch_direct_z(ga, n_work, ctx->SI, ctx->zsum, ctx->zbuf, s));
+      HC(launch_spmv_q(q, hin, n_work, ctx->zbuf, ctx->Qz, 1.0, s));
+    }
+  }
+  if (st) HC(hipMemsetAsync(ctx->d_max, 0, sizeof(unsigned long long), s));
+  HC(launch_gamma(ga, n_work, ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, P, pld,
+                  st ? ctx->d_max : nullptr, s));
+  if (prune) {
+    // F2 = supp S[j, :] unless row j of Q is empty before an insertion / after a deletion
+    // (case C2: B_0 = supp S[j, :] | {j}).
+    const int f2 = case_id == 2 ? 1 : (op > 0 ? (dj > 0) : (dj > delta));
+    HC(launch_aff_level0(aa, ctx->suppJ, f2, j, s));
+  }
+
+  // Graph edit.
+  std::vector<std::pair<int32_t, int32_t>> edges;
+  for (int32_t i : I) edges.push_back({i, j});
+  sr_status es = edit_graph(ctx, edges, op);
+  if (es != SR_OK) return es;
+  const DevQ q_new = devq(ctx);
+  const HeavyArgs hin_new = heavy_args(ctx->hin);
+
+  // K steps of eq (16a) on the new graph; level k+1 of the affected areas in the same pass:
+  // A_{k+1} = out_new(A_0 | A_k), B_{k+1} = out_new(B_0 | B_k).
+  for (int k = 0; k < K; ++k) {
+    AffLevel al;
+    al.a0 = A;
+    al.a1 = k >= 1 ? A + (int64_t)k * W : nullptr;
+    al.aout = A + (int64_t)(k + 1) * W;
+    al.b0 = B;
+    al.b1 = k >= 1 ? B + (int64_t)k * W : nullptr;
+    al.bout = B + (int64_t)(k + 1) * W;
+    HC(launch_series_step(q_new, hin_new, n_work, P, pld, k, C, 1.0, prune ? &al : nullptr,
+                          s));
+  }
+  if (ft) return SR_OK;  // applied later by the batch's fused pass
+  if (prune) HC(launch_aff_compact(aa, ctx->Ahat, ctx->Bhat, ctx->rowlist, ctx->d_cnt, s));
+
+  LowRankArgs la{};
+  la.S = ctx->S;
+  la.P = ctx->P;
+  la.pld = ctx->pld;
+  la.r = 2 * (K + 1);
+  la.ncols = n_work;
+  if (prune) {
+    la.rows = ctx->rowlist;
+    la.nrows_dev = ctx->d_cnt + 3;
+    la.nrows = n_work;
+    la.Ahat = ctx->Ahat;
+    la.Bhat = ctx->Bhat;
+  } else {
+    la.rows = nullptr;
+    la.nrows = n_work;
+  }
+  HC(run_lowrank(ctx, la));
+  ctx->last_r = 2 * (K + 1);
+  ctx->last_aff = prune;
+
+  if (st) {
+    if (prune) HC(hipMemcpyAsync(ctx->h_cnt, ctx->d_cnt, 4 * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, s));
+    HC(hipMemcpyAsync(ctx->h_max, ctx->d_max, sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    double gmax;
+    memcpy(&gmax, ctx->h_max, sizeof(double));
+    st->case_id = case_id;
+    st->op = op;
+    st->d_j = dj;
+    if (prune) {
+      st->aff_A = ctx->h_cnt[0];
+      st->aff_B = ctx->h_cnt[1];
+      st->aff_AB = ctx->h_cnt[2];
+      st->pairs = 2 * ctx->h_cnt[0] * ctx->h_cnt[1] - ctx->h_cnt[2] * ctx->h_cnt[2];
+    } else {
+      st->aff_A = st->aff_B = st->aff_AB = n_work;
+      st->pairs = n_work * n_work;
+    }
+    st->bound = 2.0 * ga.xi0 * pow(C, K + 1) / (1.0 - C) * gmax;
+  }
+  return SR_OK;
+}
+
+// C1 block (Theorem 8, Table 2 row C1): existing sources I, new sink j.
+sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_t n_work,
+                   const FusedTarget* ft = nullptr) {
+  hipStream_t s = ctx->stream;
+  const double C = ctx->cfg.C;
+  const IdList il = idlist(I, 0, I.size());
+  HC(launch_gather_rows(ctx->S, n_work, il, 0, -1, ctx->SI, nullptr, ctx->suppI, nullptr, s));
+  if (ft && ft->r_prev > 0)
+    HC(launch_panel_correct(ft->P, ft->pld_all, ft->r_prev, n_work, il, -1, ctx->wts, ctx->SI,
+                            nullptr, s));
+  HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n_work, ctx->SI, ctx->ytmp,
+                   C / (double)I.size(), s));
+  HC(launch_c1_border(ctx->S, n_work, j, ctx->ytmp, ctx->SI, il, C, s));
+  std::vector<std::pair<int32_t, int32_t>> e;
+  for (int32_t i : I) e.push_back({i, j});
+  return edit_graph(ctx, e, +1);
+}
+
+sr_status set_diags(sr_ctx* ctx, const std::vector<std::pair<int32_t, double>>& d) {
+  DiagList dl;
+  dl.count = 0;
+  for (auto& x : d) {
+    dl.id[dl.count] = x.first;
+    dl.val[dl.count] = x.second;
+    if (++dl.count == DiagList::MAX) {
+      HC(launch_set_diag(ctx->S, dl, ctx->stream));
+      dl.count = 0;
+    }
+  }
+  if (dl.count) HC(launch_set_diag(ctx->S, dl, ctx->stream));
+  return SR_OK;
+}
+
+// C3 block (Algorithm 5, Table 2 row C3): new sources I and new sink j.
+sr_status c3_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j) {
+  const double C = ctx->cfg.C;
+  std::vector<std::pair<int32_t, double>> d;
+  for (int32_t i : I) d.push_back({i, 1.0 - C});
+  d.push_back({j, (1.0 - C) * (1.0 + C / (double)I.size())});
+  sr_status r = set_diags(ctx, d);
+  if (r != SR_OK) return r;
+  std::vector<std::pair<int32_t, int32_t>> e;
+  for (int32_t i : I) e.push_back({i, j});
+  return edit_graph(ctx, e, +1);
+}
+
+// PartialSim (section 7): column q of the K_ps-term SimRank into out (n values).
+// x_0 = e_q, x_t = Q^T x_{t-1} (t = 1..K); y = x_K, y <- x_{K-t} + C Q y (t = 1..K); (1 - C) y.
+sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
+  const int64_t n = ctx->g.n;
+  const int Kp = ctx->cfg.K_ps > 0 ? ctx->cfg.K_ps : ctx->cfg.K;
+  const double C = ctx->cfg.C;
+  hipStream_t s = ctx->stream;
+  const DevQ dq = devq(ctx);
+  const DevAdj out_l = devout(ctx);
+  auto x = [&](int t) { return ctx->xs + (int64_t)t * ctx->node_cap; };
+  HC(launch_unit_vector(x(0), n, q, s));
+  const HeavyArgs hin = heavy_args(ctx->hin), hout = heavy_args(ctx->hout);
+  for (int t = 1; t <= Kp; ++t)
+    HC(launch_spmv_qt(dq, out_l, hout, n, x(t - 1), x(t), 1.0, s));
+  const double* y = x(Kp);
+  for (int t = 1; t <= Kp; ++t) {
+    double* dst = (t == Kp) ? out : ((t & 1) ? ctx->ytmp : ctx->zbuf);
+    HC(launch_spmv_q(dq, hin, n, y, dst, C, s, x(Kp - t), t == Kp ? (1.0 - C) : 1.0));
+    y = dst;
+  }
+  if (Kp == 0) HC(hipMemcpyAsync(out, x(0), (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  return SR_OK;
+}
+
+bool valid_ctx(sr_ctx* c) { return c != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+const char* sr_strerror(sr_status s) {
+  switch (s) {
+    case SR_OK: return "ok";
+    case SR_EINVAL: return "invalid argument";
+    case SR_ERANGE: return "node id out of range or new node ids not dense";
+    case SR_EEXIST: return "edge exists";
+    case SR_ENOENT: return "edge does not exist";
+    case SR_ESELF: return "self-loop";
+    case SR_ECAPACITY: return "capacity exceeded";
+    case SR_ENOMEM: return "out of memory";
+    case SR_EMODE: return "not available in this mode";
+    case SR_EHIP: return "HIP runtime error (context poisoned)";
+  }
+  return "unknown status";
+}
+
+sr_status sr_default_config(sr_config* cfg) {
+  if (!cfg) return SR_EINVAL;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->C = 0.6;
+  cfg->K = 15;
+  cfg->K_ps = 30;
+  cfg->s_prec = SR_S_FP64;
+  cfg->mode = SR_DENSE;
+  cfg->gamma_form = SR_GAMMA_CLOSED;
+  cfg->prune = 1;
+  cfg->node_cap = 0;
+  cfg->edge_cap = 0;
+  cfg->init_tol = 1e-15;
+  cfg->init_max_iter = 400;
+  cfg->batch_chunk = 64;
+  cfg->fused_batch = 1;
+  return SR_OK;
+}
+
+sr_status sr_destroy(sr_ctx* ctx) {
+  if (!ctx) return SR_OK;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& ev : ctx->prof_events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  for (int k = 0; k < 6; ++k) (void)hipFree(ctx->d_adj[k]);
+  (void)hipFree(ctx->d_in_w);
+  (void)hipFree(ctx->d_out_w);
+  (void)hipFree(ctx->d_W);
+  (void)hipFree(ctx->S_mem[0]);
+  (void)hipFree(ctx->S_mem[1]);
+  double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp,
+                  ctx->P, ctx->Pb, ctx->wts, ctx->xs};
+  for (double* p : dd) (void)hipFree(p);
+  uint32_t* bb[] = {ctx->suppI, ctx->suppJ, ctx->Abits, ctx->Bbits, ctx->Ahat, ctx->Bhat};
+  for (uint32_t* p : bb) (void)hipFree(p);
+  (void)hipFree(ctx->rowlist);
+  (void)hipFree(ctx->d_ids);
+  heavy_free(ctx->hin);
+  heavy_free(ctx->hout);
+  (void)hipFree(ctx->d_cnt);
+  (void)hipFree(ctx->d_max);
+  (void)hipHostFree(ctx->h_cnt);
+  (void)hipHostFree(ctx->h_max);
+  delete ctx;
+  return SR_OK;
+}
+
+sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                       const int32_t* dst, const double* weight, const sr_config* cfg_in,
+                       const void* S0, void* hip_stream) {
+  if (!out || n <= 0 || m < 0 || (m > 0 && (!src || !dst))) return SR_EINVAL;
+  *out = nullptr;
+  sr_config cfg;
+  if (cfg_in) {
+    cfg = *cfg_in;
+  } else {
+    sr_default_config(&cfg);
+  }
+  if (!(cfg.C > 0.0 && cfg.C < 1.0) || cfg.K < 0 || cfg.K > 200 || cfg.K_ps < 0 ||
+      cfg.s_prec < 0 || cfg.s_prec > 2 || (cfg.mode != SR_DENSE && cfg.mode != SR_COLUMN) ||
+      cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0)
+    return SR_EINVAL;
+  if (cfg.batch_chunk == 0) cfg.batch_chunk = 64;
+  if (cfg.init_max_iter <= 0) cfg.init_max_iter = 400;
+  if (cfg.mode == SR_COLUMN && S0) return SR_EINVAL;
+  const int64_t node_cap = cfg.node_cap > 0 ? cfg.node_cap : n;
+  const int64_t edge_cap = cfg.edge_cap > 0 ? cfg.edge_cap : 2 * m + 1024;
+  if (node_cap < n || edge_cap < m || node_cap > ((int64_t)1 << 31) - 64) return SR_ECAPACITY;
+  for (int64_t e = 0; e < m; ++e) {
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return SR_ERANGE;
+    if (src[e] == dst[e]) return SR_ESELF;
+  }
+
+  sr_ctx* ctx = new (std::nothrow) sr_ctx();
+  if (!ctx) return SR_ENOMEM;
+  ctx->cfg = cfg;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->node_cap = node_cap;
+  ctx->edge_cap = edge_cap;
+  ctx->weighted = weight != nullptr;
+  ctx->g.n = n;
+  ctx->g.m = m;
+  ctx->src0.assign(src, src + m);
+  ctx->dst0.assign(dst, dst + m);
+  if (weight) ctx->w0.assign(weight, weight + m);
+  for (int64_t e = 0; e < m; ++e) {
+    auto ins = ctx->g.edges.insert(HostGraph::key(src[e], dst[e]));
+    if (!ins.second) {
+      delete ctx;
+      return SR_EEXIST;
+    }
+  }
+  // Slot arrays: a repack of any graph within the capacities fits with room to spare.
+  ctx->slot_cap = edge_cap + edge_cap / 4 + 8 * node_cap + edge_cap / 2 + 4096;
+  ctx->g.in.build(node_cap, ctx->slot_cap, ctx->dst0, ctx->src0, weight);
+  ctx->g.out.build(node_cap, ctx->slot_cap, ctx->src0, ctx->dst0, weight);
+  {
+    // in-list slot -> initial edge index (build() placed each row's edges in input order)
+    ctx->slot_edge0.assign(ctx->g.in.idx.size(), -1);
+    std::vector<int32_t> fill(node_cap, 0);
+    for (int64_t e = 0; e < m; ++e) {
+      const int32_t r = dst[e];
+      ctx->slot_edge0[ctx->g.in.start[r] + fill[r]++] = (int32_t)e;
+    }
+  }
+
+  sr_status st = SR_OK;
+#define IC(expr)                      \
+  do {                                \
+    if ((expr) != hipSuccess) {       \
+      sr_destroy(ctx);                \
+      return SR_ENOMEM;               \
+    }                                 \
+  } while (0)
+  const int64_t slots = (int64_t)ctx->g.in.idx.size();
+  IC(dalloc(&ctx->d_adj[0], node_cap));
+  IC(dalloc(&ctx->d_adj[1], node_cap));
+  IC(dalloc(&ctx->d_adj[2], slots));
+  IC(dalloc(&ctx->d_adj[3], node_cap));
+  IC(dalloc(&ctx->d_adj[4], node_cap));
+  IC(dalloc(&ctx->d_adj[5], (int64_t)ctx->g.out.idx.size()));
+  if (weight) {
+    IC(dalloc(&ctx->d_in_w, slots));
+    IC(dalloc(&ctx->d_out_w, (int64_t)ctx->g.out.idx.size()));
+    IC(dalloc(&ctx->d_W, node_cap));
+    std::vector<double> Wsum(node_cap, 0.0);
+    for (int64_t e = 0; e < m; ++e) Wsum[dst[e]] += weight[e];
+    if (hipMemcpy(ctx->d_W, Wsum.data(), node_cap * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      sr_destroy(ctx);
+      return SR_EHIP;
+    }
+  }
+  // one block's panel: 32 columns when it fits (the streaming kernel reads 8 per lane group)
+  ctx->pld = 2 * (cfg.K + 1) <= 32 ? 32 : round4(2 * (cfg.K + 1));
+  ctx->W = (int)((node_cap + 31) / 32 + 64);
+  IC(dalloc(&ctx->SI, node_cap));
+  IC(dalloc(&ctx->Sj, node_cap));
+  IC(dalloc(&ctx->QSI, node_cap));
+  IC(dalloc(&ctx->zbuf, node_cap));
+  IC(dalloc(&ctx->Qz, node_cap));
+  IC(dalloc(&ctx->zsum, node_cap));
+  IC(dalloc(&ctx->ytmp, node_cap));
+  IC(dalloc(&ctx->P, node_cap * ctx->pld));
+  IC(dalloc(&ctx->suppI, ctx->W));
+  IC(dalloc(&ctx->suppJ, ctx->W));
+  IC(dalloc(&ctx->Abits, (int64_t)(cfg.K + 1) * ctx->W));
+  IC(dalloc(&ctx->Bbits, (int64_t)(cfg.K + 1) * ctx->W));
+  IC(dalloc(&ctx->Ahat, ctx->W));
+  IC(dalloc(&ctx->Bhat, ctx->W));
+  IC(dalloc(&ctx->rowlist, node_cap));
+  IC(dalloc(&ctx->d_cnt, 8));
+  IC(dalloc(&ctx->d_max, 1));
+  IC(hipHostMalloc((void**)&ctx->h_cnt, 8 * sizeof(int64_t), hipHostMallocDefault));
+  IC(hipHostMalloc((void**)&ctx->h_max, sizeof(unsigned long long), hipHostMallocDefault));
+  if (hipMemset(ctx->P, 0, (size_t)node_cap * ctx->pld * 8) != hipSuccess ||
+      hipMemset(ctx->Ahat, 0, (size_t)ctx->W * 4) != hipSuccess ||
+      hipMemset(ctx->Bhat, 0, (size_t)ctx->W * 4) != hipSuccess ||
+      hipMemset(ctx->Abits, 0, (size_t)(cfg.K + 1) * ctx->W * 4) != hipSuccess ||
+      hipMemset(ctx->Bbits, 0, (size_t)(cfg.K + 1) * ctx->W * 4) != hipSuccess ||
+      hipMemset(ctx->suppI, 0, (size_t)ctx->W * 4) != hipSuccess ||
+      hipMemset(ctx->suppJ, 0, (size_t)ctx->W * 4) != hipSuccess) {
+    sr_destroy(ctx);
+    return SR_EHIP;
+  }
+  st = upload_graph(ctx);
+  for (int64_t r = 0; r < node_cap && st == SR_OK; ++r) {
+    if (ctx->g.in.len[r] > kLight) ctx->hin.rows.insert((int32_t)r);
+    if (ctx->g.out.len[r] > kLight) ctx->hout.rows.insert((int32_t)r);
+  }
+  if (st == SR_OK) st = heavy_refresh(ctx);
+  if (st != SR_OK) {
+    sr_destroy(ctx);
+    return st;
+  }
+
+  if (cfg.mode == SR_COLUMN) {
+    const int Kp = cfg.K_ps > 0 ? cfg.K_ps : cfg.K;
+    IC(dalloc(&ctx->xs, (int64_t)(Kp + 1) * node_cap));
+    *out = ctx;
+    return SR_OK;
+  }
+
+  // Dense S with leading dimension node_cap rounded to 64; rows/cols past n stay zero.
+  const int64_t ld = (node_cap + 63) / 64 * 64;
+  ctx->S.prec = cfg.s_prec;
+  ctx->S.ld = ld;
+  const size_t cells = (size_t)node_cap * (size_t)ld;
+  if (cfg.s_prec == SR_S_FP64) {
+    IC(hipMalloc(&ctx->S_mem[0], cells * 8));
+    ctx->S.d = (double*)ctx->S_mem[0];
+    IC(hipMemset(ctx->S_mem[0], 0, cells * 8));
+  } else {
+    IC(hipMalloc(&ctx->S_mem[0], cells * 4));
+    ctx->S.hi = (float*)ctx->S_mem[0];
+    IC(hipMemset(ctx->S_mem[0], 0, cells * 4));
+    if (cfg.s_prec == SR_S_FP32_HILO) {
+      IC(hipMalloc(&ctx->S_mem[1], cells * 4));
+      ctx->S.lo = (float*)ctx->S_mem[1];
+      IC(hipMemset(ctx->S_mem[1], 0, cells * 4));
+    }
+  }
+
+  // Initial S: copy S0, or iterate S <- C Q S Q^T + (1 - C) I in float64 (eq (03a)):
+  //   T = Q S (row gather), U = T^T, S' = C Q U + (1 - C) I; S symmetric so U = S Q^T.
+  const int64_t ldi = (n + 63) / 64 * 64;
+  double *A = nullptr, *B = nullptr, *T = nullptr;
+  IC(dalloc(&A, n * ldi));
+  if (S0) {
+    // S0 has leading dimension n; re-pitch into ldi
+    if (hipMemcpy2D(A, ldi * 8, S0, n * 8, n * 8, n, hipMemcpyDeviceToDevice) != hipSuccess) {
+      (void)hipFree(A);
+      sr_destroy(ctx);
+      return SR_EHIP;
+    }
+  } else {
+    IC(dalloc(&B, n * ldi));
+    IC(dalloc(&T, n * ldi));
+    hipError_t e = hipMemsetAsync(A, 0, (size_t)n * ldi * 8, ctx->stream);
+    if (e == hipSuccess) e = launch_fill_diag(A, n, ldi, 1.0 - cfg.C, ctx->stream);
+    for (int it = 0; it < cfg.init_max_iter && e == hipSuccess; ++it) {
+      e = hipMemsetAsync(ctx->d_max, 0, 8, ctx->stream);
+      if (e == hipSuccess) e = launch_spmm_rows(devq(ctx), n, A, T, 1.0, 0.0, nullptr, nullptr,
+                                                ctx->stream);
+      if (e == hipSuccess) e = launch_transpose(n, T, B, ctx->stream);
+      if (e == hipSuccess) e = launch_spmm_rows(devq(ctx), n, B, T, cfg.C, 1.0 - cfg.C, A,
+                                                ctx->d_max, ctx->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost,
+                                              ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      std::swap(A, T);
+      double step;
+      memcpy(&step, ctx->h_max, 8);
+      if (step <= cfg.init_tol) break;
+    }
+    if (e != hipSuccess) {
+      (void)hipFree(A);
+      (void)hipFree(B);
+      (void)hipFree(T);
+      sr_destroy(ctx);
+      return SR_EHIP;
+    }
+  }
+  hipError_t e = launch_to_store(ctx->S, n, A, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(A);
+  (void)hipFree(B);
+  (void)hipFree(T);
+  if (e != hipSuccess) {
+    sr_destroy(ctx);
+    return SR_EHIP;
+  }
+  ctx->updated = false;
+  *out = ctx;
+  return SR_OK;
+#undef IC
+}
+
+sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
+                            sr_update_stats* stats) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (op != 1 && op != -1) return SR_EINVAL;
+  if (ctx->weighted) return SR_EMODE;
+  const int64_t n = ctx->g.n;
+  if (i < 0 || j < 0) return SR_ERANGE;
+  if (i == j) return SR_ESELF;
+  int case_id;
+  if (i < n && j < n) {
+    case_id = 0;
+  } else if (i < n && j == n) {
+    case_id = 1;
+  } else if (i == n && j < n) {
+    case_id = 2;
+  } else if (i == n && j == n + 1) {
+    case_id = 3;
+  } else {
+    return SR_ERANGE;
+  }
+  if (op < 0 && case_id != 0) return SR_ENOENT;
+  if (case_id == 0) {
+    const bool has = ctx->g.has(i, j);
+    if (op > 0 && has) return SR_EEXIST;
+    if (op < 0 && !has) return SR_ENOENT;
+  }
+  const int64_t n_new = n + (case_id == 3 ? 2 : (case_id == 0 ? 0 : 1));
+  if (n_new > ctx->node_cap) return SR_ECAPACITY;
+  if (op > 0 && ctx->g.m + 1 > ctx->edge_cap) return SR_ECAPACITY;
+
+  if (ctx->cfg.mode == SR_COLUMN) {
+    if (case_id != 0 || op < 0) return SR_EMODE;
+    // Algorithm 7, case C0: old columns by PartialSim, gamma, series on the new graph.
+    sr_status r = partial_sim(ctx, i, ctx->SI);
+    if (r != SR_OK) return r;
+    r = partial_sim(ctx, j, ctx->Sj);
+    if (r != SR_OK) return r;
+    hipStream_t s = ctx->stream;
+    const double C = ctx->cfg.C;
+    HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->QSI, 1.0, s));
+    GammaArgs ga{};
+    ga.kind = 0;
+    ga.op = 1;
+    ga.j = j;
+    ga.delta = 1;
+    ga.dj = ctx->g.in.len[j];
+    ga.C = C;
+    ga.xi0 = C;
+    ga.I.count = 1;
+    ga.I.id[0] = i;
+    if (stats) HC(hipMemsetAsync(ctx->d_max, 0, 8, s));
+    HC(launch_gamma(ga, n, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, ctx->P, ctx->pld,
+                    stats ? ctx->d_max : nullptr, s));
+    r = edit_graph(ctx, {{i, j}}, +1);
+    if (r != SR_OK) return r;
+    for (int k = 0; k < ctx->cfg.K; ++k)
+      HC(launch_series_step(devq(ctx), heavy_args(ctx->hin), n, ctx->P, ctx->pld, k, C, 1.0,
+                            nullptr, s));
+    ctx->last_r = 2 * (ctx->cfg.K + 1);
+    if (stats) {
+      HC(hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost, s));
+      HC(hipStreamSynchronize(s));
+      double gmax;
+      memcpy(&gmax, ctx->h_max, 8);
+      memset(stats, 0, sizeof(*stats));
+      stats->case_id = 0;
+      stats->op = 1;
+      stats->d_j = ga.dj;
+      stats->n_after = n;
+      stats->bound = 2.0 * pow(C, ctx->cfg.K + 2) / (1.0 - C) * gmax;
+    }
+    return SR_OK;
+  }
+
+  if (stats) memset(stats, 0, sizeof(*stats));
+  sr_status r = SR_OK;
+  const double C = ctx->cfg.C;
+  if (case_id == 0) {
+    r = lowrank_block(ctx, 0, op, {i}, j, n, stats);
+  } else if (case_id == 1) {
+    ctx->g.n = n_new;
+    r = c1_block(ctx, {i}, j, n);
+    ctx->last_r = 0;
+  } else if (case_id == 2) {
+    ctx->g.n = n_new;
+    r = set_diags(ctx, {{i, 1.0 - C}});
+    if (r == SR_OK) r = lowrank_block(ctx, 2, +1, {i}, j, n_new, stats);
+  } else {
+    ctx->g.n = n_new;
+    r = c3_block(ctx, {i}, j);
+    ctx->last_r = 0;
+  }
+  if (r != SR_OK) return r;
+  if (stats) {
+    stats->case_id = case_id;
+    stats->op = op;
+    stats->n_after = n_new;
+    if (case_id == 1 || case_id == 3) {
+      stats->d_j = 0;
+      stats->pairs = case_id == 1 ? 2 * n + 1 : 2;
+      HC(hipStreamSynchronize(ctx->stream));
+    }
+  }
+  return SR_OK;
+}
+
+// ------------------------------------------------------------------------------ batches
+
+}  // extern "C"
+
+namespace {
+
+struct Block {
+  int case_id;
+  int op;
+  int32_t j;
+  int64_t dj;
+  std::vector<int32_t> I;
+};
+
+// Algorithm 6 planning (section 8). Returns SR_OK and the blocks, or a validation status.
+sr_status plan_batch(const sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t* bj,
+                     const int8_t* bo, std::vector<Block>& plan, int64_t& n_new,
+                     int64_t& net_edges) {
+  const int64_t n = ctx->g.n;
+  std::map<std::pair<int32_t, int32_t>, int> net;  // (j, i) -> count, ordered by sink
+  for (int64_t e = 0; e < cnt; ++e) {
+    if (bo[e] != 1 && bo[e] != -1) return SR_EINVAL;
+    if (bi[e] < 0 || bj[e] < 0) return SR_ERANGE;
+    if (bi[e] == bj[e]) return SR_ESELF;
+    net[{bj[e], bi[e]}] += bo[e];
+  }
+  std::set<int32_t> newids;
+  std::vector<std::pair<int32_t, int32_t>> plus, minus;  // (j, i)
+  for (auto& kv : net) {
+    const int32_t j = kv.first.first, i = kv.first.second;
+    if (kv.second > 1) return SR_EEXIST;
+    if (kv.second < -1) return SR_ENOENT;
+    if (i >= n) newids.insert(i);
+    if (j >= n) newids.insert(j);
+  }
+  for (int64_t e = 0; e < cnt; ++e) {
+    if (bi[e] >= n) newids.insert(bi[e]);
+    if (bj[e] >= n) newids.insert(bj[e]);
+  }
+  n_new = n + (int64_t)newids.size();
+  if (!newids.empty() && (*newids.begin() != n || *newids.rbegin() != n_new - 1))
+    return SR_ERANGE;
+  if (n_new > ctx->node_cap) return SR_ECAPACITY;
+  int64_t ins = 0;
+  for (auto& kv : net) {
+    const int32_t j = kv.first.first, i = kv.first.second;
+    const bool old_edge = (i < n && j < n) && ctx->g.has(i, j);
+    if (kv.second == 1) {
+      if (old_edge) return SR_EEXIST;
+      plus.push_back({j, i});
+      ++ins;
+    } else if (kv.second == -1) {
+      if (!old_edge) return SR_ENOENT;
+      minus.push_back({j, i});
+    }
+  }
+  if (ctx->g.m + ins > ctx->edge_cap) return SR_ECAPACITY;
+  net_edges = (int64_t)(plus.size() + minus.size());
+
+  std::vector<int64_t> deg_change;  // tracked lazily through a map
+  std::map<int32_t, int64_t> dmod;
+  auto degree = [&](int32_t j) -> int64_t {
+    int64_t d = j < n ? ctx->g.in.len[j] : 0;
+    auto it = dmod.find(j);
+    return d + (it == dmod.end() ? 0 : it->second);
+  };
+  const size_t cap = IdList::MAX;
+  auto push_split = [&](int case_id, int op, int32_t j, std::vector<int32_t>& I) {
+    for (size_t off = 0; off < I.size(); off += cap) {
+      Block b;
+      b.case_id = case_id;
+      b.op = op;
+      b.j = j;
+      b.dj = degree(j);
+      b.I.assign(I.begin() + off, I.begin() + std::min(I.size(), off + cap));
+      dmod[j] += op * (int64_t)b.I.size();
+      plan.push_back(b);
+      // after the first chunk of a new-node block the sink / sources exist
+      if (case_id == 1) case_id = 0;
+      if (case_id == 3) case_id = 2;
+    }
+  };
+  // deletion blocks, sinks ascending
+  for (size_t a = 0; a < minus.size();) {
+    size_t b = a;
+    std::vector<int32_t> I;
+    while (b < minus.size() && minus[b].first == minus[a].first) I.push_back(minus[b++].second);
+    push_split(0, -1, minus[a].first, I);
+    a = b;
+  }
+  // insertion blocks, sinks ascending; split by source existence at processing time
+  std::set<int32_t> created;
+  auto exists = [&](int32_t v) { return v < n || created.count(v) != 0; };
+  for (size_t a = 0; a < plus.size();) {
+    size_t b = a;
+    const int32_t j = plus[a].first;
+    std::vector<int32_t> old_src, new_src;
+    while (b < plus.size() && plus[b].first == j) {
+      const int32_t i = plus[b++].second;
+      (exists(i) ? old_src : new_src).push_back(i);
+    }
+    if (!old_src.empty()) {
+      push_split(exists(j) ? 0 : 1, 1, j, old_src);
+      created.insert(j);
+    }
+    if (!new_src.empty()) {
+      push_split(exists(j) ? 2 : 3, 1, j, new_src);
+      created.insert(j);
+      for (int32_t i : new_src) created.insert(i);
+    }
+    a = b;
+  }
+  return SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t* bj,
+                      const int8_t* bo, sr_batch_stats* stats) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (cnt < 0 || (cnt > 0 && (!bi || !bj || !bo))) return SR_EINVAL;
+  if (ctx->cfg.mode != SR_DENSE || ctx->weighted) return SR_EMODE;
+  std::vector<Block> plan;
+  int64_t n_new = 0, net_edges = 0;
+  sr_status r = plan_batch(ctx, cnt, bi, bj, bo, plan, n_new, net_edges);
+  if (r != SR_OK) return r;
+  const int64_t n_old = ctx->g.n;
+  const double C = ctx->cfg.C;
+  // New nodes start as isolated nodes (SimRank 1 - C on the diagonal, 0 elsewhere); a block
+  // that creates one then writes its case's values.
+  HC(launch_diag_range(ctx->S, n_old, n_new, 1.0 - C, ctx->stream));
+  ctx->g.n = n_new;
+  int64_t pairs = 0, lowrank = 0, bc[4] = {0, 0, 0, 0};
+  // Fused form: low-rank blocks write their pairs side by side into Pb; every batch_chunk
+  // blocks (and at the end) one pass adds all of them to S (rank 2 (K+1) x blocks).
+  const bool fused = ctx->cfg.fused_batch != 0 && ctx->cfg.gamma_form == SR_GAMMA_CLOSED;
+  const int chunk = ctx->cfg.batch_chunk;
+  const int pld_all = ctx->pld * chunk;
+  if (fused && !ctx->Pb) {
+    if (dalloc(&ctx->Pb, ctx->node_cap * (int64_t)pld_all) != hipSuccess ||
+        dalloc(&ctx->wts, 2 * (int64_t)pld_all) != hipSuccess)
+      return SR_ENOMEM;
+  }
+  int q = 0;  // deferred blocks in the current chunk
+  int passes = 0;
+  auto flush = [&]() -> sr_status {
+    if (q == 0) return SR_OK;
+    LowRankArgs la{};
+    la.S = ctx->S;
+    la.P = ctx->Pb;
+    la.pld = pld_all;
+    la.r = q * ctx->pld;
+    la.rows = nullptr;
+    la.nrows = n_new;
+    la.ncols = n_new;
+    HC(run_lowrank(ctx, la));
+    ++passes;
+    q = 0;
+    return SR_OK;
+  };
+  ctx->last_plan.clear();
+  for (const Block& b : plan) {
+    bc[b.case_id]++;
+    ctx->last_plan.push_back(b.case_id);
+    ctx->last_plan.push_back(b.op);
+    ctx->last_plan.push_back(b.j);
+    ctx->last_plan.push_back((int32_t)b.dj);
+    ctx->last_plan.push_back((int32_t)b.I.size());
+    for (int32_t i : b.I) ctx->last_plan.push_back(i);
+    FusedTarget ft{ctx->Pb, pld_all, q * ctx->pld};
+    switch (b.case_id) {
+      case 0:
+      case 2:
+        r = lowrank_block(ctx, b.case_id, b.op, b.I, b.j, n_new, nullptr, fused ? &ft : nullptr);
+        ++lowrank;
+        pairs += n_new * n_new;
+        if (r == SR_OK && fused && ++q == chunk) r = flush();
+        break;
+      case 1:
+        r = c1_block(ctx, b.I, b.j, n_new, fused ? &ft : nullptr);
+        pairs += 2 * n_new + 1;
+        break;
+      default:
+        r = c3_block(ctx, b.I, b.j);
+        pairs += (int64_t)b.I.size() + 1;
+        break;
+    }
+    if (r != SR_OK) return r;
+  }
+  r = flush();
+  if (r != SR_OK) return r;
+  ctx->last_r = 0;
+  if (stats) {
+    HC(hipStreamSynchronize(ctx->stream));
+    memset(stats, 0, sizeof(*stats));
+    stats->edges_in = cnt;
+    stats->edges_net = net_edges;
+    stats->blocks = (int64_t)plan.size();
+    for (int c = 0; c < 4; ++c) stats->blocks_case[c] = bc[c];
+    stats->lowrank_blocks = lowrank;
+    stats->n_after = n_new;
+    stats->pairs = pairs;
+    stats->fused_passes = passes;
+  }
+  return SR_OK;
+}
+
+sr_status sr_last_plan(sr_ctx* ctx, int32_t* out, int64_t cap, int64_t* len) {
+  if (!valid_ctx(ctx) || !len) return SR_EINVAL;
+  *len = (int64_t)ctx->last_plan.size();
+  if (out && cap >= *len) memcpy(out, ctx->last_plan.data(), ctx->last_plan.size() * 4);
+  return SR_OK;
+}
+
+// ------------------------------------------------------------------------------ queries
+
+sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev) {
+  if (!valid_ctx(ctx) || !out_dev) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  const int64_t n = ctx->g.n;
+  if (x < 0 || x >= n) return SR_ERANGE;
+  if (what == SR_COL_S) {
+    if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+    HC(launch_copy_row(ctx->S, n, x, out_dev, ctx->stream));
+    return SR_OK;
+  }
+  if (what != SR_COL_DELTA) return SR_EINVAL;
+  if (ctx->last_r == 0) return SR_EMODE;
+  HC(launch_delta_col(ctx->P, ctx->pld, ctx->last_r, n, x, out_dev, ctx->stream));
+  return SR_OK;
+}
+
+sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* out_dev,
+                        int64_t ld_out) {
+  if (!valid_ctx(ctx) || !cols || !out_dev || ncols < 0) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  const int64_t n = ctx->g.n;
+  if (ld_out < n) return SR_EINVAL;
+  for (int32_t t = 0; t < ncols; ++t)
+    if (cols[t] < 0 || cols[t] >= n) return SR_ERANGE;
+  if (ncols == 0) return SR_OK;
+  if (ctx->ids_cap < ncols) {
+    HC(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_ids);
+    ctx->d_ids = nullptr;
+    ctx->ids_cap = 0;
+    if (dalloc(&ctx->d_ids, ncols) != hipSuccess) return SR_ENOMEM;
+    ctx->ids_cap = ncols;
+  }
+  HC(hipStreamSynchronize(ctx->stream));  // d_ids may be read by earlier work
+  HC(hipMemcpy(ctx->d_ids, cols, (size_t)ncols * 4, hipMemcpyHostToDevice));
+  if (ctx->cfg.mode == SR_DENSE) {
+    HC(launch_rows_to_f32(ctx->S, n, ctx->d_ids, ncols, out_dev, ld_out, ctx->stream));
+    return SR_OK;
+  }
+  if (ctx->last_r == 0) return SR_EMODE;
+  LowRankArgs la{};
+  la.P = ctx->P;
+  la.pld = ctx->pld;
+  la.r = ctx->last_r;
+  la.rows = ctx->d_ids;
+  la.nrows = ncols;
+  la.ncols = n;
+  la.out = out_dev;
+  la.ld_out = ld_out;
+  HC(launch_lowrank(la, ctx->stream));
+  return SR_OK;
+}
+
+sr_status sr_gather_pairs(sr_ctx* ctx, int64_t np, const int32_t* a, const int32_t* b,
+                          double* out) {
+  if (!valid_ctx(ctx) || np < 0 || (np > 0 && (!a || !b || !out))) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+  HC(launch_gather_pairs(ctx->S, np, a, b, out, ctx->stream));
+  return SR_OK;
+}
+
+sr_status sr_copy_S(sr_ctx* ctx, double* out_dev, int64_t ld) {
+  if (!valid_ctx(ctx) || !out_dev) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+  if (ld < ctx->g.n) return SR_EINVAL;
+  HC(launch_from_store(ctx->S, ctx->g.n, out_dev, ld, ctx->stream));
+  return SR_OK;
+}
+
+sr_status sr_get_aff(sr_ctx* ctx, int32_t level, int32_t* A_dev, int64_t* nA, int32_t* B_dev,
+                     int64_t* nB) {
+  if (!valid_ctx(ctx) || !nA || !nB) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (!ctx->last_aff) return SR_EMODE;
+  if (level < -1 || level > ctx->cfg.K) return SR_ERANGE;
+  const uint32_t* a = level < 0 ? ctx->Ahat : ctx->Abits + (int64_t)level * ctx->W;
+  const uint32_t* b = level < 0 ? ctx->Bhat : ctx->Bbits + (int64_t)level * ctx->W;
+  HC(launch_bits_to_list(a, ctx->g.n, ctx->W, A_dev, ctx->d_cnt + 4, ctx->stream));
+  HC(launch_bits_to_list(b, ctx->g.n, ctx->W, B_dev, ctx->d_cnt + 5, ctx->stream));
+  HC(hipMemcpyAsync(ctx->h_cnt + 4, ctx->d_cnt + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                    ctx->stream));
+  HC(hipStreamSynchronize(ctx->stream));
+  *nA = ctx->h_cnt[4];
+  *nB = ctx->h_cnt[5];
+  return SR_OK;
+}
+
+sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (n) *n = ctx->g.n;
+  if (m) *m = ctx->g.m;
+  return SR_OK;
+}
+
+sr_status sr_synchronize(sr_ctx* ctx) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  HC(hipStreamSynchronize(ctx->stream));
+  return SR_OK;
+}
+
+// ------------------------------------------------------------------------------ adjoint
+
+sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int32_t* b_dev,
+                   const double* g_dev, double* dw_dev) {
+  if (!valid_ctx(ctx) || npairs < 0 || !dw_dev || (npairs > 0 && (!a_dev || !b_dev || !g_dev)))
+    return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (ctx->cfg.mode != SR_DENSE || ctx->updated) return SR_EMODE;
+  const int64_t n = ctx->g.n;
+  const int64_t m = (int64_t)ctx->src0.size();
+  const double C = ctx->cfg.C;
+  hipStream_t s = ctx->stream;
+  const int64_t ldi = (n + 63) / 64 * 64;
+  double *Sig = nullptr, *T = nullptr, *U = nullptr, *G = nullptr, *dq = nullptr;
+  int32_t* se = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(Sig);
+    (void)hipFree(T);
+    (void)hipFree(U);
+    (void)hipFree(G);
+    (void)hipFree(dq);
+    (void)hipFree(se);
+  };
+  if (dalloc(&Sig, n * ldi) != hipSuccess || dalloc(&T, n * ldi) != hipSuccess ||
+      dalloc(&U, n * ldi) != hipSuccess || dalloc(&G, n * ldi) != hipSuccess ||
+      dalloc(&dq, (int64_t)ctx->g.in.idx.size()) != hipSuccess ||
+      dalloc(&se, (int64_t)ctx->slot_edge0.size()) != hipSuccess) {
+    cleanup();
+    return SR_ENOMEM;
+  }
+  const DevQ q = devq(ctx);
+  const DevAdj out = devout(ctx);
+  hipError_t e = hipMemcpy(se, ctx->slot_edge0.data(), ctx->slot_edge0.size() * 4,
+                           hipMemcpyHostToDevice);
+  // Gs = G + G^T: Sig = Lam + Lam^T solves Sig = Gs + C Q^T Sig Q (Lam = G + C Q^T Lam Q).
+  if (e == hipSuccess) e = hipMemsetAsync(G, 0, (size_t)n * ldi * 8, s);
+  if (e == hipSuccess) e = launch_scatter_pairs_sym(G, n, npairs, a_dev, b_dev, g_dev, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(Sig, G, (size_t)n * ldi * 8,
+                                          hipMemcpyDeviceToDevice, s);
+  // Sig symmetric: Q^T Sig Q = Q^T (Q^T Sig)^T, so U = Q^T Sig, T = U^T, Sig' = Gs + C Q^T T.
+  for (int it = 0; it < ctx->cfg.init_max_iter && e == hipSuccess; ++it) {
+    e = hipMemsetAsync(ctx->d_max, 0, 8, s);
+    if (e == hipSuccess) e = launch_spmm_qt_rows(q, out, n, Sig, U, 1.0, nullptr, nullptr,
+                                                 nullptr, s);
+    if (e == hipSuccess) e = launch_transpose(n, U, T, s);
+    if (e == hipSuccess) e = launch_spmm_qt_rows(q, out, n, T, U, C, G, Sig, ctx->d_max, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost,
+                                            s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    std::swap(Sig, U);
+    double step;
+    memcpy(&step, ctx->h_max, 8);
+    if (step <= ctx->cfg.init_tol) break;
+  }
+  // T = (Q S)^T: T = S (float64), U = Q T, T = U^T.
+  if (e == hipSuccess) e = launch_from_store(ctx->S, n, T, ldi, s);
+  if (e == hipSuccess) e = launch_spmm_rows(q, n, T, U, 1.0, 0.0, nullptr, nullptr, s);
+  if (e == hipSuccess) e = launch_transpose(n, U, T, s);
+  if (e == hipSuccess) e = launch_edge_grad(q, n, Sig, T, C, se, dq, dw_dev, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  (void)m;
+  if (e != hipSuccess) return fail_hip(ctx);
+  return SR_OK;
+}
+
+sr_status sr_profile(sr_ctx* ctx, int32_t enable) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  ctx->profiling = enable != 0;
+  return SR_OK;
+}
+
+sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t reset) {
+  if (!valid_ctx(ctx) || !ms || !launches) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  HC(hipStreamSynchronize(ctx->stream));
+  for (auto& ev : ctx->prof_events) {
+    float t = 0.0f;
+    HC(hipEventElapsedTime(&t, ev.first, ev.second));
+    ctx->prof_ms += t;
+    ctx->prof_launches++;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  ctx->prof_events.clear();
+  *ms = ctx->prof_ms;
+  *launches = ctx->prof_launches;
+  if (reset) {
+    ctx->prof_ms = 0.0;
+    ctx->prof_launches = 0;
+  }
+  return SR_OK;
+}
+
+sr_status sr_mfma_layout_probe(const double* a_dev, const double* b_dev, double* out_dev,
+                               void* hip_stream) {
+  if (!a_dev || !b_dev || !out_dev) return SR_EINVAL;
+  return launch_mfma_probe(a_dev, b_dev, out_dev, (hipStream_t)hip_stream) == hipSuccess
+             ? SR_OK
+             : SR_EHIP;
+}
+
+}  // extern "C"

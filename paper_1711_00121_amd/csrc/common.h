@@ -1,0 +1,73 @@
+// Device-side definitions shared by the kernels of libsimrank (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sr {
+
+// Storage kinds of the dense S (values of sr_config::s_prec).
+enum { PREC_FP64 = 0, PREC_HILO = 1, PREC_FP32 = 2 };
+
+// A view of the dense S: row-major with leading dimension ld.
+//  FP64:  value = d[a*ld + b]
+//  HILO:  value = (double)hi[a*ld + b] + (double)lo[a*ld + b]; lo holds the rounding error of
+//         hi, so the pair carries about 48 significant bits.
+//  FP32:  value = hi[a*ld + b]
+struct SView {
+  int prec;
+  double* d;
+  float* hi;
+  float* lo;
+  int64_t ld;
+};
+
+__device__ __forceinline__ double s_get(const SView& s, int64_t off) {
+  if (s.prec == PREC_FP64) return s.d[off];
+  if (s.prec == PREC_HILO) return (double)s.hi[off] + (double)s.lo[off];
+  return (double)s.hi[off];
+}
+
+// Stores the float64 value t: HILO splits it into the nearest float and the float nearest to
+// the remainder.
+__device__ __forceinline__ void s_put(const SView& s, int64_t off, double t) {
+  if (s.prec == PREC_FP64) {
+    s.d[off] = t;
+  } else if (s.prec == PREC_HILO) {
+    float h = (float)t;
+    s.hi[off] = h;
+    s.lo[off] = (float)(t - (double)h);
+  } else {
+    s.hi[off] = (float)t;
+  }
+}
+
+// Slotted CSR on the device. Row r of a list occupies idx[start[r] .. start[r] + len[r]);
+// rows keep spare slots so single-edge insertions patch in place.
+struct DevAdj {
+  const int32_t* start;
+  const int32_t* len;
+  const int32_t* idx;
+  const double* w;  // per-slot weight, or null (unweighted)
+};
+
+// Q of the current graph: in-lists by sink. Q[a][x] = 1/len[a] (unweighted) or w/W[a].
+struct DevQ {
+  DevAdj in;
+  const double* W;  // row weight sums (weighted), or null
+};
+
+__device__ __forceinline__ double wave_sum(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+
+__device__ __forceinline__ bool bit_get(const uint32_t* bm, int64_t v) {
+  return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+
+__device__ __forceinline__ void bit_set_atomic(uint32_t* bm, int64_t v) {
+  atomicOr(bm + (v >> 5), 1u << (v & 31));
+}
+
+}  // namespace sr

@@ -1,0 +1,398 @@
+// Dense-S kernels: row gathers and the gamma vector of the rank-one Sylvester equation
+// (Theorems 2, 3, 7, 9 and Table 2), new-node writes (Theorem 8, Algorithm 5), the initial S
+// by the fixed point of eq (03a), and queries.
+#include "kernels.h"
+
+namespace sr {
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ void block_max_atomic(double v, unsigned long long* dst) {
+  // v >= 0: the IEEE bit patterns of nonnegative doubles order like unsigned integers.
+  __shared__ double red[kB / 64];
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ __launch_bounds__(kB) void gather_rows_kernel(SView S, int64_t n, IdList I, int acc,
+                                                         int32_t j, double* __restrict__ SI,
+                                                         double* __restrict__ Sj,
+                                                         uint32_t* __restrict__ suppI,
+                                                         uint32_t* __restrict__ suppJ) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const bool in = a < n;
+  double s = (in && acc) ? SI[a] : 0.0;
+  bool sup = false;
+  if (in) {
+    for (int t = 0; t < I.count; ++t) {
+      const double v = s_get(S, (int64_t)I.id[t] * S.ld + a);
+      s += v;
+      sup |= (v != 0.0);
+    }
+    SI[a] = s;
+  }
+  const uint64_t bI = __ballot(sup);
+  const int lane = threadIdx.x & 63;
+  const int64_t word = a >> 5;
+  if (lane == 0 || lane == 32) {
+    const uint32_t bits = (uint32_t)(lane == 0 ? bI : (bI >> 32));
+    if (a < n) suppI[word] = acc ? (suppI[word] | bits) : bits;
+  }
+  if (j >= 0) {
+    bool supj = false;
+    if (in) {
+      const double v = s_get(S, (int64_t)j * S.ld + a);
+      Sj[a] = v;
+      supj = v != 0.0;
+    }
+    const uint64_t bJ = __ballot(supj);
+    if ((lane == 0 || lane == 32) && a < n)
+      suppJ[word] = (uint32_t)(lane == 0 ? bJ : (bJ >> 32));
+  }
+}
+
+__global__ __launch_bounds__(kB) void gather_inrows_kernel(SView S, int64_t n, DevQ q, int32_t j,
+                                                           double* __restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a >= n) return;
+  const int len = q.in.len[j];
+  const int st = q.in.start[j];
+  double s = 0.0;
+  for (int p = 0; p < len; ++p) s += s_get(S, (int64_t)q.in.idx[st + p] * S.ld + a);
+  out[a] = s;
+}
+
+__device__ __forceinline__ double sum_at(const double* v, const IdList& I) {
+  double s = 0.0;
+  for (int t = 0; t < I.count; ++t) s += v[I.id[t]];
+  return s;
+}
+
+__global__ __launch_bounds__(kB) void direct_z_kernel(GammaArgs g, int64_t n,
+                                                      const double* __restrict__ SI,
+                                                      const double* __restrict__ zsum,
+                                                      double* __restrict__ z) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a >= n) return;
+  const double d = (double)g.delta;
+  const double si = SI[a] / d;
+  double v;
+  if (g.op > 0) {
+    v = (g.dj == 0) ? si : si - zsum[a] / (double)g.dj;
+  } else {
+    v = (g.dj == g.delta) ? -si : zsum[a] / (double)g.dj - si;
+  }
+  z[a] = v;
+}
+
+__global__ __launch_bounds__(kB) void gamma_kernel(GammaArgs g, int64_t n,
+                                                   const double* __restrict__ SI,
+                                                   const double* __restrict__ Sj,
+                                                   const double* __restrict__ QSI,
+                                                   const double* __restrict__ z,
+                                                   const double* __restrict__ Qz,
+                                                   double* __restrict__ P, int pld,
+                                                   unsigned long long* maxabs) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const double C = g.C;
+  const double d = (double)g.delta;
+  const double dj = (double)g.dj;
+  const bool isj = (a == g.j);
+  double gam = 0.0;
+  if (a < n) {
+    if (g.kind == 0) {
+      // Theorem 3 (eqs (29aa), (29bb), (29b)), Theorem 9, Table 2 rows (C0).
+      const double SII = sum_at(SI, g.I);
+      const double lam = SII / (d * d) + Sj[g.j] / C - (2.0 / d) * QSI[g.j] - 1.0 / C + 1.0;
+      if (g.op > 0) {
+        if (g.dj == 0) {
+          gam = QSI[a] / d + (isj ? SII / (2.0 * d * d) : 0.0);
+        } else {
+          const double f = d / (dj + d);
+          gam = f * (QSI[a] / d - Sj[a] / C +
+                     (isj ? lam * d / (2.0 * (dj + d)) + 1.0 / C - 1.0 : 0.0));
+        }
+      } else {
+        if (g.dj == g.delta) {
+          gam = -QSI[a] / d + (isj ? SII / (2.0 * d * d) : 0.0);
+        } else {
+          const double f = d / (dj - d);
+          gam = f * (Sj[a] / C - QSI[a] / d +
+                     (isj ? lam * d / (2.0 * (dj - d)) - 1.0 / C + 1.0 : 0.0));
+        }
+      }
+    } else if (g.kind == 1) {
+      // Theorem 2, eq (20): w = Q z + (v^T z / 2) u with z = S v; gamma = u_j w.
+      const double zI = sum_at(z, g.I) / d;
+      double vz, uj;
+      if (g.op > 0) {
+        vz = (g.dj == 0) ? zI : zI - Qz[g.j];
+        uj = (g.dj == 0) ? 1.0 : d / (dj + d);
+      } else {
+        vz = (g.dj == g.delta) ? -zI : Qz[g.j] - zI;
+        uj = (g.dj == g.delta) ? 1.0 : d / (dj - d);
+      }
+      gam = uj * (Qz[a] + (isj ? 0.5 * vz * uj : 0.0));
+    } else {
+      // Eq (60) and Table 2 row (C2): the z vector is eta_0.
+      const double sjj = Sj[g.j];
+      gam = (isj ? (d * sjj - (d - C) * (1.0 - C)) / (2.0 * C * (dj + d)) + (1.0 - C) / C
+                 : 0.0) -
+            Sj[a] / C;
+    }
+    *reinterpret_cast<double2*>(P + a * pld) = make_double2(isj ? g.xi0 : 0.0, gam);
+  }
+  if (maxabs) block_max_atomic(a < n ? fabs(gam) : 0.0, maxabs);
+}
+
+__global__ __launch_bounds__(kB) void c1_border_kernel(SView S, int64_t n_old, int32_t j,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ SI, IdList I,
+                                                       double C) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a < n_old && a != j) {
+    const double v = y[a];
+    s_put(S, (int64_t)j * S.ld + a, v);
+    s_put(S, a * S.ld + j, v);
+  }
+  if (a == 0) {
+    const double d = (double)I.count;
+    const double SII = sum_at(SI, I);
+    s_put(S, (int64_t)j * S.ld + j, C / (d * d) * SII + 1.0 - C);
+  }
+}
+
+__global__ void set_diag_kernel(SView S, DiagList dl) {
+  const int t = threadIdx.x;
+  if (t < dl.count) s_put(S, (int64_t)dl.id[t] * S.ld + dl.id[t], dl.val[t]);
+}
+
+// Y[a][c] = scale * (1/d_a) sum_{x in in(a)} X[x][c] (+ add_diag at c == a). X and Y use the
+// leading dimension ldi (a multiple of 64), rows and columns < n.
+__global__ __launch_bounds__(kB) void spmm_rows_kernel(DevQ q, int64_t n, int64_t ldi,
+                                                       const double* __restrict__ X,
+                                                       double* __restrict__ Y, double scale,
+                                                       double add_diag,
+                                                       const double* __restrict__ prev,
+                                                       unsigned long long* maxdiff) {
+  const int64_t a = blockIdx.x;
+  const int64_t c = ((int64_t)blockIdx.y * kB + threadIdx.x) * 2;
+  const int len = q.in.len[a];
+  const int st = q.in.start[a];
+  double2 acc = make_double2(0.0, 0.0);
+  if (c < n) {
+    for (int p = 0; p < len; ++p) {
+      const int64_t x = q.in.idx[st + p];
+      const double2 v = *reinterpret_cast<const double2*>(X + x * ldi + c);
+      if (q.in.w) {
+        const double w = q.in.w[st + p];
+        acc.x += w * v.x;
+        acc.y += w * v.y;
+      } else {
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+    }
+  }
+  double diff = 0.0;
+  if (c < n) {
+    double inv = 0.0;
+    if (len > 0) inv = q.W ? 1.0 / q.W[a] : 1.0 / (double)len;
+    double2 o = make_double2(scale * (acc.x * inv), scale * (acc.y * inv));
+    if (c == a) o.x += add_diag;
+    if (c + 1 == a) o.y += add_diag;
+    if (c + 1 >= n) o.y = 0.0;
+    *reinterpret_cast<double2*>(Y + a * ldi + c) = o;
+    if (prev) {
+      const double2 pv = *reinterpret_cast<const double2*>(prev + a * ldi + c);
+      diff = fmax(fabs(o.x - pv.x), (c + 1 < n) ? fabs(o.y - pv.y) : 0.0);
+    }
+  }
+  if (maxdiff) block_max_atomic(diff, maxdiff);
+}
+
+__global__ __launch_bounds__(1024) void transpose_kernel(int64_t n, int64_t ldi,
+                                                         const double* __restrict__ X,
+                                                         double* __restrict__ Y) {
+  __shared__ double tile[32][33];
+  const int64_t bx = (int64_t)blockIdx.x * 32, by = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  if (by + ty < n && bx + tx < n) tile[ty][tx] = X[(by + ty) * ldi + bx + tx];
+  __syncthreads();
+  if (bx + ty < n && by + tx < n) Y[(bx + ty) * ldi + by + tx] = tile[tx][ty];
+}
+
+__global__ __launch_bounds__(kB) void to_store_kernel(SView dst, int64_t n, int64_t ldi,
+                                                      const double* __restrict__ src) {
+  const int64_t a = blockIdx.x;
+  const int64_t c = (int64_t)blockIdx.y * kB + threadIdx.x;
+  if (c < n) s_put(dst, a * dst.ld + c, src[a * ldi + c]);
+}
+
+__global__ __launch_bounds__(kB) void from_store_kernel(SView src, int64_t n,
+                                                        double* __restrict__ dst,
+                                                        int64_t ld_dst) {
+  const int64_t a = blockIdx.x;
+  const int64_t c = (int64_t)blockIdx.y * kB + threadIdx.x;
+  if (c < n) dst[a * ld_dst + c] = s_get(src, a * src.ld + c);
+}
+
+__global__ __launch_bounds__(kB) void copy_row_kernel(SView S, int64_t n, int32_t x,
+                                                      double* __restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a < n) out[a] = s_get(S, (int64_t)x * S.ld + a);
+}
+
+__global__ __launch_bounds__(kB) void gather_pairs_kernel(SView S, int64_t np,
+                                                          const int32_t* __restrict__ pa,
+                                                          const int32_t* __restrict__ pb,
+                                                          double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (p < np) out[p] = s_get(S, (int64_t)pa[p] * S.ld + pb[p]);
+}
+
+__global__ __launch_bounds__(kB) void rows_to_f32_kernel(SView S, int64_t n,
+                                                         const int32_t* __restrict__ rows,
+                                                         float* __restrict__ out,
+                                                         int64_t ld_out) {
+  const int64_t t = blockIdx.x;
+  const int64_t a = (int64_t)blockIdx.y * kB + threadIdx.x;
+  if (a < n) out[t * ld_out + a] = (float)s_get(S, (int64_t)rows[t] * S.ld + a);
+}
+
+__global__ __launch_bounds__(kB) void unit_vector_kernel(double* x, int64_t n, int32_t q) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a < n) x[a] = (a == q) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(kB) void fill_diag_kernel(double* A, int64_t n, int64_t ld,
+                                                       double v) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a < n) A[a * ld + a] = v;
+}
+
+__global__ __launch_bounds__(kB) void diag_range_kernel(SView S, int64_t lo, int64_t hi,
+                                                        double v) {
+  const int64_t a = lo + (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a < hi) s_put(S, a * S.ld + a, v);
+}
+
+inline unsigned g1(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+}  // namespace
+
+hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unit_vector_kernel<<<g1(n), kB, 0, s>>>(x, n, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_diag_kernel<<<g1(n), kB, 0, s>>>(A, n, ld, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s) {
+  if (hi <= lo) return hipSuccess;
+  diag_range_kernel<<<g1(hi - lo), kB, 0, s>>>(S, lo, hi, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(SView S, int64_t n, const IdList& I, int acc, int32_t j,
+                              double* SI, double* Sj, uint32_t* suppI, uint32_t* suppJ,
+                              hipStream_t s) {
+  gather_rows_kernel<<<g1(n), kB, 0, s>>>(S, n, I, acc, j, SI, Sj, suppI, suppJ);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_inrows(SView S, int64_t n, const DevQ& q, int32_t j, double* out,
+                                hipStream_t s) {
+  gather_inrows_kernel<<<g1(n), kB, 0, s>>>(S, n, q, j, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_z(const GammaArgs& g, int64_t n, const double* SI, const double* zsum,
+                           double* zbuf, hipStream_t s) {
+  direct_z_kernel<<<g1(n), kB, 0, s>>>(g, n, SI, zsum, zbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma(const GammaArgs& g, int64_t n, const double* SI, const double* Sj,
+                        const double* QSI, const double* zbuf, const double* Qz, double* P,
+                        int pld, unsigned long long* maxabs, hipStream_t s) {
+  gamma_kernel<<<g1(n), kB, 0, s>>>(g, n, SI, Sj, QSI, zbuf, Qz, P, pld, maxabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_c1_border(SView S, int64_t n_old, int32_t j, const double* y,
+                            const double* SI, const IdList& I, double C, hipStream_t s) {
+  c1_border_kernel<<<g1(n_old > 0 ? n_old : 1), kB, 0, s>>>(S, n_old, j, y, SI, I, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_diag(SView S, const DiagList& d, hipStream_t s) {
+  if (d.count <= 0) return hipSuccess;
+  set_diag_kernel<<<1, 64, 0, s>>>(S, d);
+  return hipGetLastError();
+}
+
+static int64_t init_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+hipError_t launch_spmm_rows(const DevQ& q, int64_t n, const double* X, double* Y, double scale,
+                            double add_diag, const double* prev, unsigned long long* maxdiff,
+                            hipStream_t s) {
+  const int64_t ldi = init_ld(n);
+  dim3 grid((unsigned)n, (unsigned)((n + 2 * kB - 1) / (2 * kB)));
+  spmm_rows_kernel<<<grid, kB, 0, s>>>(q, n, ldi, X, Y, scale, add_diag, prev, maxdiff);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(int64_t n, const double* X, double* Y, hipStream_t s) {
+  const int64_t ldi = init_ld(n);
+  dim3 grid((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32));
+  transpose_kernel<<<grid, dim3(32, 32), 0, s>>>(n, ldi, X, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_store(SView dst, int64_t n, const double* src, hipStream_t s) {
+  dim3 grid((unsigned)n, g1(n));
+  to_store_kernel<<<grid, kB, 0, s>>>(dst, n, init_ld(n), src);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_store(SView src, int64_t n, double* dst, int64_t ld_dst, hipStream_t s) {
+  dim3 grid((unsigned)n, g1(n));
+  from_store_kernel<<<grid, kB, 0, s>>>(src, n, dst, ld_dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_row(SView S, int64_t n, int32_t x, double* out, hipStream_t s) {
+  copy_row_kernel<<<g1(n), kB, 0, s>>>(S, n, x, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_pairs(SView S, int64_t np, const int32_t* a, const int32_t* b,
+                               double* out, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  gather_pairs_kernel<<<g1(np), kB, 0, s>>>(S, np, a, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_to_f32(SView S, int64_t n, const int32_t* rows, int32_t nrows,
+                              float* out, int64_t ld_out, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  dim3 grid((unsigned)nrows, g1(n));
+  rows_to_f32_kernel<<<grid, kB, 0, s>>>(S, n, rows, out, ld_out);
+  return hipGetLastError();
+}
+
+}  // namespace sr

@@ -1,0 +1,215 @@
+// Host-side launchers of the HIP kernels of libsimrank. Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace sr {
+
+// ---------------------------------------------------------------------------------------
+// Graph patches: small in-place edits of the device slotted CSR, passed by value.
+struct Patch {
+  static constexpr int MAX = 30;
+  int32_t count;
+  int32_t array[MAX];  // index into the pointer table below
+  int32_t index[MAX];
+  int32_t value[MAX];
+};
+// Pointer table order: in_start, in_len, in_idx, out_start, out_len, out_idx.
+struct AdjPtrs {
+  int32_t* p[6];
+};
+hipError_t launch_patch(const AdjPtrs& t, const Patch& p, hipStream_t s);
+
+// Row lists passed by value (sources I of a block, up to 60 per launch).
+struct IdList {
+  static constexpr int MAX = 60;
+  int32_t count;
+  int32_t id[MAX];
+};
+
+// ---------------------------------------------------------------------------------------
+// Sparse traversals. Rows with more than kLight entries are "heavy": the host lists them and
+// they are processed in chunks of kChunk entries by whole workgroups.
+constexpr int kLight = 256;
+constexpr int kChunk = 4096;
+struct HeavyArgs {
+  const int32_t* rows;  // heavy row ids (device), nh of them
+  int32_t nh;
+  int32_t maxc;         // chunk slots per heavy row (>= ceil(len / kChunk) for every row)
+  double* partial;      // 2 * nh * maxc doubles
+  uint32_t* counter;    // nh counters; zero between launches
+};
+// Pull form of one affected-area level (Theorem 4): out bit b is set when some in-neighbour x
+// of b (new graph) has (s0 | s1)(x). Null sets are empty.
+struct AffLevel {
+  const uint32_t* a0;
+  const uint32_t* a1;
+  uint32_t* aout;
+  const uint32_t* b0;
+  const uint32_t* b1;
+  uint32_t* bout;
+};
+// y[a] = post * (base[a] + scale * (Q x)[a]) for a < n (base may be null). When fout is set,
+// bit a of fout is also set if some in-neighbour x of a has bit x of fin (old-graph F1).
+hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const double* x,
+                         double* y, double scale, hipStream_t s, const double* base = nullptr,
+                         double post = 1.0, const uint32_t* fin = nullptr,
+                         uint32_t* fout = nullptr);
+// y[b] = scale * (Q^T x)[b] = scale * sum_{a in out(b)} Q[a][b] x[a] (h: heavy out-rows).
+hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
+                          const double* x, double* y, double scale, hipStream_t s);
+// One step of eq (16a) on the panel P (row a holds (xi_k, eta_k) pairs for k = 0..K, pld
+// doubles per row): xi_{k+1} = sx * Q xi_k, eta_{k+1} = sy * Q eta_k; optionally one
+// affected-area level in the same pass.
+hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, double* P, int pld,
+                              int k, double sx, double sy, const AffLevel* aff, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Dense S helpers.
+// SI[a] = sum_{i in I} S[i][a] (accumulate when acc != 0), suppI |= (S[i][a] != 0);
+// when j >= 0 also Sj[a] = S[j][a], suppJ bit = (S[j][a] != 0).
+hipError_t launch_gather_rows(SView S, int64_t n, const IdList& I, int acc, int32_t j,
+                              double* SI, double* Sj, uint32_t* suppI, uint32_t* suppJ,
+                              hipStream_t s);
+// out[a] = sum_{x in in_old(j)} S[x][a] (rows of S for the in-neighbours of j).
+hipError_t launch_gather_inrows(SView S, int64_t n, const DevQ& q, int32_t j, double* out,
+                                hipStream_t s);
+
+// Scalars and coefficients of one block update, shared by the gamma kernels.
+struct GammaArgs {
+  int32_t kind;     // 0 closed form (C0), 1 direct form (C0), 2 C2 z of eq (60) / Table 2
+  int32_t op;       // +1 insert, -1 delete
+  int32_t j;
+  int32_t delta;
+  int64_t dj;       // in-degree of j before the block
+  double C;
+  double xi0;       // xi_0 = xi0 * e_j
+  IdList I;         // sources (for S_II and the direct form's v)
+};
+// Writes column 0 of the panel: (xi_0, eta_0) = (xi0 e_j, gamma). Inputs: SI = S[:, I],
+// Sj = S[:, j], QSI = Q_old S[:, I]; the direct form also needs zsum = sum over in_old(j)
+// of S rows and Qz = Q_old z (computed by the caller from zbuf). maxabs receives
+// max|gamma| bits (atomicMax on the IEEE pattern of a nonnegative double).
+hipError_t launch_gamma(const GammaArgs& g, int64_t n, const double* SI, const double* Sj,
+                        const double* QSI, const double* zbuf, const double* Qz, double* P,
+                        int pld, unsigned long long* maxabs, hipStream_t s);
+// Direct form step 1: z = S v into zbuf, from SI and zsum (see Theorem 2, eq (20)).
+hipError_t launch_direct_z(const GammaArgs& g, int64_t n, const double* SI,
+                           const double* zsum, double* zbuf, hipStream_t s);
+
+// C1 border (Theorem 8, Table 2 row C1): S[j][a] = S[a][j] = y[a] for a < n_old,
+// S[j][j] = corner = (C/delta^2) S_II + 1 - C (S_II read from SI at the sources).
+hipError_t launch_c1_border(SView S, int64_t n_old, int32_t j, const double* y,
+                            const double* SI, const IdList& I, double C, hipStream_t s);
+// Writes S[id][id] = val[t] for a short list (new-node diagonals).
+struct DiagList {
+  static constexpr int MAX = 30;
+  int32_t count;
+  int32_t id[MAX];
+  double val[MAX];
+};
+hipError_t launch_set_diag(SView S, const DiagList& d, hipStream_t s);
+
+// Initial S by the fixed point of eq (03a), in float64 with leading dimension n.
+// Y[a][:] = scale * (Q X)[a][:]  (+ add_diag on Y[a][a]); when prev != null also
+// maxdiff = max |Y - prev| (atomicMax on the IEEE bits).
+hipError_t launch_spmm_rows(const DevQ& q, int64_t n, const double* X, double* Y,
+                            double scale, double add_diag, const double* prev,
+                            unsigned long long* maxdiff, hipStream_t s);
+hipError_t launch_transpose(int64_t n, const double* X, double* Y, hipStream_t s);
+// dst (store format, leading dim ld) = src (float64, leading dim n), rows/cols < n.
+hipError_t launch_to_store(SView dst, int64_t n, const double* src, hipStream_t s);
+hipError_t launch_from_store(SView src, int64_t n, double* dst, int64_t ld_dst,
+                             hipStream_t s);
+hipError_t launch_copy_row(SView S, int64_t n, int32_t x, double* out, hipStream_t s);
+hipError_t launch_gather_pairs(SView S, int64_t np, const int32_t* a, const int32_t* b,
+                               double* out, hipStream_t s);
+hipError_t launch_rows_to_f32(SView S, int64_t n, const int32_t* rows, int32_t nrows,
+                              float* out, int64_t ld_out, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Affected areas (Theorem 4). Bitmaps of W words per level; A and B hold K+1 levels each.
+struct AffArgs {
+  int64_t n;
+  int32_t W;       // words per bitmap
+  int32_t K;
+  uint32_t* A;     // (K+1) * W words
+  uint32_t* B;
+};
+// Level 0 (after F1 = out_old(supp S[I, :]) was or-ed into B_0 by the Q S[:, I] product):
+// B_0 |= supp S[j, :] when f2, and j joins A_0 and B_0.
+hipError_t launch_aff_level0(const AffArgs& a, const uint32_t* suppJ, int f2, int32_t j,
+                             hipStream_t s);
+// A_hat = A_0 | A_K, B_hat = B_0 | B_K into Ahat/Bhat; rows = ascending list of
+// A_hat | B_hat, entry (node << 2) | (in A_hat << 1) | (in B_hat);
+// cnt[0..3] = |A_hat|, |B_hat|, |A_hat & B_hat|, |rows|.
+hipError_t launch_aff_compact(const AffArgs& a, uint32_t* Ahat, uint32_t* Bhat,
+                              int32_t* rows, int64_t* cnt, hipStream_t s);
+// Ascending list of the set bits of bm (n bits) into out; *cnt receives the count.
+hipError_t launch_bits_to_list(const uint32_t* bm, int64_t n, int32_t W, int32_t* out,
+                               int64_t* cnt, hipStream_t s);
+// Or-combination helper: dst = a | b (W words).
+hipError_t launch_bits_or(const uint32_t* a, const uint32_t* b, uint32_t* dst, int32_t W,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Low-rank update of S (the hot kernel):
+//   for each listed row a (rows[t], t < nrows; with a mask the entries are packed as
+//   (node << 2) | (in Ahat << 1) | (in Bhat)) and column b < ncols where the pair is in
+//   Ahat x Bhat u Bhat x Ahat (all pairs when Ahat is null):
+//       S[a][b] += sum_{c < r} P[a][c] * P[b][c ^ 1]
+// P rows hold (xi_k, eta_k) pairs, so the sum is sum_k xi_k[a] eta_k[b] + eta_k[a] xi_k[b].
+// For several blocks the panel holds their pairs side by side (r = 2 (K+1) * blocks).
+// Column-output form (out != null): out[t][b] = sum_c P[rows[t]][c] * P[b][c ^ 1] as float32
+// (row t of out at out + t * ld_out), no mask; S is not touched.
+struct LowRankArgs {
+  SView S;
+  const double* P;
+  int32_t pld;        // doubles per panel row (multiple of 4)
+  int32_t r;          // columns of the panel used (multiple of 2)
+  const int32_t* rows;
+  int64_t nrows;      // used when nrows_dev is null
+  const int64_t* nrows_dev;
+  int64_t ncols;
+  const uint32_t* Ahat;
+  const uint32_t* Bhat;
+  float* out;
+  int64_t ld_out;
+};
+hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
+// Fused batches: the columns S_t[:, c] of the current S are the stored S plus the deferred
+// blocks' terms sum_{col < r} P[:, col] P[c, col ^ 1]. wts[col] = sum_{i in I} P[i][col ^ 1]
+// and wts[r + col] = P[j][col ^ 1] (j < 0: no second vector), then
+// SI[a] += sum_col P[a][col] wts[col] (when I nonempty), Sj[a] += sum_col P[a][col] wts[r+col].
+hipError_t launch_panel_correct(const double* P, int pld, int r, int64_t n, const IdList& I,
+                                int32_t j, double* wts, double* SI, double* Sj, hipStream_t s);
+// Plain reference form of the same update (one thread per entry, no MFMA), for checks.
+hipError_t launch_lowrank_ref(const LowRankArgs& a, hipStream_t s);
+// out[a] = sum_{c < r} P[a][c] * P[x][c ^ 1] for a < n (Delta S[:, x], eq (71)), float64.
+hipError_t launch_delta_col(const double* P, int pld, int r, int64_t n, int32_t x, double* out,
+                            hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Adjoint (edge-weight gradient). Dense matrices use leading dimension round_up(n, 64).
+// G[a][b] += g and G[b][a] += g for every pair (the symmetric part of dL/dS, doubled).
+hipError_t launch_scatter_pairs_sym(double* G, int64_t n, int64_t np, const int32_t* a,
+                                    const int32_t* b, const double* g, hipStream_t s);
+// Y[b][:] = scale * (Q^T X)[b][:] (+ Gadd[b][:] when Gadd != null); maxdiff vs prev as above.
+hipError_t launch_spmm_qt_rows(const DevQ& q, const DevAdj& out, int64_t n, const double* X,
+                               double* Y, double scale, const double* Gadd, const double* prev,
+                               unsigned long long* maxdiff, hipStream_t s);
+// Per sink x and in-list slot p (source y): dq[p] = C * <Sig[x, :], T[y, :]>, then
+// dw[slot_edge[p]] = (dq[p] - sum_p' Q[x][y_p'] dq[p']) / W_x (W_x = in-degree unweighted).
+hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const double* T,
+                            double C, const int32_t* slot_edge, double* dq, double* dw,
+                            hipStream_t s);
+// Small helpers.
+hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s);
+hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
+hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
+hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);
+
+}  // namespace sr

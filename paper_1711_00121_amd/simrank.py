@@ -1,0 +1,233 @@
+"""Python front of libsimrank: argument marshalling only. Every step of the incremental
+method runs in the library's HIP kernels; torch provides device memory and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp64": L.SR_S_FP64, "hilo": L.SR_S_FP32_HILO, "fp32": L.SR_S_FP32}
+_MODE = {"dense": L.SR_DENSE, "column": L.SR_COLUMN}
+_GAMMA = {"closed": L.SR_GAMMA_CLOSED, "direct": L.SR_GAMMA_DIRECT}
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(arr, ctype):
+    return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+def _dev(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def default_config(**kw):
+    lib = L.load()
+    cfg = L.sr_config()
+    L.check(lib.sr_default_config(C.byref(cfg)), "sr_default_config")
+    for k, v in kw.items():
+        if k == "s_prec":
+            v = _PREC[v] if isinstance(v, str) else v
+        elif k == "mode":
+            v = _MODE[v] if isinstance(v, str) else v
+        elif k == "gamma_form":
+            v = _GAMMA[v] if isinstance(v, str) else v
+        elif k in ("prune", "fused_batch"):
+            v = int(bool(v))
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Context:
+    """One incremental-SimRank context on the current CUDA (HIP) device and stream.
+
+    ``Context(n, src, dst, weight=None, S0=None, **config)`` builds the graph and the initial
+    S (fixed point of eq (03a) on the device unless ``S0`` is given). Config keys follow
+    ``sr_config``: C, K, K_ps, s_prec ('fp64' | 'hilo' | 'fp32'), mode ('dense' | 'column'),
+    gamma_form ('closed' | 'direct'), prune, node_cap, edge_cap, init_tol, init_max_iter,
+    batch_chunk, fused_batch.
+    """
+
+    def __init__(self, n, src, dst, weight=None, S0=None, stream=None, **config):
+        self.lib = L.load()
+        self.cfg = default_config(**config)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        src = _i32(src)
+        dst = _i32(dst)
+        w = None
+        if weight is not None:
+            w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64))
+        s0 = None
+        if S0 is not None:
+            s0 = S0.to(device="cuda", dtype=torch.float64).contiguous()
+        handle = C.c_void_p()
+        st = self.lib.init_simrank(
+            C.byref(handle), int(n), int(len(src)), _ptr(src, C.c_int32), _ptr(dst, C.c_int32),
+            _ptr(w, C.c_double) if w is not None else None, C.byref(self.cfg),
+            _dev(s0) if s0 is not None else None, C.c_void_p(self.stream.cuda_stream))
+        L.check(st, "init_simrank")
+        self.h = handle
+        self.m0 = len(src)
+
+    # ------------------------------------------------------------------ updates
+    def apply_edge_update(self, i, j, op=1, stats=False):
+        s = L.sr_update_stats() if stats else None
+        st = self.lib.apply_edge_update(self.h, int(i), int(j), int(op),
+                                        C.byref(s) if s is not None else None)
+        L.check(st, "apply_edge_update")
+        if s is None:
+            return None
+        return {f: getattr(s, f) for f, _ in L.sr_update_stats._fields_}
+
+    def apply_batch(self, src, dst, op, stats=False):
+        src = _i32(src)
+        dst = _i32(dst)
+        op = np.ascontiguousarray(np.asarray(op, dtype=np.int8))
+        s = L.sr_batch_stats() if stats else None
+        st = self.lib.apply_batch(self.h, int(len(src)), _ptr(src, C.c_int32),
+                                  _ptr(dst, C.c_int32), _ptr(op, C.c_int8),
+                                  C.byref(s) if s is not None else None)
+        L.check(st, "apply_batch")
+        if s is None:
+            return None
+        out = {f: getattr(s, f) for f, _ in L.sr_batch_stats._fields_}
+        out["blocks_case"] = list(s.blocks_case)
+        return out
+
+    # ------------------------------------------------------------------ queries
+    def sizes(self):
+        n = C.c_int64()
+        m = C.c_int64()
+        L.check(self.lib.sr_sizes(self.h, C.byref(n), C.byref(m)), "sr_sizes")
+        return n.value, m.value
+
+    def query_column(self, x, what="S"):
+        n, _ = self.sizes()
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        w = L.SR_COL_S if what == "S" else L.SR_COL_DELTA
+        L.check(self.lib.query_column(self.h, int(x), w, _dev(out)), "query_column")
+        return out
+
+    def query_columns(self, cols, out=None):
+        """Float32 columns as rows of the result: ``out[t, :] = column cols[t]``."""
+        n, _ = self.sizes()
+        cols = _i32(cols)
+        if out is None:
+            out = torch.empty((len(cols), n), dtype=torch.float32, device="cuda")
+        L.check(self.lib.query_columns(self.h, _ptr(cols, C.c_int32), len(cols), _dev(out),
+                                       out.stride(0)), "query_columns")
+        return out
+
+    def gather_pairs(self, a, b):
+        a = torch.as_tensor(a, dtype=torch.int32, device="cuda").contiguous()
+        b = torch.as_tensor(b, dtype=torch.int32, device="cuda").contiguous()
+        out = torch.empty(a.numel(), dtype=torch.float64, device="cuda")
+        L.check(self.lib.sr_gather_pairs(self.h, a.numel(), _dev(a), _dev(b), _dev(out)),
+                "sr_gather_pairs")
+        return out
+
+    def S(self):
+        n, _ = self.sizes()
+        out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        L.check(self.lib.sr_copy_S(self.h, _dev(out), n), "sr_copy_S")
+        return out
+
+    def get_aff(self, level=-1):
+        n, _ = self.sizes()
+        A = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        B = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        nA = C.c_int64()
+        nB = C.c_int64()
+        L.check(self.lib.sr_get_aff(self.h, int(level), _dev(A), C.byref(nA), _dev(B),
+                                    C.byref(nB)), "sr_get_aff")
+        return A[:nA.value].clone(), B[:nB.value].clone()
+
+    def last_plan(self):
+        ln = C.c_int64()
+        L.check(self.lib.sr_last_plan(self.h, None, 0, C.byref(ln)), "sr_last_plan")
+        buf = np.zeros(max(ln.value, 1), dtype=np.int32)
+        L.check(self.lib.sr_last_plan(self.h, _ptr(buf, C.c_int32), ln.value, C.byref(ln)),
+                "sr_last_plan")
+        flat = buf[:ln.value].tolist()
+        plan, p = [], 0
+        while p < len(flat):
+            case, op, j, dj, delta = flat[p:p + 5]
+            plan.append(dict(case=case, op=op, j=j, dj=dj, I=flat[p + 5:p + 5 + delta]))
+            p += 5 + delta
+        return plan
+
+    def backward(self, a, b, g):
+        a = torch.as_tensor(a, dtype=torch.int32, device="cuda").contiguous()
+        b = torch.as_tensor(b, dtype=torch.int32, device="cuda").contiguous()
+        g = torch.as_tensor(g, dtype=torch.float64, device="cuda").contiguous()
+        dw = torch.empty(self.m0, dtype=torch.float64, device="cuda")
+        L.check(self.lib.backward(self.h, a.numel(), _dev(a), _dev(b), _dev(g), _dev(dw)),
+                "backward")
+        return dw
+
+    def profile(self, enable=True):
+        L.check(self.lib.sr_profile(self.h, int(bool(enable))), "sr_profile")
+
+    def profile_read(self, reset=True):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        L.check(self.lib.sr_profile_read(self.h, C.byref(ms), C.byref(cnt), int(bool(reset))),
+                "sr_profile_read")
+        return ms.value, cnt.value
+
+    def synchronize(self):
+        L.check(self.lib.sr_synchronize(self.h), "sr_synchronize")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SimRankPairs(torch.autograd.Function):
+    """``S[a, b]`` for the context's graph as a function of its edge weights.
+
+    ``forward(weights, context, a, b)`` returns the pair values; ``weights`` must be the
+    (m,) tensor the context was built from. ``backward`` calls the library's adjoint and
+    returns dL/dweights.
+    """
+
+    @staticmethod
+    def forward(ctx, weights, context, a, b):
+        a = torch.as_tensor(a, dtype=torch.int32, device="cuda").contiguous()
+        b = torch.as_tensor(b, dtype=torch.int32, device="cuda").contiguous()
+        ctx.context = context
+        ctx.save_for_backward(a, b)
+        return context.gather_pairs(a, b)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        a, b = ctx.saved_tensors
+        dw = ctx.context.backward(a, b, grad_out.detach().to(torch.float64).contiguous())
+        return dw, None, None, None
+
+
+def simrank_pairs(weights, context, a, b):
+    return SimRankPairs.apply(weights, context, a, b)
+
+
+def mfma_layout_probe(a, b):
+    lib = L.load()
+    a = a.to(device="cuda", dtype=torch.float64).contiguous()
+    b = b.to(device="cuda", dtype=torch.float64).contiguous()
+    out = torch.empty(256, dtype=torch.float64, device="cuda")
+    L.check(lib.sr_mfma_layout_probe(_dev(a), _dev(b), _dev(out),
+                                     C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+            "sr_mfma_layout_probe")
+    return out

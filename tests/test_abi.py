@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every function include/simrank.h declares, and the
+ctypes structures match the C layout (sizes and offsets compiled from the header by gcc).
+No GPU work is launched."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "simrank.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", text)
+    skip = {"if", "while", "for", "switch", "return", "sizeof"}
+    decl = set()
+    for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                         text, flags=re.M):
+        if m.group(1) not in skip:
+            decl.add(m.group(1))
+    assert decl and decl <= set(names)
+    return sorted(decl)
+
+
+def lib():
+    from paper_1711_00121_amd import _lib
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported():
+    L = lib()
+    names = declared_functions()
+    assert "init_simrank" in names and "backward" in names and "apply_batch" in names
+    for name in names:
+        assert hasattr(L, name), name
+    from paper_1711_00121_amd import _lib
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_default_config_and_strerror():
+    from paper_1711_00121_amd import _lib
+    L = lib()
+    cfg = _lib.sr_config()
+    assert L.sr_default_config(ctypes.byref(cfg)) == 0
+    assert cfg.C == 0.6 and cfg.K == 15 and cfg.K_ps == 30 and cfg.prune == 1
+    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 64
+    assert L.sr_strerror(-3) == b"edge exists"
+    assert L.sr_default_config(None) == _lib.SR_EINVAL
+
+
+def test_null_context_arguments_are_rejected_without_gpu():
+    from paper_1711_00121_amd import _lib
+    L = lib()
+    assert L.apply_edge_update(None, 0, 1, 1, None) == _lib.SR_EINVAL
+    assert L.sr_destroy(None) == _lib.SR_OK
+    assert L.init_simrank(None, 10, 0, None, None, None, None, None, None) == _lib.SR_EINVAL
+
+
+def test_struct_layout_matches_header():
+    from paper_1711_00121_amd import _lib
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "simrank.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("sr_config %zu\n", sizeof(sr_config));
+  printf("sr_update_stats %zu\n", sizeof(sr_update_stats));
+  printf("sr_batch_stats %zu\n", sizeof(sr_batch_stats));
+  F(sr_config, node_cap) F(sr_config, init_tol) F(sr_config, fused_batch)
+  F(sr_update_stats, bound) F(sr_batch_stats, pairs) F(sr_batch_stats, fused_passes)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        r = subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("gcc unavailable: " + r.stderr)
+        out = subprocess.run([exe], capture_output=True, text=True).stdout.split("\n")
+    got = dict(l.split() for l in out if l.strip())
+    assert int(got["sr_config"]) == ctypes.sizeof(_lib.sr_config)
+    assert int(got["sr_update_stats"]) == ctypes.sizeof(_lib.sr_update_stats)
+    assert int(got["sr_batch_stats"]) == ctypes.sizeof(_lib.sr_batch_stats)
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(getattr(_lib, t), f).offset == int(val), key
