@@ -92,8 +92,6 @@ sr_status fail_hip(sr_ctx* c) {
     if (e__ != hipSuccess) return fail_hip(ctx); \
   } while (0)
 
-int round4(int x) { return (x + 3) / 4 * 4; }
-
 DevQ devq(const sr_ctx* c) {
   DevQ q;
   q.in.start = c->d_adj[0];
@@ -691,8 +689,9 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
       return SR_EHIP;
     }
   }
-  // one block's panel: 32 columns when it fits (the streaming kernel reads 8 per lane group)
-  ctx->pld = 2 * (cfg.K + 1) <= 32 ? 32 : round4(2 * (cfg.K + 1));
+  // one block's panel width, a multiple of 32: the streaming kernel reads 32 columns per pass
+  // (8 per lane group), and passes start at multiples of 32
+  ctx->pld = (2 * (cfg.K + 1) + 31) / 32 * 32;
   ctx->W = (int)((node_cap + 31) / 32 + 64);
   IC(dalloc(&ctx->SI, node_cap));
   IC(dalloc(&ctx->Sj, node_cap));
@@ -1068,6 +1067,8 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     if (dalloc(&ctx->Pb, ctx->node_cap * (int64_t)pld_all) != hipSuccess ||
         dalloc(&ctx->wts, 2 * (int64_t)pld_all) != hipSuccess)
       return SR_ENOMEM;
+    // padding columns of each block's segment are never written and must read as zero
+    HC(hipMemsetAsync(ctx->Pb, 0, (size_t)ctx->node_cap * pld_all * 8, ctx->stream));
   }
   int q = 0;  // deferred blocks in the current chunk
   int passes = 0;

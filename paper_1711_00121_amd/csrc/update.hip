@@ -151,9 +151,11 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
     bool rok[4], rA[4], rB[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      rok[v] = rbase + v * 4 + lk < nrows;
+      const int64_t pc = rbase + v * 4 + lk;
+      rok[v] = pc < nrows;
       const int32_t packed = cur[1 + v];
-      const int64_t rr = MASK ? (packed >> 2) : packed;
+      // column output: the output row is the position in the query list, not the node
+      const int64_t rr = COLOUT ? pc : (MASK ? (packed >> 2) : packed);
       crow[v] = rok[v] ? rr : 0;
       rA[v] = MASK ? ((packed >> 1) & 1) : true;
       rB[v] = MASK ? (packed & 1) : true;
