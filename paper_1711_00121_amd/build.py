@@ -31,6 +31,9 @@ COMMON = [
     "-Wno-unused-function",
     # keep hipcc from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs: with AGPR accumulators the fused GEMM's loop copied all
+    # 128 accumulator registers between the two files on every chunk
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,
 ]

@@ -35,6 +35,7 @@ struct sr_ctx {
   bool weighted = false;
   bool updated = false;  // graph changed since init
   int64_t node_cap = 0, edge_cap = 0, slot_cap = 0;
+  int64_t p_rows = 0;  // panel rows: node_cap rounded up to 128; rows past n stay zero
   HostGraph g;
   std::vector<int32_t> src0, dst0;  // initial edges (the order of backward's output)
   std::vector<double> w0;
@@ -422,6 +423,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   la.S = ctx->S;
   la.P = ctx->P;
   la.pld = ctx->pld;
+  la.p_rows = ctx->p_rows;
   la.r = 2 * (K + 1);
   la.ncols = n_work;
   if (prune) {
@@ -433,6 +435,9 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   } else {
     la.rows = nullptr;
     la.nrows = n_work;
+    // above 32 columns the GEMM form runs over whole 32-column chunks; the panel's columns
+    // past 2 (K + 1) are zero
+    if (la.r > 32) la.r = ctx->pld;
   }
   HC(run_lowrank(ctx, la));
   ctx->last_r = 2 * (K + 1);
@@ -700,7 +705,8 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   IC(dalloc(&ctx->Qz, node_cap));
   IC(dalloc(&ctx->zsum, node_cap));
   IC(dalloc(&ctx->ytmp, node_cap));
-  IC(dalloc(&ctx->P, node_cap * ctx->pld));
+  ctx->p_rows = (node_cap + 127) / 128 * 128;
+  IC(dalloc(&ctx->P, ctx->p_rows * ctx->pld));
   IC(dalloc(&ctx->suppI, ctx->W));
   IC(dalloc(&ctx->suppJ, ctx->W));
   IC(dalloc(&ctx->Abits, (int64_t)(cfg.K + 1) * ctx->W));
@@ -712,7 +718,7 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   IC(dalloc(&ctx->d_max, 1));
   IC(hipHostMalloc((void**)&ctx->h_cnt, 8 * sizeof(int64_t), hipHostMallocDefault));
   IC(hipHostMalloc((void**)&ctx->h_max, sizeof(unsigned long long), hipHostMallocDefault));
-  if (hipMemset(ctx->P, 0, (size_t)node_cap * ctx->pld * 8) != hipSuccess ||
+  if (hipMemset(ctx->P, 0, (size_t)ctx->p_rows * ctx->pld * 8) != hipSuccess ||
       hipMemset(ctx->Ahat, 0, (size_t)ctx->W * 4) != hipSuccess ||
       hipMemset(ctx->Bhat, 0, (size_t)ctx->W * 4) != hipSuccess ||
       hipMemset(ctx->Abits, 0, (size_t)(cfg.K + 1) * ctx->W * 4) != hipSuccess ||
@@ -1064,11 +1070,11 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   const int chunk = ctx->cfg.batch_chunk;
   const int pld_all = ctx->pld * chunk;
   if (fused && !ctx->Pb) {
-    if (dalloc(&ctx->Pb, ctx->node_cap * (int64_t)pld_all) != hipSuccess ||
+    if (dalloc(&ctx->Pb, ctx->p_rows * (int64_t)pld_all) != hipSuccess ||
         dalloc(&ctx->wts, 2 * (int64_t)pld_all) != hipSuccess)
       return SR_ENOMEM;
     // padding columns of each block's segment are never written and must read as zero
-    HC(hipMemsetAsync(ctx->Pb, 0, (size_t)ctx->node_cap * pld_all * 8, ctx->stream));
+    HC(hipMemsetAsync(ctx->Pb, 0, (size_t)ctx->p_rows * pld_all * 8, ctx->stream));
   }
   int q = 0;  // deferred blocks in the current chunk
   int passes = 0;
@@ -1078,6 +1084,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     la.S = ctx->S;
     la.P = ctx->Pb;
     la.pld = pld_all;
+    la.p_rows = ctx->p_rows;
     la.r = q * ctx->pld;
     la.rows = nullptr;
     la.nrows = n_new;
@@ -1186,6 +1193,7 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
   LowRankArgs la{};
   la.P = ctx->P;
   la.pld = ctx->pld;
+  la.p_rows = ctx->p_rows;
   la.r = ctx->last_r;
   la.rows = ctx->d_ids;
   la.nrows = ncols;

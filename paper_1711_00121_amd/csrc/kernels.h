@@ -163,6 +163,9 @@ hipError_t launch_bits_or(const uint32_t* a, const uint32_t* b, uint32_t* dst, i
 //       S[a][b] += sum_{c < r} P[a][c] * P[b][c ^ 1]
 // P rows hold (xi_k, eta_k) pairs, so the sum is sum_k xi_k[a] eta_k[b] + eta_k[a] xi_k[b].
 // For several blocks the panel holds their pairs side by side (r = 2 (K+1) * blocks).
+// With r > 32 and no row list or mask (fused passes) the update runs as a GEMM over the
+// upper triangle of 128 x 128 tiles; it then needs nrows == ncols, r a multiple of 32 and
+// p_rows >= nrows rounded up to 128, with panel rows [nrows, p_rows) zero.
 // Column-output form (out != null): out[t][b] = sum_c P[rows[t]][c] * P[b][c ^ 1] as float32
 // (row t of out at out + t * ld_out), no mask; S is not touched.
 struct LowRankArgs {
@@ -178,6 +181,7 @@ struct LowRankArgs {
   const uint32_t* Bhat;
   float* out;
   int64_t ld_out;
+  int64_t p_rows;     // rows allocated in P (rows past the written ones are zero)
 };
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
 // Fused batches: the columns S_t[:, c] of the current S are the stored S plus the deferred

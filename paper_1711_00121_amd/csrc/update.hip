@@ -3,14 +3,14 @@
 // M_K = sum_k xi_k eta_k^T (eq (16a)). Entry (a, b) receives
 //     sum_k xi_k[a] eta_k[b] + eta_k[a] xi_k[b] = sum_c P[a][c] P[b][c ^ 1]
 // with panel rows P[a] = (xi_0[a], eta_0[a], xi_1[a], eta_1[a], ...). Several blocks of a batch
-// stack their pairs along c, so the same kernel applies a rank-2(K+1)B update in one pass.
+// stack their pairs along c, so the same product applies a rank-2(K+1)B update in one pass.
 //
-// Mapping to gfx950: each 256-thread workgroup owns a 64 x 128 tile of (listed rows) x
-// (columns) and stages the tile's panel rows in LDS; each wave computes a 32 x 64 sub-tile
-// with v_mfma_f64_16x16x4_f64 (2 x 4 accumulators of 16 x 16). The wave issues its S loads
-// before the MFMA loop, so HBM latency overlaps the matrix work, then adds, re-splits (hi/lo)
-// and stores. S is read and written once per update; the kernel is bound by HBM bandwidth
-// for one block and by FP64 matrix throughput for large batches.
+// Two kernels, both on v_mfma_f64_16x16x4_f64 (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator slot v of lane l is D[4v + l/16][l%16]):
+//  - lowrank_strip_kernel, one block (r <= 32): bound by HBM. S streams through once; the
+//    S loads of the next row tile are in flight while the current tile multiplies and stores.
+//  - lowrank_gemm_kernel, fused batches (r = 32 B): bound by FP64 matrix throughput. Only
+//    the upper triangle of tiles is computed (the update is symmetric).
 #include "kernels.h"
 
 namespace sr {
@@ -31,18 +31,38 @@ __device__ __forceinline__ bool pair_in(const uint32_t* Ah, const uint32_t* Bh, 
   return (ra && cb) || (rb && ca);
 }
 
+// An S entry as loaded (no arithmetic on it until it is needed, so that the load can stay in
+// flight): FP64 value, or FP32 value and compensation.
 template <int PREC>
-__device__ __forceinline__ double sget(const SView& S, int64_t off) {
-  if (PREC == PREC_FP64) return S.d[off];
-  if (PREC == PREC_HILO) return (double)S.hi[off] + (double)S.lo[off];
-  return (double)S.hi[off];
+struct Raw {
+  double d;
+  float h, l;
+};
+
+template <int PREC>
+__device__ __forceinline__ void sload(const SView& S, int64_t off, Raw<PREC>& x) {
+  if constexpr (PREC == PREC_FP64) {
+    x.d = S.d[off];
+  } else if constexpr (PREC == PREC_HILO) {
+    x.h = S.hi[off];
+    x.l = S.lo[off];
+  } else {
+    x.h = S.hi[off];
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ double sval(const Raw<PREC>& x) {
+  if constexpr (PREC == PREC_FP64) return x.d;
+  else if constexpr (PREC == PREC_HILO) return (double)x.h + (double)x.l;
+  else return (double)x.h;
 }
 
 template <int PREC>
 __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
-  if (PREC == PREC_FP64) {
+  if constexpr (PREC == PREC_FP64) {
     S.d[off] = t;
-  } else if (PREC == PREC_HILO) {
+  } else if constexpr (PREC == PREC_HILO) {
     const float h = (float)t;
     S.hi[off] = h;
     S.lo[off] = (float)(t - (double)h);
@@ -53,9 +73,13 @@ __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
 
 // Streaming update for one block (r <= RC panel columns). Workgroup = strip of SC columns whose
 // panel rows live in LDS for the whole strip; the workgroup walks row tiles of TR listed rows,
-// wave w taking rows [16 w, 16 w + 16) of each tile against the strip's SC columns (SC / 16
-// accumulators). Per tile a wave issues its A-fragment loads and all its S loads before the
-// MFMAs, so the S latency overlaps the matrix work of this and the other resident waves.
+// wave w taking rows [16 w, 16 w + 16) of each tile against the strip's SC columns (ST
+// accumulators of 16 x 16). Per tile a wave first issues the A fragments and S loads of its
+// NEXT tile and the row-list entries of the tile after that, then runs the MFMAs and stores
+// the current tile from values loaded one iteration earlier. Each wave thus keeps a tile of
+// S loads in flight while it computes and stores, which HBM latency at full bandwidth needs;
+// and since the waits count loads in issue order, waiting for the current tile's operands
+// never waits for the next tile's.
 // Every load is unconditional from an in-bounds address (rows past the list read row 0;
 // columns past n stay inside the padded leading dimension, a multiple of SC) and selected
 // afterwards: a load under a branch is followed by a full wait and serialises the tile.
@@ -91,31 +115,31 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
       lcol[rr * LP + cc + 1] = vv[u].y;
     }
   }
-  bool cin[ST], cA[ST], cB[ST];
+  // Column flags of this lane's 16-column slices, one bit per slice t.
+  int cin = 0, cA = 0, cB = 0;
 #pragma unroll
   for (int t = 0; t < ST; ++t) {
     const int64_t b = c0 + t * 16 + l16;
-    cin[t] = b < g.ncols;
+    const int in = b < g.ncols;
+    cin |= in << t;
     if (MASK) {
-      const int64_t bb = cin[t] ? b : 0;
+      const int64_t bb = in ? b : 0;
       const uint32_t wa = g.Ahat[bb >> 5], wb = g.Bhat[bb >> 5];
-      cA[t] = (wa >> (bb & 31)) & 1u;
-      cB[t] = (wb >> (bb & 31)) & 1u;
-    } else {
-      cA[t] = cB[t] = true;
+      cA |= (int)((wa >> (bb & 31)) & 1u) << t;
+      cB |= (int)((wb >> (bb & 31)) & 1u) << t;
     }
   }
+  if (!MASK) cA = cB = (1 << ST) - 1;
   __syncthreads();
 
   const int64_t nrows = g.nrows_dev ? *g.nrows_dev : g.nrows;
   const int64_t nrt = (nrows + TR - 1) / TR;
-  const int ksteps = RC / 4;  // columns past r are zero on both sides
+  const int64_t gy = gridDim.y;
+  const int64_t last = nrows > 0 ? nrows - 1 : 0;
   // Row-list entries of a tile: [0] the A-operand row (rbase + l16), [1..4] the accumulator
-  // rows (rbase + 4 v + lk). They are fetched one tile ahead so the S addresses of a tile do
-  // not wait on a list load.
+  // rows (rbase + 4 v + lk). Positions past the list read the last entry (any in-bounds row).
   auto fetch = [&](int64_t rt, int32_t (&e)[5]) {
     const int64_t rbase = rt * TR + wave * 16;
-    const int64_t last = nrows > 0 ? nrows - 1 : 0;
     const int64_t p0 = rbase + l16;
     e[0] = HASROWS ? g.rows[p0 < nrows ? p0 : last] : (int32_t)p0;
 #pragma unroll
@@ -124,135 +148,172 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
       e[1 + v] = HASROWS ? g.rows[pc < nrows ? pc : last] : (int32_t)pc;
     }
   };
-  int32_t cur[5], nxt[5];
-  if ((int64_t)blockIdx.y < nrt) fetch(blockIdx.y, cur);
-  for (int64_t rt = blockIdx.y; rt < nrt; rt += gridDim.y) {
-    const int64_t rbase = rt * TR + wave * 16;
-    // A operand. The inner sum over panel columns is order-free, so k-step ks of lane group
-    // lk uses column 8 lk + ks (same permutation on the B side): each lane's 8 A values are
-    // contiguous. With a mask the row list holds (node << 2) | (in A_hat << 1) | in B_hat.
-    const bool pa_ok = rbase + l16 < nrows;
-    const int64_t arow = pa_ok ? ((int64_t)cur[0] >> (MASK ? 2 : 0)) : 0;
-    double av[RC / 4];
-    {
-      const double2* src = reinterpret_cast<const double2*>(g.P + arow * g.pld + 8 * lk);
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const double2 v = src[h];
-        av[2 * h] = v.x;
-        av[2 * h + 1] = v.y;
-      }
-#pragma unroll
-      for (int ks = 0; ks < RC / 4; ++ks)
-        if (!pa_ok || 8 * lk + ks >= g.r) av[ks] = 0.0;
-    }
-    // accumulator rows of this lane: rbase + 4 v + lk
-    int64_t crow[4];
-    bool rok[4], rA[4], rB[4];
+  // Output row of accumulator slot v: the node (with a mask the entry is packed as
+  // (node << 2) | (in A_hat << 1) | in B_hat), or the list position in column-output form.
+  auto out_row = [&](int64_t rt, const int32_t (&e)[5], int v) -> int64_t {
+    const int64_t pc = rt * TR + wave * 16 + v * 4 + lk;
+    const int64_t rr = COLOUT ? pc : (MASK ? ((int64_t)e[1 + v] >> 2) : (int64_t)e[1 + v]);
+    return pc < nrows ? rr : 0;
+  };
+  auto load_tile = [&](int64_t rt, const int32_t (&e)[5], Raw<PREC> (&x)[ST][4]) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t pc = rbase + v * 4 + lk;
-      rok[v] = pc < nrows;
-      const int32_t packed = cur[1 + v];
-      // column output: the output row is the position in the query list, not the node
-      const int64_t rr = COLOUT ? pc : (MASK ? (packed >> 2) : packed);
-      crow[v] = rok[v] ? rr : 0;
-      rA[v] = MASK ? ((packed >> 1) & 1) : true;
-      rB[v] = MASK ? (packed & 1) : true;
+      const int64_t base = out_row(rt, e, v) * g.S.ld + c0 + l16;
+#pragma unroll
+      for (int t = 0; t < ST; ++t) sload<PREC>(g.S, base + t * 16, x[t][v]);
     }
-    if (rt + gridDim.y < nrt) fetch(rt + gridDim.y, nxt);
-    bool on[ST][4];
+  };
+
+  // A operand of a tile: row (rbase + l16) of the panel. The inner sum over panel columns is
+  // order-free, so k-step ks of lane group lk uses column 8 lk + ks (same permutation on the
+  // B side): each lane's 8 A values are contiguous. No select is applied: positions past the
+  // list read row 0 and their output rows are never stored, and panel columns at or past r
+  // meet zeros on the B side (staged above).
+  auto load_a = [&](int64_t rt, const int32_t (&e)[5], double (&av)[RC / 4]) {
+    const int64_t p0 = rt * TR + wave * 16 + l16;
+    const int64_t arow = p0 < nrows ? ((int64_t)e[0] >> (MASK ? 2 : 0)) : 0;
+    const double2* src = reinterpret_cast<const double2*>(g.P + arow * g.pld + 8 * lk);
 #pragma unroll
-    for (int t = 0; t < ST; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        on[t][v] = rok[v] && cin[t] && ((rA[v] && cB[t]) || (rB[v] && cA[t]));
-    double old[ST][4];
-    if (!COLOUT) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t base = crow[v] * g.S.ld + c0 + l16;
-#pragma unroll
-        for (int t = 0; t < ST; ++t) old[t][v] = sget<PREC>(g.S, base + t * 16);
-      }
+    for (int h = 0; h < 4; ++h) {
+      const double2 v = src[h];
+      av[2 * h] = v.x;
+      av[2 * h + 1] = v.y;
     }
+  };
+
+  // Pipeline: iteration rt holds the entries, S values and A operand of tile rt (loaded one
+  // iteration earlier) and issues those of tile rt + gy (entries: rt + 2 gy) before its MFMAs.
+  int32_t e0[5], e1[5], e2[5];
+  Raw<PREC> x0[ST][4], x1[ST][4];
+  double a0[RC / 4], a1[RC / 4];
+  int64_t rt = blockIdx.y;
+  fetch(rt, e0);
+  if (!COLOUT) load_tile(rt, e0, x0);
+  load_a(rt, e0, a0);
+  fetch(rt + gy, e1);
+  for (; rt < nrt; rt += gy) {
+    const int64_t rbase = rt * TR + wave * 16;
+    load_a(rt + gy, e1, a1);
+    if (!COLOUT) load_tile(rt + gy, e1, x1);
+    fetch(rt + 2 * gy, e2);
     dbl4 acc[ST];
 #pragma unroll
     for (int t = 0; t < ST; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < RC / 4; ++ks) {
-      if (ks < ksteps) {
-        const int c = (8 * lk + ks) ^ 1;
+      const int c = (8 * lk + ks) ^ 1;
 #pragma unroll
-        for (int t = 0; t < ST; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], lcol[(t * 16 + l16) * LP + c],
-                                                        acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < ST; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], lcol[(t * 16 + l16) * LP + c],
+                                                      acc[t], 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      const int64_t pc = rbase + v * 4 + lk;
+      const int64_t row = out_row(rt, e0, v);
+      const int rok = pc < nrows;
+      const int rA = MASK ? ((e0[1 + v] >> 1) & 1) : 1;
+      const int rB = MASK ? (e0[1 + v] & 1) : 1;
+      // pairs in A_hat x B_hat u B_hat x A_hat, as a bit per slice
+      const int on = (rok ? cin : 0) & ((rA ? cB : 0) | (rB ? cA : 0));
 #pragma unroll
       for (int t = 0; t < ST; ++t) {
-        if (!on[t][v]) continue;
+        if (!((on >> t) & 1)) continue;
         const int64_t b = c0 + t * 16 + l16;
         if (COLOUT) {
-          g.out[crow[v] * g.ld_out + b] = (float)acc[t][v];
+          g.out[row * g.ld_out + b] = (float)acc[t][v];
         } else {
-          sput<PREC>(g.S, crow[v] * g.S.ld + b, old[t][v] + acc[t][v]);
+          sput<PREC>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) cur[q] = nxt[q];
+    for (int q = 0; q < 5; ++q) {
+      e0[q] = e1[q];
+      e1[q] = e2[q];
+    }
+#pragma unroll
+    for (int q = 0; q < RC / 4; ++q) a0[q] = a1[q];
+    if (!COLOUT) {
+#pragma unroll
+      for (int t = 0; t < ST; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x0[t][v] = x1[t][v];
+    }
   }
 }
 
-// Fused batch pass (any r, all rows and columns, no mask): S += P swap(P)^T as a GEMM with
-// inner dimension r. 128 x 128 tiles; wave (wr, wc) owns a 64 x 64 quarter (4 x 4 accumulators
-// of 16 x 16). Panel columns are staged through LDS 16 at a time, double buffered: the global
-// loads of chunk c + 1 are in flight while the MFMAs of chunk c run.
+// Fused batch pass (any r that is a multiple of GC, all rows and columns, no mask):
+// S += P swap(P)^T as a GEMM with inner dimension r. The product is symmetric
+// (sum_c P[a][c] P[b][c^1] = sum_c P[b][c] P[a][c^1]), so only tiles (I, J) with I <= J of the
+// 128 x 128 tiling are computed: a diagonal tile adds its product to S[I][I], an
+// off-diagonal tile adds it to S[I][J] and its transpose to S[J][I]. That halves the matrix
+// work and keeps S exactly symmetric. Wave (wr, wc) owns a 64 x 64 quarter (4 x 4
+// accumulators of 16 x 16). Panel columns are staged through LDS GC at a time, double
+// buffered: the global loads of chunk c + 1 are issued before the MFMAs of chunk c and land
+// in LDS after them. The global panel loads are unconditional (the panel holds zero rows up
+// to a multiple of GT and zero columns up to a multiple of GC), so the loop has no branch.
+// Workgroups are dealt to the 8 XCDs round-robin; workgroup w takes triangle tile
+// (w % 8) * per + w / 8, so each XCD walks a contiguous run of tiles (mostly one tile row)
+// and shares that row's panel in its L2.
 constexpr int GT = 128;       // tile rows = tile cols
-constexpr int GC = 16;        // panel columns per chunk
+constexpr int GC = 32;        // panel columns per chunk
 constexpr int GP = GC + 1;    // LDS pitch (doubles)
-constexpr int GL = GT * (GC / 2) / NT;  // double2 loads per thread per side per chunk (4)
+constexpr int GL = GT * (GC / 2) / NT;  // double2 loads per thread per side per chunk (8)
+constexpr int NXCD = 8;
+
+// Tile t of the upper triangle of a T x T tiling, row by row: row I holds (I, I..T-1) and
+// starts at I T - I (I - 1) / 2.
+__device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64_t& J) {
+  const double b = 2.0 * (double)T + 1.0;
+  int64_t i = (int64_t)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+  i = i < 0 ? 0 : (i > T - 1 ? T - 1 : i);
+  while (i > 0 && i * T - i * (i - 1) / 2 > t) --i;
+  while (i + 1 < T && (i + 1) * T - (i + 1) * i / 2 <= t) ++i;
+  I = i;
+  J = i + (t - (i * T - i * (i - 1) / 2));
+}
 
 template <int PREC>
-__global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g) {
+__global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
+                                                          int64_t per) {
   __shared__ double As[2][GT * GP];
   __shared__ double Bs[2][GT * GP];
+  const int64_t w = blockIdx.x;
+  const int64_t t = (w % NXCD) * per + w / NXCD;
+  if (t >= T * (T + 1) / 2) return;
+  int64_t I, J;
+  tri_tile(t, T, I, J);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int l16 = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.y * GT;
-  const int64_t c0 = (int64_t)blockIdx.x * GT;
-  const int64_t nrows = g.nrows;
-  const int nch = (g.r + GC - 1) / GC;
+  const int64_t r0 = I * GT;
+  const int64_t c0 = J * GT;
+  const int nch = g.r / GC;
 
+  // This thread stages rows (tid / 16) + 16 u, columns 2 (tid % 16) + {0, 1} of each chunk.
+  const int lrow = tid >> 4, lcol = 2 * (tid & 15);
+  const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
+  const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
+  const int64_t ustep = 16 * (int64_t)g.pld;
   double2 ra[GL], rb[GL];
   auto load = [&](int ch) {
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      const int e = tid + u * NT;
-      const int rr = e / (GC / 2), cc = ch * GC + (e % (GC / 2)) * 2;
-      const int64_t a = r0 + rr, b = c0 + rr;
-      const bool oka = a < nrows && cc < g.r, okb = b < g.ncols && cc < g.r;
-      ra[u] = *reinterpret_cast<const double2*>(g.P + (oka ? a * g.pld + cc : 0));
-      rb[u] = *reinterpret_cast<const double2*>(g.P + (okb ? b * g.pld + cc : 0));
-      if (!oka) ra[u] = make_double2(0.0, 0.0);
-      if (!okb) rb[u] = make_double2(0.0, 0.0);
+      ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + ch * GC);
+      rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + ch * GC);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      const int e = tid + u * NT;
-      const int rr = e / (GC / 2), cc = (e % (GC / 2)) * 2;
-      As[buf][rr * GP + cc] = ra[u].x;
-      As[buf][rr * GP + cc + 1] = ra[u].y;
-      Bs[buf][rr * GP + cc] = rb[u].x;
-      Bs[buf][rr * GP + cc + 1] = rb[u].y;
+      const int o = (lrow + 16 * u) * GP + lcol;
+      As[buf][o] = ra[u].x;
+      As[buf][o + 1] = ra[u].y;
+      Bs[buf][o] = rb[u].x;
+      Bs[buf][o + 1] = rb[u].y;
     }
   };
 
@@ -260,14 +321,15 @@ __global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g) {
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[s][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 4; ++q) acc[s][q] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   load(0);
   store(0);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nch) load(ch + 1);
+    // the last chunk reloads itself (uniform, harmless) so the loop body has no branch
+    load(ch + 1 < nch ? ch + 1 : ch);
 #pragma unroll
     for (int k4 = 0; k4 < GC; k4 += 4) {
       const int c = k4 + lk;
@@ -275,41 +337,61 @@ __global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) av[s] = As[buf][(wr * 64 + s * 16 + l16) * GP + c];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bv[t] = Bs[buf][(wc * 64 + t * 16 + l16) * GP + (c ^ 1)];
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[buf][(wc * 64 + q * 16 + l16) * GP + (c ^ 1)];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[t], acc[s][t], 0, 0, 0);
+        for (int q = 0; q < 4; ++q)
+          acc[s][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[q], acc[s][q], 0, 0, 0);
     }
-    if (ch + 1 < nch) store(buf ^ 1);
+    store(buf ^ 1);
     __syncthreads();
   }
 
-  // S += acc, one row sub-tile at a time (16 entries per lane), loads unconditional.
+  // S[a][b] += acc (and S[b][a] += acc off the diagonal), one row sub-tile at a time.
+  // Loads are unconditional from clamped addresses; out-of-range entries are not stored.
+  const bool mirror = I != J;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    double old[4][4];
-    bool on[4][4];
+    Raw<PREC> x[4][4];
+    int on[4][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
-        const int64_t b = c0 + wc * 64 + t * 16 + l16;
-        on[t][v] = a < nrows && b < g.ncols;
-        const double x = sget<PREC>(g.S, on[t][v] ? a * g.S.ld + b : 0);
-        old[t][v] = x;
+        const int64_t b = c0 + wc * 64 + q * 16 + l16;
+        on[q][v] = a < g.nrows && b < g.ncols;
+        sload<PREC>(g.S, on[q][v] ? a * g.S.ld + b : 0, x[q][v]);
       }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (!on[t][v]) continue;
+        if (!on[q][v]) continue;
         const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
-        const int64_t b = c0 + wc * 64 + t * 16 + l16;
-        sput<PREC>(g.S, a * g.S.ld + b, old[t][v] + acc[s][t][v]);
+        const int64_t b = c0 + wc * 64 + q * 16 + l16;
+        sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + acc[s][q][v]);
       }
+    if (mirror) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
+          const int64_t b = c0 + wc * 64 + q * 16 + l16;
+          sload<PREC>(g.S, on[q][v] ? b * g.S.ld + a : 0, x[q][v]);
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (!on[q][v]) continue;
+          const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
+          const int64_t b = c0 + wc * 64 + q * 16 + l16;
+          sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(x[q][v]) + acc[s][q][v]);
+        }
+    }
   }
 }
 
@@ -445,16 +527,22 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     }
     return hipGetLastError();
   }
-  // Several blocks: the fused GEMM (all rows and columns; rows list and mask not used).
-  if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr)
+  // Several blocks: the fused GEMM over the upper triangle of tiles (rows list and mask not
+  // used; see lowrank_gemm_kernel for what the panel must hold).
+  if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr ||
+      a.nrows != a.ncols || a.r % GC != 0 || a.pld % 2 != 0)
     return hipErrorInvalidValue;
-  dim3 grid((unsigned)((a.ncols + GT - 1) / GT), (unsigned)((a.nrows + GT - 1) / GT));
+  const int64_t T = (a.nrows + GT - 1) / GT;
+  if (a.p_rows < T * GT) return hipErrorInvalidValue;
+  const int64_t tiles = T * (T + 1) / 2;
+  const int64_t per = (tiles + NXCD - 1) / NXCD;
+  const unsigned grid = (unsigned)(per * NXCD);
   if (a.S.prec == PREC_FP64) {
-    lowrank_gemm_kernel<PREC_FP64><<<grid, NT, 0, s>>>(a);
+    lowrank_gemm_kernel<PREC_FP64><<<grid, NT, 0, s>>>(a, T, per);
   } else if (a.S.prec == PREC_HILO) {
-    lowrank_gemm_kernel<PREC_HILO><<<grid, NT, 0, s>>>(a);
+    lowrank_gemm_kernel<PREC_HILO><<<grid, NT, 0, s>>>(a, T, per);
   } else {
-    lowrank_gemm_kernel<PREC_FP32><<<grid, NT, 0, s>>>(a);
+    lowrank_gemm_kernel<PREC_FP32><<<grid, NT, 0, s>>>(a, T, per);
   }
   return hipGetLastError();
 }
