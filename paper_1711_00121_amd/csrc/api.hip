@@ -17,15 +17,12 @@ using namespace sr;
 // Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
 // process them in chunks (see graph.hip).
 struct HeavySet {
-  std::set<int32_t> rows;
-  std::vector<int32_t> list;
-  int32_t maxc = 1;
+  std::map<int32_t, int8_t> rows;  // listed row -> tier (1 medium, 2 heavy)
+  std::vector<int32_t> med, heavy;
   bool dirty = true;
-  int32_t* d_rows = nullptr;
-  int64_t cap_rows = 0;
-  double* d_partial = nullptr;
-  int64_t cap_slots = 0;
-  uint32_t* d_counter = nullptr;
+  int32_t* d_med = nullptr;
+  int32_t* d_heavy = nullptr;
+  int64_t cap_med = 0, cap_heavy = 0;
 };
 
 struct sr_ctx {
@@ -125,73 +122,73 @@ hipError_t dalloc(T** p, int64_t count) {
   return hipMalloc((void**)p, (size_t)count * sizeof(T));
 }
 
+// Records row r's tier after an edit; a change marks the set for upload.
 void heavy_touch(HeavySet& H, const SlotList& L, int32_t r) {
   const int32_t len = L.len[r];
-  const bool heavy = len > kLight;
-  const bool was = H.rows.count(r) != 0;
-  if (heavy != was) {
-    if (heavy) H.rows.insert(r); else H.rows.erase(r);
+  auto it = H.rows.find(r);
+  if (len <= kLight) {
+    if (it != H.rows.end()) {
+      H.rows.erase(it);
+      H.dirty = true;
+    }
+    return;
+  }
+  const int8_t tier = len > kMedium ? 2 : 1;
+  if (it == H.rows.end() || it->second != tier) {
+    H.rows[r] = tier;
     H.dirty = true;
   }
-  if (heavy && (len + kChunk - 1) / kChunk > H.maxc) H.dirty = true;
 }
 
 void heavy_free(HeavySet& H) {
-  (void)hipFree(H.d_rows);
-  (void)hipFree(H.d_partial);
-  (void)hipFree(H.d_counter);
-  H.d_rows = nullptr;
-  H.d_partial = nullptr;
-  H.d_counter = nullptr;
-  H.cap_rows = H.cap_slots = 0;
+  (void)hipFree(H.d_med);
+  (void)hipFree(H.d_heavy);
+  H.d_med = nullptr;
+  H.d_heavy = nullptr;
+  H.cap_med = H.cap_heavy = 0;
 }
 
-// Uploads the heavy list when it changed. Counters are zero between launches, so they can be
-// reallocated (and zeroed) whenever the list grows.
-sr_status heavy_sync(sr_ctx* ctx, HeavySet& H, const SlotList& L) {
+hipError_t upload_list(const std::vector<int32_t>& v, int32_t** d, int64_t* cap) {
+  const int64_t cnt = (int64_t)v.size();
+  if (cnt > *cap) {
+    (void)hipFree(*d);
+    *d = nullptr;
+    const int64_t c = std::max<int64_t>(64, 2 * cnt);
+    hipError_t e = hipMalloc((void**)d, (size_t)c * 4);
+    if (e != hipSuccess) return e;
+    *cap = c;
+  }
+  if (cnt) return hipMemcpy(*d, v.data(), (size_t)cnt * 4, hipMemcpyHostToDevice);
+  return hipSuccess;
+}
+
+// Uploads the medium and heavy lists when they changed.
+sr_status heavy_sync(sr_ctx* ctx, HeavySet& H) {
   if (!H.dirty) return SR_OK;
   HC(hipStreamSynchronize(ctx->stream));
-  H.list.assign(H.rows.begin(), H.rows.end());
-  int32_t maxc = 1;
-  for (int32_t r : H.list) maxc = std::max<int32_t>(maxc, (L.len[r] + kChunk - 1) / kChunk + 1);
-  H.maxc = maxc;
-  const int64_t nh = (int64_t)H.list.size();
-  if (nh > H.cap_rows) {
-    (void)hipFree(H.d_rows);
-    (void)hipFree(H.d_counter);
-    H.d_rows = nullptr;
-    H.d_counter = nullptr;
-    const int64_t cap = std::max<int64_t>(64, 2 * nh);
-    if (dalloc(&H.d_rows, cap) != hipSuccess || dalloc(&H.d_counter, cap) != hipSuccess)
-      return SR_ENOMEM;
-    HC(hipMemset(H.d_counter, 0, (size_t)cap * 4));
-    H.cap_rows = cap;
-  }
-  if (nh * maxc > H.cap_slots) {
-    (void)hipFree(H.d_partial);
-    H.d_partial = nullptr;
-    const int64_t cap = std::max<int64_t>(256, 2 * nh * maxc);
-    if (dalloc(&H.d_partial, 2 * cap) != hipSuccess) return SR_ENOMEM;
-    H.cap_slots = cap;
-  }
-  if (nh) HC(hipMemcpy(H.d_rows, H.list.data(), (size_t)nh * 4, hipMemcpyHostToDevice));
+  H.med.clear();
+  H.heavy.clear();
+  for (const auto& rt : H.rows) (rt.second == 2 ? H.heavy : H.med).push_back(rt.first);
+  hipError_t e = upload_list(H.med, &H.d_med, &H.cap_med);
+  if (e == hipSuccess) e = upload_list(H.heavy, &H.d_heavy, &H.cap_heavy);
+  if (e == hipErrorOutOfMemory) return SR_ENOMEM;
+  HC(e);
   H.dirty = false;
   return SR_OK;
 }
 
 HeavyArgs heavy_args(const HeavySet& H) {
   HeavyArgs h;
-  h.rows = H.d_rows;
-  h.nh = (int32_t)H.list.size();
-  h.maxc = H.maxc;
-  h.partial = H.d_partial;
-  h.counter = H.d_counter;
+  h.med = H.d_med;
+  h.nmed = (int32_t)H.med.size();
+  h.heavy = H.d_heavy;
+  h.nheavy = (int32_t)H.heavy.size();
   return h;
 }
 
 sr_status heavy_refresh(sr_ctx* ctx) {
-  sr_status r = heavy_sync(ctx, ctx->hin, ctx->g.in);
-  if (r == SR_OK) r = heavy_sync(ctx, ctx->hout, ctx->g.out);
+  sr_status r = heavy_sync(ctx, ctx->hin);
+  if (r == SR_OK) r = heavy_sync(ctx, ctx->hout);
   return r;
 }
 
@@ -322,12 +319,14 @@ AffArgs aff_args(const sr_ctx* c, int64_t n) {
   return a;
 }
 
-// Deferred application inside a fused batch: the block writes its (xi_k, eta_k) pairs into
-// panel columns [r_prev, r_prev + pld) of P (leading dimension pld_all), and S_t columns are
-// corrected by the r_prev deferred columns before gamma.
+// Deferred application inside a fused batch: the batch panel holds one n x pld panel per
+// deferred block, gstride doubles apart (block-major, so that the series traversal of a block
+// gathers from rows of pld doubles). A block writes its (xi_k, eta_k) pairs into panel
+// r_prev / pld, and S_t columns are corrected by the r_prev deferred columns before gamma.
 struct FusedTarget {
   double* P;
-  int pld_all;
+  int64_t gstride;
+  int pld;
   int r_prev;
 };
 
@@ -343,8 +342,8 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   const int delta = (int)I.size();
   const int64_t dj = ctx->g.in.len[j];
   const bool prune = ctx->cfg.prune != 0 && ft == nullptr;
-  double* P = ft ? ft->P + ft->r_prev : ctx->P;
-  const int pld = ft ? ft->pld_all : ctx->pld;
+  double* P = ft ? ft->P + (int64_t)(ft->r_prev / ft->pld) * ft->gstride : ctx->P;
+  const int pld = ctx->pld;
   const bool direct = (case_id == 0) && ctx->cfg.gamma_form == SR_GAMMA_DIRECT;
   hipStream_t s = ctx->stream;
   const DevQ q = devq(ctx);
@@ -364,7 +363,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   HC(launch_gather_rows(ctx->S, n_work, src_rows, 0, j, ctx->SI, ctx->Sj, ctx->suppI,
                         ctx->suppJ, s));
   if (ft && ft->r_prev > 0)
-    HC(launch_panel_correct(ft->P, ft->pld_all, ft->r_prev, n_work, src_rows, j, ctx->wts,
+    HC(launch_panel_correct(ft->P, ft->pld, ft->gstride, ft->r_prev, n_work, src_rows, j, ctx->wts,
                             ctx->SI, ctx->Sj, s));
   const AffArgs aa = aff_args(ctx, n_work);
   const int64_t W = ctx->W;
@@ -423,6 +422,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   la.S = ctx->S;
   la.P = ctx->P;
   la.pld = ctx->pld;
+  la.gstride = ctx->p_rows * ctx->pld;
   la.p_rows = ctx->p_rows;
   la.r = 2 * (K + 1);
   la.ncols = n_work;
@@ -476,7 +476,7 @@ sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_
   const IdList il = idlist(I, 0, I.size());
   HC(launch_gather_rows(ctx->S, n_work, il, 0, -1, ctx->SI, nullptr, ctx->suppI, nullptr, s));
   if (ft && ft->r_prev > 0)
-    HC(launch_panel_correct(ft->P, ft->pld_all, ft->r_prev, n_work, il, -1, ctx->wts, ctx->SI,
+    HC(launch_panel_correct(ft->P, ft->pld, ft->gstride, ft->r_prev, n_work, il, -1, ctx->wts, ctx->SI,
                             nullptr, s));
   HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n_work, ctx->SI, ctx->ytmp,
                    C / (double)I.size(), s));
@@ -730,8 +730,8 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   }
   st = upload_graph(ctx);
   for (int64_t r = 0; r < node_cap && st == SR_OK; ++r) {
-    if (ctx->g.in.len[r] > kLight) ctx->hin.rows.insert((int32_t)r);
-    if (ctx->g.out.len[r] > kLight) ctx->hout.rows.insert((int32_t)r);
+    heavy_touch(ctx->hin, ctx->g.in, (int32_t)r);
+    heavy_touch(ctx->hout, ctx->g.out, (int32_t)r);
   }
   if (st == SR_OK) st = heavy_refresh(ctx);
   if (st != SR_OK) {
@@ -1083,7 +1083,8 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     LowRankArgs la{};
     la.S = ctx->S;
     la.P = ctx->Pb;
-    la.pld = pld_all;
+    la.pld = ctx->pld;
+    la.gstride = ctx->p_rows * ctx->pld;
     la.p_rows = ctx->p_rows;
     la.r = q * ctx->pld;
     la.rows = nullptr;
@@ -1103,7 +1104,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     ctx->last_plan.push_back((int32_t)b.dj);
     ctx->last_plan.push_back((int32_t)b.I.size());
     for (int32_t i : b.I) ctx->last_plan.push_back(i);
-    FusedTarget ft{ctx->Pb, pld_all, q * ctx->pld};
+    FusedTarget ft{ctx->Pb, ctx->p_rows * ctx->pld, ctx->pld, q * ctx->pld};
     switch (b.case_id) {
       case 0:
       case 2:
@@ -1193,6 +1194,7 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
   LowRankArgs la{};
   la.P = ctx->P;
   la.pld = ctx->pld;
+  la.gstride = ctx->p_rows * ctx->pld;
   la.p_rows = ctx->p_rows;
   la.r = ctx->last_r;
   la.rows = ctx->d_ids;

@@ -5,20 +5,23 @@
 // Q[a][x] = 1/indeg(a) for an edge x -> a (section 3.1). Rows are in-lists by sink, so
 // (Q x)[a] gathers over a's in-neighbours and (Q^T x)[b] over b's out-neighbours.
 //
-// Power-law rows: a row of at most kLight entries is handled by a group of 8 lanes that
-// combine with shuffles. Longer rows ("heavy", listed by the host) are cut into chunks of
-// kChunk entries, one 256-thread workgroup per chunk; each chunk writes a partial sum and the
-// last chunk to finish (device-scope counter, no waiting) adds the partials in chunk order,
-// so results do not depend on scheduling.
+// Power-law rows, three tiers, all in 1024-thread workgroups of one launch: a row of at most
+// kLight entries is handled by a group of 8 lanes, a medium row (at most kMedium entries,
+// listed by the host) by one wave, a heavy row (listed) by a whole workgroup. Each lane takes
+// its entries 8 or 16 at a time with all loads issued together, since the traversal is bound
+// by memory latency; every row is reduced inside one workgroup in a fixed order, so there is
+// no cross-workgroup combine (whose device-scope fences write back the L2 of an XCD) and the
+// results do not depend on scheduling.
 #include "kernels.h"
 
 namespace sr {
 
 namespace {
 
-constexpr int kB = 256;
+constexpr int kB = 1024;
 constexpr int kG = 8;                   // lanes per light row
-constexpr int kRowsPerBlock = kB / kG;  // 32
+constexpr int kRowsPerBlock = kB / kG;  // 128
+constexpr int kWaves = kB / 64;         // 16: medium rows per workgroup
 
 __global__ __launch_bounds__(64) void patch_kernel(AdjPtrs t, Patch p) {
   int i = threadIdx.x;
@@ -44,102 +47,177 @@ struct Op {
   uint32_t* bout;
 };
 
-__device__ __forceinline__ bool member(const uint32_t* s0, const uint32_t* s1, int64_t x) {
-  return (s0 && bit_get(s0, x)) || (s1 && bit_get(s1, x));
-}
+// Compile-time shape of one traversal: KIND (0: y = post (base + scale Q x); 1: series step;
+// 2: y = scale Q^T x), WT (weighted graph), AFF (0: no bitmaps; 1: bout only, from b0 | b1;
+// 2: aout and bout). Every instantiation is straight-line: no load sits under a branch, so
+// no load waits for another that it does not depend on.
+template <int KIND, bool WT, int AFF>
+struct Shape {};
 
-// Accumulates the entries [p0, p1) of row `row` (list L) with stride `step` from lane `lane`.
-__device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const DevAdj& L, int st,
-                                           int p0, int p1, int lane, int step, double& v0,
-                                           double& v1, bool& fa, bool& fb) {
-  for (int p = p0 + lane; p < p1; p += step) {
-    const int64_t x = L.idx[st + p];
-    if (o.kind == 1) {
-      const double2 v = *reinterpret_cast<const double2*>(o.P + x * o.pld + 2 * o.k);
-      const double w = L.w ? L.w[st + p] : 1.0;
-      v0 += w * v.x;
-      v1 += w * v.y;
-    } else if (o.kind == 0) {
-      const double w = L.w ? L.w[st + p] : 1.0;
-      v0 += w * o.x[x];
-    } else {
-      const double qa = q.W ? L.w[st + p] / q.W[x] : 1.0 / (double)q.in.len[x];
-      v0 += qa * o.x[x];
+// Accumulates the entries [p0, p1) of the row starting at slot st of list L, lane `lane` of
+// `step` lanes. Entries are taken U at a time: the U index loads, then the U dependent
+// gathers (and bitmap words), are issued together; positions past p1 read entry p0 and are
+// masked out. A lane thus waits for two memory latencies per U entries instead of two per
+// entry.
+template <int U, int KIND, bool WT, int AFF>
+__device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const DevAdj& L,
+                                           int64_t st, int p0, int p1, int lane, int step,
+                                           double& v0, double& v1, uint32_t& fa, uint32_t& fb) {
+  for (int base = p0 + lane; base < p1; base += U * step) {
+    int32_t x[U];
+    double w[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = base + u * step;
+      ok[u] = p < p1;
+      const int64_t pc = st + (ok[u] ? p : p0);
+      x[u] = L.idx[pc];
+      w[u] = WT ? L.w[pc] : 1.0;
     }
-    if (o.aout && !fa) fa = member(o.a0, o.a1, x);
-    if (o.bout && !fb) fb = member(o.b0, o.b1, x);
+    if constexpr (KIND == 1) {
+      double2 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        v[u] = *reinterpret_cast<const double2*>(o.P + (int64_t)x[u] * o.pld + 2 * o.k);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v0 += ok[u] ? w[u] * v[u].x : 0.0;
+        v1 += ok[u] ? w[u] * v[u].y : 0.0;
+      }
+    } else if constexpr (KIND == 0) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = o.x[x[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v0 += ok[u] ? w[u] * v[u] : 0.0;
+    } else {
+      // (Q^T x)[b] = sum over out-neighbours a of Q[a][b] x[a], Q[a][b] = w / W_a or 1 / indeg(a)
+      double v[U], d[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = o.x[x[u]];
+        d[u] = WT ? q.W[x[u]] : (double)q.in.len[x[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v0 += ok[u] ? (w[u] / d[u]) * v[u] : 0.0;
+    }
+    if constexpr (AFF == 2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t wa = o.a0[x[u] >> 5] | o.a1[x[u] >> 5];
+        fa |= ok[u] ? (wa >> (x[u] & 31)) & 1u : 0u;
+      }
+    }
+    if constexpr (AFF >= 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t wb = o.b0[x[u] >> 5] | o.b1[x[u] >> 5];
+        fb |= ok[u] ? (wb >> (x[u] & 31)) & 1u : 0u;
+      }
+    }
   }
 }
 
+template <int KIND, bool WT>
 __device__ __forceinline__ void finish(const Op& o, const DevQ& q, int64_t row, int len,
-                                       double v0, double v1, bool fa, bool fb) {
-  if (o.kind == 1) {
+                                       double v0, double v1) {
+  if constexpr (KIND == 1) {
     double2 out = make_double2(0.0, 0.0);
     if (len > 0) {
-      const double inv = q.W ? 1.0 / q.W[row] : 1.0 / (double)len;
+      const double inv = WT ? 1.0 / q.W[row] : 1.0 / (double)len;
       out.x = o.sx * (v0 * inv);
       out.y = o.sy * (v1 * inv);
     }
     *reinterpret_cast<double2*>(o.P + row * o.pld + 2 * (o.k + 1)) = out;
-  } else if (o.kind == 0) {
+  } else if constexpr (KIND == 0) {
     double v = 0.0;
-    if (len > 0) v = q.W ? v0 / q.W[row] : v0 / (double)len;
+    if (len > 0) v = WT ? v0 / q.W[row] : v0 / (double)len;
     v *= o.scale;
     if (o.base) v += o.base[row];
     o.y[row] = o.post * v;
   } else {
     o.y[row] = o.scale * v0;
   }
-  if (fa) bit_set_atomic(o.aout, row);
-  if (fb) bit_set_atomic(o.bout, row);
 }
 
+template <int KIND, bool WT, int AFF>
 __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, int64_t n,
-                                                      int64_t n_light_blocks, HeavyArgs h) {
-  __shared__ double red0[kB / 64], red1[kB / 64];
-  __shared__ int redf[kB / 64];
-  __shared__ int is_last;
-  if ((int64_t)blockIdx.x < n_light_blocks) {
-    const int64_t row = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kG;
+                                                      int64_t n_light_blocks,
+                                                      int64_t n_med_blocks, HeavyArgs h) {
+  __shared__ double red0[kWaves], red1[kWaves];
+  __shared__ int redf[kWaves];
+  const int64_t bid = blockIdx.x;
+  const int lane64 = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  double v0 = 0.0, v1 = 0.0;
+  uint32_t fa = 0, fb = 0;
+  if (bid < n_light_blocks) {
+    // light rows (<= kLight entries): 8 lanes per row, one pass of 8 entries per lane
+    const int64_t row = bid * kRowsPerBlock + threadIdx.x / kG;
     const int lane = threadIdx.x % kG;
-    double v0 = 0.0, v1 = 0.0;
-    bool fa = false, fb = false;
     int len = 0;
     bool mine = false;
     if (row < n) {
       len = L.len[row];
       mine = len <= kLight;
-      if (mine) accumulate(o, q, L, L.start[row], 0, len, lane, kG, v0, v1, fa, fb);
+      if (mine)
+        accumulate<kLight / kG, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, lane, kG, v0,
+                                               v1, fa, fb);
     }
     v0 = wave_sum(v0, kG);
     v1 = wave_sum(v1, kG);
-    for (int s = kG >> 1; s > 0; s >>= 1) {
-      fa |= (bool)__shfl_xor((int)fa, s, kG);
-      fb |= (bool)__shfl_xor((int)fb, s, kG);
+    if constexpr (AFF > 0) {
+      for (int s = kG >> 1; s > 0; s >>= 1) {
+        fa |= (uint32_t)__shfl_xor((int)fa, s, kG);
+        fb |= (uint32_t)__shfl_xor((int)fb, s, kG);
+      }
     }
-    if (mine && lane == 0) finish(o, q, row, len, v0, v1, fa, fb);
+    if (mine && lane == 0) {
+      finish<KIND, WT>(o, q, row, len, v0, v1);
+      if (AFF == 2 && fa) bit_set_atomic(o.aout, row);
+      if (AFF >= 1 && fb) bit_set_atomic(o.bout, row);
+    }
     return;
   }
-  // heavy chunk
-  const int64_t hc = (int64_t)blockIdx.x - n_light_blocks;
-  const int hi = (int)(hc / h.maxc);
-  const int c = (int)(hc % h.maxc);
-  if (hi >= h.nh) return;
-  const int64_t row = h.rows[hi];
+  if (bid < n_light_blocks + n_med_blocks) {
+    // medium rows (kLight < len <= kMedium): one wave per row, 16 entries per lane per pass
+    const int64_t mi = (bid - n_light_blocks) * kWaves + wid;
+    if (mi >= h.nmed) return;
+    const int64_t row = h.med[mi];
+    const int len = L.len[row];
+    // (8 at a time with bitmaps, which would otherwise spill registers)
+    accumulate<AFF == 2 ? 8 : 16, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, lane64, 64,
+                                                 v0, v1, fa, fb);
+    v0 = wave_sum(v0, 64);
+    v1 = wave_sum(v1, 64);
+    if constexpr (AFF > 0) {
+      for (int s = 32; s > 0; s >>= 1) {
+        fa |= (uint32_t)__shfl_xor((int)fa, s, 64);
+        fb |= (uint32_t)__shfl_xor((int)fb, s, 64);
+      }
+    }
+    if (lane64 == 0) {
+      finish<KIND, WT>(o, q, row, len, v0, v1);
+      if (AFF == 2 && fa) bit_set_atomic(o.aout, row);
+      if (AFF >= 1 && fb) bit_set_atomic(o.bout, row);
+    }
+    return;
+  }
+  // heavy row (len > kMedium): the whole workgroup, 8 entries per thread per pass, then a
+  // fixed-order reduction (shuffles, then the wave sums in order)
+  const int64_t hi = bid - n_light_blocks - n_med_blocks;
+  if (hi >= h.nheavy) return;
+  const int64_t row = h.heavy[hi];
   const int len = L.len[row];
-  const int nch = (len + kChunk - 1) / kChunk;
-  if (c >= nch) return;
-  double v0 = 0.0, v1 = 0.0;
-  bool fa = false, fb = false;
-  const int p0 = c * kChunk;
-  const int p1 = min(len, p0 + kChunk);
-  accumulate(o, q, L, L.start[row], p0, p1, threadIdx.x, kB, v0, v1, fa, fb);
+  accumulate<8, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, threadIdx.x, kB, v0, v1, fa, fb);
   v0 = wave_sum(v0, 64);
   v1 = wave_sum(v1, 64);
   int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
-  for (int sh = 32; sh > 0; sh >>= 1) fw |= __shfl_xor(fw, sh, 64);
-  const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
+  if constexpr (AFF > 0) {
+    for (int sh = 32; sh > 0; sh >>= 1) fw |= __shfl_xor(fw, sh, 64);
+  }
+  if (lane64 == 0) {
     red0[wid] = v0;
     red1[wid] = v1;
     redf[wid] = fw;
@@ -148,41 +226,43 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
   if (threadIdx.x == 0) {
     double s0 = 0.0, s1 = 0.0;
     int ff = 0;
-    for (int w = 0; w < kB / 64; ++w) {
+    for (int w = 0; w < kWaves; ++w) {
       s0 += red0[w];
       s1 += red1[w];
       ff |= redf[w];
     }
-    double* part = h.partial + 2 * ((int64_t)hi * h.maxc + c);
-    part[0] = s0;
-    part[1] = s1;
-    if ((ff & 1) && o.aout) bit_set_atomic(o.aout, row);
-    if ((ff & 2) && o.bout) bit_set_atomic(o.bout, row);
-    __threadfence();
-    const unsigned prev = atomicAdd(h.counter + hi, 1u);
-    is_last = (prev == (unsigned)(nch - 1));
+    finish<KIND, WT>(o, q, row, len, s0, s1);
+    if (AFF == 2 && (ff & 1)) bit_set_atomic(o.aout, row);
+    if (AFF >= 1 && (ff & 2)) bit_set_atomic(o.bout, row);
   }
-  __syncthreads();
-  if (is_last && threadIdx.x == 0) {
-    __threadfence();
-    double s0 = 0.0, s1 = 0.0;
-    for (int cc = 0; cc < nch; ++cc) {
-      const double* part = h.partial + 2 * ((int64_t)hi * h.maxc + cc);
-      s0 += __hip_atomic_load(part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s1 += __hip_atomic_load(part + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    finish(o, q, row, len, s0, s1, false, false);
-    h.counter[hi] = 0u;
-  }
+}
+
+template <int KIND, bool WT, int AFF>
+hipError_t run_shape(const Op& o, const DevQ& q, const DevAdj& L, int64_t n,
+                     const HeavyArgs& h, hipStream_t s) {
+  const int64_t nlb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int64_t nmb = ((int64_t)h.nmed + kWaves - 1) / kWaves;
+  const int64_t grid = nlb + nmb + (int64_t)h.nheavy;
+  traverse_kernel<KIND, WT, AFF><<<(unsigned)grid, kB, 0, s>>>(o, q, L, n, nlb, nmb, h);
+  return hipGetLastError();
 }
 
 hipError_t run(const Op& o, const DevQ& q, const DevAdj& L, int64_t n, const HeavyArgs& h,
                hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t nlb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-  const int64_t grid = nlb + (int64_t)h.nh * h.maxc;
-  traverse_kernel<<<(unsigned)grid, kB, 0, s>>>(o, q, L, n, nlb, h);
-  return hipGetLastError();
+  const bool wt = q.W != nullptr;
+  // bitmaps: every set used is non-null (an absent second set is passed as the first)
+  if (o.kind == 0) {
+    if (o.bout)
+      return wt ? run_shape<0, true, 1>(o, q, L, n, h, s) : run_shape<0, false, 1>(o, q, L, n, h, s);
+    return wt ? run_shape<0, true, 0>(o, q, L, n, h, s) : run_shape<0, false, 0>(o, q, L, n, h, s);
+  }
+  if (o.kind == 1) {
+    if (o.aout)
+      return wt ? run_shape<1, true, 2>(o, q, L, n, h, s) : run_shape<1, false, 2>(o, q, L, n, h, s);
+    return wt ? run_shape<1, true, 0>(o, q, L, n, h, s) : run_shape<1, false, 0>(o, q, L, n, h, s);
+  }
+  return wt ? run_shape<2, true, 0>(o, q, L, n, h, s) : run_shape<2, false, 0>(o, q, L, n, h, s);
 }
 
 Op blank() {
@@ -213,6 +293,7 @@ hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const dou
   o.base = base;
   o.post = post;
   o.b0 = fin;
+  o.b1 = fin;
   o.bout = fout;
   return run(o, q, q.in, n, h, s);
 }
@@ -238,10 +319,10 @@ hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, doub
   o.sy = sy;
   if (aff) {
     o.a0 = aff->a0;
-    o.a1 = aff->a1;
+    o.a1 = aff->a1 ? aff->a1 : aff->a0;
     o.aout = aff->aout;
     o.b0 = aff->b0;
-    o.b1 = aff->b1;
+    o.b1 = aff->b1 ? aff->b1 : aff->b0;
     o.bout = aff->bout;
   }
   return run(o, q, q.in, n, h, s);

@@ -31,16 +31,15 @@ struct IdList {
 };
 
 // ---------------------------------------------------------------------------------------
-// Sparse traversals. Rows with more than kLight entries are "heavy": the host lists them and
-// they are processed in chunks of kChunk entries by whole workgroups.
-constexpr int kLight = 256;
-constexpr int kChunk = 4096;
+// Sparse traversals. Rows with more than kLight entries are listed by the host: "medium"
+// rows (at most kMedium entries) are handled by one wave each, "heavy" rows by a workgroup.
+constexpr int kLight = 64;
+constexpr int kMedium = 2048;
 struct HeavyArgs {
-  const int32_t* rows;  // heavy row ids (device), nh of them
-  int32_t nh;
-  int32_t maxc;         // chunk slots per heavy row (>= ceil(len / kChunk) for every row)
-  double* partial;      // 2 * nh * maxc doubles
-  uint32_t* counter;    // nh counters; zero between launches
+  const int32_t* med;    // medium row ids (device), ascending
+  int32_t nmed;
+  const int32_t* heavy;  // heavy row ids (device), ascending
+  int32_t nheavy;
 };
 // Pull form of one affected-area level (Theorem 4): out bit b is set when some in-neighbour x
 // of b (new graph) has (s0 | s1)(x). Null sets are empty.
@@ -164,7 +163,7 @@ hipError_t launch_bits_or(const uint32_t* a, const uint32_t* b, uint32_t* dst, i
 // P rows hold (xi_k, eta_k) pairs, so the sum is sum_k xi_k[a] eta_k[b] + eta_k[a] xi_k[b].
 // For several blocks the panel holds their pairs side by side (r = 2 (K+1) * blocks).
 // With r > 32 and no row list or mask (fused passes) the update runs as a GEMM over the
-// upper triangle of 128 x 128 tiles; it then needs nrows == ncols, r a multiple of 32 and
+// upper triangle of 128 x 128 tiles; it then needs nrows == ncols, r and pld multiples of 32,
 // p_rows >= nrows rounded up to 128, with panel rows [nrows, p_rows) zero.
 // Column-output form (out != null): out[t][b] = sum_c P[rows[t]][c] * P[b][c ^ 1] as float32
 // (row t of out at out + t * ld_out), no mask; S is not touched.
@@ -182,14 +181,18 @@ struct LowRankArgs {
   float* out;
   int64_t ld_out;
   int64_t p_rows;     // rows allocated in P (rows past the written ones are zero)
+  int64_t gstride;    // doubles between consecutive groups of pld columns (block-major
+                      // batch panel); column c of row a is at (c / pld) gstride + a pld + c % pld
 };
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
 // Fused batches: the columns S_t[:, c] of the current S are the stored S plus the deferred
 // blocks' terms sum_{col < r} P[:, col] P[c, col ^ 1]. wts[col] = sum_{i in I} P[i][col ^ 1]
 // and wts[r + col] = P[j][col ^ 1] (j < 0: no second vector), then
 // SI[a] += sum_col P[a][col] wts[col] (when I nonempty), Sj[a] += sum_col P[a][col] wts[r+col].
-hipError_t launch_panel_correct(const double* P, int pld, int r, int64_t n, const IdList& I,
-                                int32_t j, double* wts, double* SI, double* Sj, hipStream_t s);
+// P is block-major: column col of row a at (col / pld) gstride + a pld + col % pld.
+hipError_t launch_panel_correct(const double* P, int pld, int64_t gstride, int r, int64_t n,
+                                const IdList& I, int32_t j, double* wts, double* SI,
+                                double* Sj, hipStream_t s);
 // Plain reference form of the same update (one thread per entry, no MFMA), for checks.
 hipError_t launch_lowrank_ref(const LowRankArgs& a, hipStream_t s);
 // out[a] = sum_{c < r} P[a][c] * P[x][c ^ 1] for a < n (Delta S[:, x], eq (71)), float64.

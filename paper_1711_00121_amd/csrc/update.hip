@@ -253,13 +253,19 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
 // buffered: the global loads of chunk c + 1 are issued before the MFMAs of chunk c and land
 // in LDS after them. The global panel loads are unconditional (the panel holds zero rows up
 // to a multiple of GT and zero columns up to a multiple of GC), so the loop has no branch.
+// Two workgroups share a CU (74 KB of LDS and at most 256 registers each), so one
+// workgroup's barrier and LDS staging overlap the other's MFMAs.
 // Workgroups are dealt to the 8 XCDs round-robin; workgroup w takes triangle tile
 // (w % 8) * per + w / 8, so each XCD walks a contiguous run of tiles (mostly one tile row)
 // and shares that row's panel in its L2.
 constexpr int GT = 128;       // tile rows = tile cols
-constexpr int GC = 32;        // panel columns per chunk
-constexpr int GP = GC + 1;    // LDS pitch (doubles)
-constexpr int GL = GT * (GC / 2) / NT;  // double2 loads per thread per side per chunk (8)
+constexpr int GC = 16;        // panel columns per chunk
+// LDS pitch in doubles. A wave reads 16 rows x 4 columns per operand; with 64 four-byte banks
+// a half-wave (16 rows x 2 columns) touches 32 distinct doubles when 18 * row mod 32 spreads
+// the rows over the even double slots, so the reads are free of bank conflicts.
+constexpr int GP = 18;
+constexpr int GL = GT * (GC / 2) / NT;  // double2 loads per thread per side per chunk (4)
+constexpr int GR = NT / (GC / 2);       // rows staged per load round (32)
 constexpr int NXCD = 8;
 
 // Tile t of the upper triangle of a T x T tiling, row by row: row I holds (I, I..T-1) and
@@ -275,7 +281,7 @@ __device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64
 }
 
 template <int PREC>
-__global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
+__global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
                                                           int64_t per) {
   __shared__ double As[2][GT * GP];
   __shared__ double Bs[2][GT * GP];
@@ -293,23 +299,25 @@ __global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g, int64_t
   const int64_t c0 = J * GT;
   const int nch = g.r / GC;
 
-  // This thread stages rows (tid / 16) + 16 u, columns 2 (tid % 16) + {0, 1} of each chunk.
-  const int lrow = tid >> 4, lcol = 2 * (tid & 15);
+  // This thread stages rows lrow + GR u, columns lcol + {0, 1} of each chunk.
+  const int lrow = tid / (GC / 2), lcol = 2 * (tid % (GC / 2));
   const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
   const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
-  const int64_t ustep = 16 * (int64_t)g.pld;
+  const int64_t ustep = GR * (int64_t)g.pld;
   double2 ra[GL], rb[GL];
   auto load = [&](int ch) {
+    // chunk ch: columns [ch GC, ch GC + GC) lie in column group (ch GC) / pld
+    const int64_t cb = (int64_t)((ch * GC) / g.pld) * g.gstride + (ch * GC) % g.pld;
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + ch * GC);
-      rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + ch * GC);
+      ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
+      rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      const int o = (lrow + 16 * u) * GP + lcol;
+      const int o = (lrow + GR * u) * GP + lcol;
       As[buf][o] = ra[u].x;
       As[buf][o + 1] = ra[u].y;
       Bs[buf][o] = rb[u].x;
@@ -344,6 +352,8 @@ __global__ __launch_bounds__(NT) void lowrank_gemm_kernel(LowRankArgs g, int64_t
         for (int q = 0; q < 4; ++q)
           acc[s][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[q], acc[s][q], 0, 0, 0);
     }
+    // keep the staging stores (and their wait for the global loads) after the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
     store(buf ^ 1);
     __syncthreads();
   }
@@ -427,19 +437,21 @@ __global__ __launch_bounds__(256) void delta_col_kernel(const double* __restrict
 }
 
 __global__ __launch_bounds__(256) void panel_weights_kernel(const double* __restrict__ P, int pld,
-                                                           int r, IdList I, int32_t j,
-                                                           double* __restrict__ wts) {
+                                                           int64_t gstride, int r, IdList I,
+                                                           int32_t j, double* __restrict__ wts) {
   const int col = blockIdx.x * 256 + threadIdx.x;
   if (col >= r) return;
+  const int cs = col ^ 1;
+  const double* base = P + (int64_t)(cs / pld) * gstride + cs % pld;
   double w = 0.0;
-  for (int t = 0; t < I.count; ++t) w += P[(int64_t)I.id[t] * pld + (col ^ 1)];
+  for (int t = 0; t < I.count; ++t) w += base[(int64_t)I.id[t] * pld];
   wts[col] = w;
-  wts[r + col] = j >= 0 ? P[(int64_t)j * pld + (col ^ 1)] : 0.0;
+  wts[r + col] = j >= 0 ? base[(int64_t)j * pld] : 0.0;
 }
 
 // One wave per row: lanes stride over the row's r panel entries (contiguous), then reduce.
 __global__ __launch_bounds__(256) void panel_gemv_kernel(const double* __restrict__ P, int pld,
-                                                         int r, int64_t n,
+                                                         int64_t gstride, int r, int64_t n,
                                                          const double* __restrict__ wts,
                                                          double* __restrict__ SI,
                                                          double* __restrict__ Sj) {
@@ -449,7 +461,7 @@ __global__ __launch_bounds__(256) void panel_gemv_kernel(const double* __restric
   const double* row = P + a * pld;
   double s0 = 0.0, s1 = 0.0;
   for (int col = lane; col < r; col += 64) {
-    const double p = row[col];
+    const double p = row[(int64_t)(col / pld) * gstride + col % pld];
     s0 += p * wts[col];
     s1 += p * wts[r + col];
   }
@@ -463,13 +475,15 @@ __global__ __launch_bounds__(256) void panel_gemv_kernel(const double* __restric
 
 }  // namespace
 
-hipError_t launch_panel_correct(const double* P, int pld, int r, int64_t n, const IdList& I,
-                                int32_t j, double* wts, double* SI, double* Sj, hipStream_t s) {
+hipError_t launch_panel_correct(const double* P, int pld, int64_t gstride, int r, int64_t n,
+                                const IdList& I, int32_t j, double* wts, double* SI,
+                                double* Sj, hipStream_t s) {
   if (r <= 0 || n <= 0) return hipSuccess;
-  panel_weights_kernel<<<(unsigned)((r + 255) / 256), 256, 0, s>>>(P, pld, r, I, j, wts);
+  panel_weights_kernel<<<(unsigned)((r + 255) / 256), 256, 0, s>>>(P, pld, gstride, r, I, j,
+                                                                    wts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  panel_gemv_kernel<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(P, pld, r, n, wts,
+  panel_gemv_kernel<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(P, pld, gstride, r, n, wts,
                                                             I.count ? SI : nullptr,
                                                             j >= 0 ? Sj : nullptr);
   return hipGetLastError();
@@ -530,7 +544,7 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   // Several blocks: the fused GEMM over the upper triangle of tiles (rows list and mask not
   // used; see lowrank_gemm_kernel for what the panel must hold).
   if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr ||
-      a.nrows != a.ncols || a.r % GC != 0 || a.pld % 2 != 0)
+      a.nrows != a.ncols || a.r % GC != 0 || a.pld % GC != 0)
     return hipErrorInvalidValue;
   const int64_t T = (a.nrows + GT - 1) / GT;
   if (a.p_rows < T * GT) return hipErrorInvalidValue;
