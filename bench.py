@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of incremental all-pairs SimRank on one MI355X.
 
-Workload (default): directed Chung-Lu graph n = 50,000, m = 1,000,000 (exponent 2.1),
-C = 0.6, K = 15, S stored as float32 value + float32 compensation (updates in float64);
-one step = one batch of edge updates (sizes uniform in 1..4096; 40% new source, 20% new
-sink, 10% both new, 30% between existing nodes; 25% of edges share a sink), applied by the
-batch algorithm with deferred low-rank blocks and one fused pass over S per chunk.
+Default workload (--workload batch): directed Chung-Lu graph n = 50,000, m = 1,000,000
+(exponent 2.1), C = 0.6, K = 15, S stored as float32 value + float32 compensation (updates
+in float64); one step = one batch of edge updates (sizes uniform in 1..4096; 40% new
+source, 20% new sink, 10% both new, 30% between existing nodes; 25% of edges share a sink),
+applied by the batch algorithm with deferred low-rank blocks and fused passes over S.
 
 Prints one JSON line: value = Delta S pair-updates/s (S entries updated per low-rank block,
 summed, over wall time), plus edge updates/s, the plain per-edge GPU path on the same GPU and
-accuracy, the roofline of the dominant kernel (live HIP events) and the oracle timed on the
-host CPU.
+accuracy, the roofline of the dominant kernel (HIP events on the library's stream) and the
+oracle timed on the host CPU.
+
+The other workloads of the method are measured the same way with --workload:
+  stream   n = 20k, m = 200k, 1,000 single-edge updates (70% insert), pruned, K = 15
+  columns  n = 1M, m = 10M, column-by-column mode (no stored S), K = 10, PartialSim depth
+           30; per insertion 65,536 Delta S columns in blocks of 8,192, float32 output
+  adjoint  n = 20k, m = 200k weighted (lognormal(0, 0.5)), dL/dw of a loss over 4,096 pairs
 """
 import argparse
 import json
@@ -24,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("ΔS pair-updates/s + edge updates/s at n=50k vs plain GPU path; % HBM peak")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+C = 0.6
 
 
 def log(*a):
@@ -35,8 +42,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=50_000)
-    ap.add_argument("--m", type=int, default=1_000_000)
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "stream", "columns", "adjoint"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--max-batch", type=int, default=4096)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-fused", action="store_true")
@@ -52,7 +61,33 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    import torch
+    torch.cuda.set_device(0)
+    run = {"batch": run_batch, "stream": run_stream, "columns": run_columns,
+           "adjoint": run_adjoint}[args.workload]
+    print(json.dumps(run(args)), flush=True)
 
+
+def common(args, cfg, value, unit, dt, steps, dtype="f64", extra_cfg=None):
+    c = {"workload": cfg["name"], "n": args.n or cfg["n"], "m": args.m or cfg["m"],
+         "C": cfg["C"], "K": cfg["K"], "parallelism": "single GPU"}
+    c.update(extra_cfg or {})
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * dt / max(steps, 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": c}
+
+
+def hbm_roof(bytes_, ms, kernel, launches, algorithmic):
+    gbs = bytes_ / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic(kernel), "kernel": kernel,
+            "launches": launches, "avg_ms": round(ms / max(launches, 1), 3),
+            "algorithmic": algorithmic}
+
+
+# ------------------------------------------------------------------------------ batch
+def run_batch(args):
     import numpy as np
     import torch
 
@@ -60,12 +95,11 @@ def main():
     from paper_1711_00121_amd import Context
 
     cfg = W.WORKLOADS[3]
-    n, m, C, K = args.n, args.m, cfg["C"], cfg["K"]
+    n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
     nb = args.warmup + args.steps + 1
     log(f"bench: generating Chung-Lu n={n} m={m} and {nb} batches")
     s, d = W.chung_lu(n, m, seed=1003)
     batches, counts = W.batch_stream(n, s, d, nb, args.max_batch, seed=2003)
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     ctx = Context(n, s, d, C=C, K=K, s_prec="hilo", node_cap=counts[-1] + 64,
                   edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
@@ -81,10 +115,7 @@ def main():
 
     ctx.profile(True)
     ctx.profile_read(reset=True)
-    edges = 0
-    pairs = 0
-    lowrank = 0
-    passes = 0
+    edges = pairs = lowrank = passes = 0
     n_nodes = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -104,42 +135,36 @@ def main():
     ctx.profile(False)
 
     # Plain GPU path: the next batch's edges between existing nodes, one apply_edge_update each
-    # (pruned single-edge update, same precision).
+    # (pruned single-edge update, same precision), keeping edges whose net effect in the batch
+    # is this single operation.
+    from collections import Counter
     bi, bj, bo = batches[args.warmup + args.steps]
     cur_n = ctx.sizes()[0]
-    plain = [(int(a), int(b), int(o)) for a, b, o in zip(bi, bj, bo) if a < cur_n and b < cur_n]
-    seen = set()
-    sample = []
-    for a, b, o in plain:
-        if (a, b) in seen:
-            continue
-        seen.add((a, b))
-        sample.append((a, b, o))
-    # keep only edges whose net effect in the batch is this single op
-    from collections import Counter
     cnt = Counter((int(a), int(b)) for a, b in zip(bi, bj))
-    sample = [e for e in sample if cnt[(e[0], e[1])] == 1][:args.plain_edges]
+    sample, seen = [], set()
+    for a, b, o in zip(bi.tolist(), bj.tolist(), bo.tolist()):
+        if a < cur_n and b < cur_n and (a, b) not in seen and cnt[(a, b)] == 1:
+            seen.add((a, b))
+            sample.append((a, b, o))
+    sample = sample[:args.plain_edges]
     ctx.profile(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plain_pairs = 0
     for a, b, o in sample:
-        st = ctx.apply_edge_update(a, b, o, stats=True)
-        plain_pairs += st["pairs"]
+        plain_pairs += ctx.apply_edge_update(a, b, o, stats=True)["pairs"]
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t1
     plain_ms, plain_launches = ctx.profile_read(reset=True)
     ctx.profile(False)
 
-    value = pairs / dt
     edge_rate = edges / dt
     plain_edge_rate = len(sample) / dt_plain if sample else None
-    plain_pair_rate = plain_pairs / dt_plain if sample else None
     nf = float(np.mean(n_nodes))
     pld = 2 * (K + 1)
     if passes:
-        # fused pass: Delta S is symmetric, so the method's work per low-rank block is its
-        # n (n + 1) / 2 distinct entries at 2 (K + 1) multiply-adds each
+        # Delta S is symmetric: the method's work per low-rank block is its n (n + 1) / 2
+        # distinct entries at 2 (K + 1) multiply-adds each
         flops = nf * (nf + 1.0) * pld * lowrank
         achieved = flops / (kern_ms / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
@@ -147,59 +172,204 @@ def main():
                 "traffic": traffic("lowrank_gemm_kernel"),
                 "kernel": "lowrank_gemm_kernel (fused batch pass)",
                 "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
-                "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank block"}
+                "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
+                               "block"}
     else:
-        achieved = 16.0 * pairs / (kern_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic("lowrank_strip_kernel"),
-                "kernel": "lowrank_strip_kernel", "launches": launches,
-                "avg_ms": round(kern_ms / max(launches, 1), 3),
-                "algorithmic": "16 B per pair-update (S value + compensation, read + write)"}
+        roof = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
+                        "16 B per pair-update (S value + compensation, read + write)")
     plain_roof = None
     if sample:
-        gbs = 16.0 * plain_pairs / (plain_ms / 1e3) / 1e9
-        plain_roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                      "kernel": "lowrank_strip_kernel", "avg_ms": round(
-                          plain_ms / max(plain_launches, 1), 3)}
-
+        plain_roof = hbm_roof(16.0 * plain_pairs, plain_ms, "lowrank_strip_kernel",
+                              plain_launches,
+                              "16 B per pair-update (S value + compensation, read + write)")
     cpu = None
     if not args.no_cpu_baseline:
-        applied = list(zip(batches[:args.warmup + args.steps],
-                           counts[:args.warmup + args.steps]))
-        cpu = cpu_baseline(n, s, d, applied, args.cpu_seconds)
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "pair-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": cfg["name"], "n": n, "m": m, "C": C, "K": K,
-                   "s_store": "f32 value + f32 compensation", "max_batch": args.max_batch,
-                   "batch_chunk": args.chunk, "fused": not args.no_fused,
-                   "parallelism": "single GPU"},
-        "edge_updates_per_s": edge_rate,
-        "edges": edges,
-        "lowrank_blocks": lowrank,
+        applied = list(zip(batches[:args.warmup + args.steps], counts[:args.warmup + args.steps]))
+        cpu = cpu_baseline_columns(*graph_after(n, s, d, applied), args.cpu_seconds,
+                                   "the graph after the timed batches")
+    out = common(args, cfg, pairs / dt, "pair-updates/s", dt, args.steps,
+                 extra_cfg={"s_store": "f32 value + f32 compensation",
+                            "max_batch": args.max_batch, "batch_chunk": args.chunk,
+                            "fused": not args.no_fused})
+    out.update({
+        "edge_updates_per_s": edge_rate, "edges": edges, "lowrank_blocks": lowrank,
         "fused_passes": passes,
         "plain_gpu": {"edges": len(sample), "edge_updates_per_s": plain_edge_rate,
-                      "pair_updates_per_s": plain_pair_rate, "roofline": plain_roof},
+                      "pair_updates_per_s": plain_pairs / dt_plain if sample else None,
+                      "roofline": plain_roof},
         "speedup_edges_vs_plain": (edge_rate / plain_edge_rate) if plain_edge_rate else None,
         "roofline": roof,
+        "hbm_rmw_ceiling_gbs": rmw_ceiling(),
         "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    })
+    return out
 
 
+# ------------------------------------------------------------------------------ stream
+def run_stream(args):
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context
+
+    cfg = W.WORKLOADS[2]
+    n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
+    log(f"bench: generating Chung-Lu n={n} m={m} and {cfg['updates']} updates")
+    s, d = W.chung_lu(n, m, seed=1002)
+    oi, oj, oo = W.mixed_stream(n, s, d, cfg["updates"], cfg["p_insert"], seed=2002)
+    ctx = Context(n, s, d, C=C, K=K, s_prec="hilo", prune=True)
+    torch.cuda.synchronize()
+    stream = list(zip(oi.tolist(), oj.tolist(), oo.tolist()))
+    wu = min(args.warmup * 10, len(stream) // 10)
+    for i, j, op in stream[:wu]:
+        ctx.apply_edge_update(i, j, op)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    pairs = 0
+    t0 = time.perf_counter()
+    for t, (i, j, op) in enumerate(stream[wu:]):
+        pairs += ctx.apply_edge_update(i, j, op, stats=True)["pairs"]
+        if (t + 1) % 250 == 0:
+            log(f"bench: {t + 1} updates")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    done = len(stream) - wu
+    out = common(args, cfg, pairs / dt, "pair-updates/s", dt, done,
+                 extra_cfg={"s_store": "f32 value + f32 compensation", "prune": True,
+                            "updates": done, "p_insert": cfg["p_insert"]})
+    out["edge_updates_per_s"] = done / dt
+    out["mean_pairs_per_update"] = pairs / done
+    out["roofline"] = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
+                               "16 B per pair-update (S value + compensation, read + write)")
+    out["hbm_rmw_ceiling_gbs"] = rmw_ceiling()
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        fs, fd = final_edges(s, d, stream)
+        out["cpu_baseline"] = cpu_baseline_columns(n, fs, fd, args.cpu_seconds,
+                                                   "the graph after the stream")
+    return out
+
+
+# ------------------------------------------------------------------------------ columns
+def run_columns(args):
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context
+
+    cfg = W.WORKLOADS[4]
+    n, m, K, Kps = args.n or cfg["n"], args.m or cfg["m"], cfg["K"], cfg["K_ps"]
+    steps = args.steps
+    log(f"bench: generating Chung-Lu n={n} m={m}")
+    s, d = W.chung_lu(n, m, seed=1004)
+    ii, jj = W.insertion_stream(n, s, d, args.warmup + steps, seed=2004)
+    cols = W.column_sample(n, cfg["columns"], seed=3004)[:cfg["columns"]]
+    blocks = [cols[b:b + cfg["block"]] for b in range(0, len(cols), cfg["block"])]
+    ctx = Context(n, s, d, C=C, K=K, K_ps=Kps, mode="column",
+                  edge_cap=m + args.warmup + steps + 1024)
+    out_buf = torch.empty((cfg["block"], n), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    def one(t):
+        ctx.apply_edge_update(int(ii[t]), int(jj[t]), 1)
+        for blk in blocks:
+            ctx.query_columns(blk, out=out_buf[:len(blk)])
+
+    for t in range(args.warmup):
+        one(t)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for t in range(args.warmup, args.warmup + steps):
+        one(t)
+        log(f"bench: insertion {t - args.warmup + 1}/{steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    values = float(n) * len(cols) * steps
+    out = common(args, cfg, values / dt, "pair-values/s", dt, steps,
+                 extra_cfg={"K_ps": Kps, "columns": len(cols), "block": cfg["block"],
+                            "output": "float32"})
+    out["metric"] = "ΔS column values/s, column-by-column mode (no stored S)"
+    out["columns_per_s"] = len(cols) * steps / dt
+    out["roofline"] = hbm_roof(4.0 * values, kern_ms, "lowrank_strip_kernel (column output)",
+                               launches, "4 B written per output value")
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_delta_columns(n, s, d, int(ii[0]), int(jj[0]), cols,
+                                                         K, Kps, args.cpu_seconds)
+    return out
+
+
+# ------------------------------------------------------------------------------ adjoint
+def run_adjoint(args):
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context
+
+    cfg = W.WORKLOADS[5]
+    n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
+    log(f"bench: generating weighted Chung-Lu n={n} m={m}")
+    s, d = W.chung_lu(n, m, seed=1005)
+    w = W.lognormal_weights(m, seed=3005)
+    a, b, tgt = W.loss_pairs(n, cfg["pairs"], seed=3105)
+    ctx = Context(n, s, d, weight=w, C=C, K=K, s_prec="fp64")
+    at = torch.as_tensor(a, device="cuda")
+    bt = torch.as_tensor(b, device="cuda")
+    tt = torch.as_tensor(tgt, device="cuda")
+
+    def step():
+        vals = ctx.gather_pairs(at, bt)
+        return ctx.backward(at, bt, 2.0 * (vals - tt))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    # Plain path to the same gradient: one incremental unit update per edge (its first-order
+    # part is the directional derivative), timed on a few insertions into an unweighted
+    # context of the same graph at the same accuracy.
+    plain = Context(n, s, d, C=C, K=K, s_prec="fp64", prune=True)
+    ins_i, ins_j = W.insertion_stream(n, s, d, 8, seed=3405)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i, j in zip(ins_i.tolist(), ins_j.tolist()):
+        plain.apply_edge_update(i, j, 1)
+    torch.cuda.synchronize()
+    per_edge = (time.perf_counter() - t1) / len(ins_i)
+    out = common(args, cfg, m * args.steps / dt, "edge-gradients/s", dt, args.steps,
+                 extra_cfg={"pairs": cfg["pairs"], "weights": "lognormal(0, 0.5)"})
+    out["metric"] = "dL/dw for all m edge weights per second (adjoint of eq (03a))"
+    out["plain_gpu"] = {"seconds_per_edge_update": per_edge,
+                        "seconds_for_all_edges": per_edge * m,
+                        "speedup_adjoint_vs_plain": per_edge * m / (dt / args.steps)}
+    # spmm_qt_rows: reads X and writes Y (n^2 float64 each); the second product of an
+    # iteration also reads G and the previous iterate
+    nbytes = 8.0 * n * n * 3.0 * launches
+    out["roofline"] = hbm_roof(nbytes, kern_ms, "spmm_qt_rows_kernel", launches,
+                               "n^2 x 8 B read + n^2 x 8 B written (+ 2 n^2 x 8 B read on "
+                               "every second launch)")
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_gradient(n, s, d, w, a, b, args.cpu_seconds)
+    return out
+
+
+# ------------------------------------------------------------------------------ helpers
 def copy_calibration():
     """A plain device copy of 1 GiB, three times: the HBM counters of this launch calibrate
     FETCH_SIZE and WRITE_SIZE (bytes moved are known exactly)."""
@@ -212,54 +382,136 @@ def copy_calibration():
     log(f"copy calibration: 3 x torch.neg over {x.numel() * 8} bytes read + written")
 
 
+def rmw_ceiling():
+    """Read-modify-write bandwidth of a plain library kernel (torch's in-place add over two
+    2 GiB float32 planes): the practical ceiling of an update that reads and writes every
+    entry once, for context beside the 8 TB/s peak."""
+    import torch
+    x = torch.zeros(1 << 29, dtype=torch.float32, device="cuda")
+    y = torch.zeros(1 << 29, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        x.add_(1.0)
+        y.add_(1.0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        x.add_(1.0)
+        y.add_(1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    gbs = 5 * 2 * 2 * x.numel() * 4 / (ms / 1e3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
     kernel's source has changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"{kernel}_pmc.md")
-    src = os.path.join(ROOT, "paper_1711_00121_amd", "csrc", "update.hip")
+    name = kernel.split(" ")[0]
+    path = os.path.join(ROOT, "profiles", f"{name}_pmc.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
+    m_src = re.search(r"Source: `([^`]+)`", text)
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_sha and m_b):
+    if not (m_src and m_sha and m_b):
+        return None
+    src = os.path.join(ROOT, m_src.group(1))
+    if not os.path.exists(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
         return None
     return float(m_b.group(1))
 
 
-def cpu_baseline(n, s, d, applied, seconds):
-    """The oracle on the host: converged single-source columns S[:, x] of the graph after the
-    timed batches (eq (17) by PartialSim to a tail C^(K+1) <= 1e-13), i.e. pair values of the
-    updated S computed from scratch, timed on a bounded sample of columns."""
-    import numpy as np
-
+def graph_after(n, s, d, applied):
     from oracle import graph as Gr
     from oracle import incremental as OI
-    from oracle import simrank as O
-
     cur_n, cur_s, cur_d = n, s, d
     for (bi, bj, bo), nn in applied:
         plus, minus = OI.net_update(bi, bj, bo)
         cur_n, cur_s, cur_d = Gr.apply_edges(
             cur_n, cur_s, cur_d, [e[0] for e in plus + minus], [e[1] for e in plus + minus],
             [1] * len(plus) + [-1] * len(minus), n_new=nn)
-    Q = Gr.transition_matrix(cur_n, cur_s, cur_d)
+    return cur_n, cur_s, cur_d
+
+
+def final_edges(s, d, stream):
+    import numpy as np
+    es = set(zip(s.tolist(), d.tolist()))
+    for i, j, op in stream:
+        if op > 0:
+            es.add((i, j))
+        else:
+            es.discard((i, j))
+    e = sorted(es, key=lambda t: (t[1], t[0]))
+    return (np.asarray([a for a, _ in e], dtype=np.int64),
+            np.asarray([b for _, b in e], dtype=np.int64))
+
+
+def cpu_baseline_columns(n, s, d, seconds, what):
+    """The oracle on the host: converged single-source columns S[:, x] of the updated graph
+    (eq (17) by PartialSim to a tail <= 1e-13), i.e. pair values of the updated S computed
+    from scratch, timed on a bounded sample of columns."""
+    import numpy as np
+
+    from oracle import graph as Gr
+    from oracle import simrank as O
+    Q = Gr.transition_matrix(n, s, d)
     rng = np.random.default_rng(7)
     t0 = time.perf_counter()
     cols = 0
     while time.perf_counter() - t0 < seconds:
-        O.single_source(Q, int(rng.integers(cur_n)), 0.6, tol=1e-13)
+        O.single_source(Q, int(rng.integers(n)), C, tol=1e-13)
         cols += 1
     dt = time.perf_counter() - t0
-    return {"value": cols * cur_n / dt, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cols} converged single-source columns S[:, x] (x uniform) of the "
-                      f"graph after the timed batches (n={cur_n}), oracle PartialSim to a "
-                      f"tail <= 1e-13, {dt:.1f} s on one host thread (scipy sparse products "
-                      f"are single-threaded)"}
+    return {"value": cols * n / dt, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cols} converged single-source columns S[:, x] (x uniform) of {what} "
+                      f"(n={n}), oracle PartialSim to a tail <= 1e-13, {dt:.1f} s on one host "
+                      f"thread (scipy sparse products are single-threaded)"}
+
+
+def cpu_baseline_delta_columns(n, s, d, i, j, cols, K, Kps, seconds):
+    """The oracle's column-by-column Delta S (same K and PartialSim depth) for the first
+    insertion, 8 columns per call until the time budget is used."""
+    import numpy as np
+
+    from oracle import incremental as OI
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < seconds and done < len(cols):
+        OI.delta_columns_c0(n, s.astype(np.int64), d.astype(np.int64), i, j,
+                            cols[done:done + 8], C, K, Kps)
+        done += 8
+    dt = time.perf_counter() - t0
+    return {"value": float(n) * done / dt, "unit": "pair-values/s", "cores": 1,
+            "kind": "oracle", "sample": f"{done} Delta S columns of one insertion "
+                                        f"(8 per oracle call), {dt:.1f} s on one host thread"}
+
+
+def cpu_baseline_gradient(n, s, d, w, a, b, seconds):
+    """The oracle's per-edge gradient (no dense matrices; upstream dL/dS = 1 at each pair),
+    timed on a bounded number of edges, scaled to edges/s."""
+    import numpy as np
+
+    from oracle import adjoint as OA
+    t0 = time.perf_counter()
+    done = 0
+    g = np.ones(len(a))
+    while time.perf_counter() - t0 < seconds:
+        OA.grad_weight_edges(n, s.astype(np.int64), d.astype(np.int64), w, a, b, None, C,
+                             [done], g_pairs=g)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "edge-gradients/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} edge-weight gradients by the oracle's per-edge adjoint form, "
+                      f"{dt:.1f} s on one host thread"}
 
 
 if __name__ == "__main__":

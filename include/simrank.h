@@ -200,12 +200,13 @@ sr_status sr_destroy(sr_ctx* ctx);
 const char* sr_strerror(sr_status status);
 
 /* Diagnostics: kernel timing of the S-update launches. enable = 1 records a pair of HIP events
- * on the context's stream around every S-update launch (single-update and fused-batch
- * kernels); 0 stops recording. */
+ * on the context's stream around every launch of a call's dominant kernel: the S update
+ * (single-update and fused-batch kernels), the column output of query_columns in column
+ * mode, and the dense Q^T X products of backward; 0 stops recording. */
 sr_status sr_profile(sr_ctx* ctx, int32_t enable);
 
-/* Synchronises, then returns the summed elapsed milliseconds of the recorded S-update
- * launches (*ms) and their count (*launches); reset = 1 clears the record. */
+/* Synchronises, then returns the summed elapsed milliseconds of the recorded launches (*ms)
+ * and their count (*launches); reset = 1 clears the record. */
 sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
 
 /* Diagnostics: runs one v_mfma_f64_16x16x4_f64 on a single wave with lane l supplying

@@ -99,26 +99,32 @@ def lam_col(Q, QT, G, x, C, K):
     return acc
 
 
-def grad_weight_edges(n, src, dst, w, a, b, t, C, edges, S_pairs=None, tol=1e-13):
+def grad_weight_edges(n, src, dst, w, a, b, t, C, edges, S_pairs=None, tol=1e-13,
+                      g_pairs=None):
     """dL/dw for selected edge indices without dense matrices (large n).
 
     Needs S only at the loss pairs (``S_pairs``; computed by ``single_source`` when
     missing) and, per edge ``y -> x``, column y and column x of the converged S. Uses
     ``sum_{y'} Q[x, y'] (Q S)[:, y'] = (Q S Q^T)[:, x] = (S[:, x] - (1 - C) e_x) / C``.
+
+    ``g_pairs``, when given, is dL/dS at the pairs directly (any upstream gradient, summed
+    over repeated pairs); then ``t`` and ``S_pairs`` are not used.
     """
     Q = transition_matrix(n, src, dst, weight=w)
     QT = Q.T.tocsr()
     a = np.asarray(a, dtype=np.int64)
     b = np.asarray(b, dtype=np.int64)
-    if S_pairs is None:
-        cache = {}
-        S_pairs = np.empty(len(a))
-        for p in range(len(a)):
-            col = cache.get(int(b[p]))
-            if col is None:
-                col = cache[int(b[p])] = single_source(Q, int(b[p]), C, tol)
-            S_pairs[p] = col[a[p]]
-    G = sp.csr_matrix((2.0 * (S_pairs - t), (a, b)), shape=(n, n))
+    if g_pairs is None:
+        if S_pairs is None:
+            cache = {}
+            S_pairs = np.empty(len(a))
+            for p in range(len(a)):
+                col = cache.get(int(b[p]))
+                if col is None:
+                    col = cache[int(b[p])] = single_source(Q, int(b[p]), C, tol)
+                S_pairs[p] = col[a[p]]
+        g_pairs = 2.0 * (S_pairs - t)
+    G = sp.csr_matrix((np.asarray(g_pairs, dtype=np.float64), (a, b)), shape=(n, n))
     K = depth_for(C, tol)
     W = np.bincount(np.asarray(dst, dtype=np.int64), weights=np.asarray(w), minlength=n)
     out = np.empty(len(edges))

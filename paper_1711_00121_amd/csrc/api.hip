@@ -285,8 +285,10 @@ sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>
   return SR_OK;
 }
 
-// Launches the S update, bracketed by events when profiling is on.
-hipError_t run_lowrank(sr_ctx* ctx, const LowRankArgs& la) {
+// Runs one launch of a call's dominant kernel, bracketed by events on the context stream
+// when profiling is on.
+template <typename F>
+hipError_t profiled(sr_ctx* ctx, F&& launch) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profiling) {
     hipError_t e = hipEventCreate(&e0);
@@ -294,12 +296,17 @@ hipError_t run_lowrank(sr_ctx* ctx, const LowRankArgs& la) {
     if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = launch_lowrank(la, ctx->stream);
+  hipError_t e = launch();
   if (e == hipSuccess && ctx->profiling) {
     e = hipEventRecord(e1, ctx->stream);
     ctx->prof_events.push_back({e0, e1});
   }
   return e;
+}
+
+// Launches the S update (or the column output), profiled.
+hipError_t run_lowrank(sr_ctx* ctx, const LowRankArgs& la) {
+  return profiled(ctx, [&]() { return launch_lowrank(la, ctx->stream); });
 }
 
 IdList idlist(const std::vector<int32_t>& v, size_t off, size_t cnt) {
@@ -1202,7 +1209,7 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
   la.ncols = n;
   la.out = out_dev;
   la.ld_out = ld_out;
-  HC(launch_lowrank(la, ctx->stream));
+  HC(run_lowrank(ctx, la));
   return SR_OK;
 }
 
@@ -1298,10 +1305,13 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   // Sig symmetric: Q^T Sig Q = Q^T (Q^T Sig)^T, so U = Q^T Sig, T = U^T, Sig' = Gs + C Q^T T.
   for (int it = 0; it < ctx->cfg.init_max_iter && e == hipSuccess; ++it) {
     e = hipMemsetAsync(ctx->d_max, 0, 8, s);
-    if (e == hipSuccess) e = launch_spmm_qt_rows(q, out, n, Sig, U, 1.0, nullptr, nullptr,
-                                                 nullptr, s);
+    if (e == hipSuccess) e = profiled(ctx, [&]() {
+      return launch_spmm_qt_rows(q, out, n, Sig, U, 1.0, nullptr, nullptr, nullptr, s);
+    });
     if (e == hipSuccess) e = launch_transpose(n, U, T, s);
-    if (e == hipSuccess) e = launch_spmm_qt_rows(q, out, n, T, U, C, G, Sig, ctx->d_max, s);
+    if (e == hipSuccess) e = profiled(ctx, [&]() {
+      return launch_spmm_qt_rows(q, out, n, T, U, C, G, Sig, ctx->d_max, s);
+    });
     if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost,
                                             s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -1,0 +1,163 @@
+"""Parity at the full sizes of the five workloads, on outputs the oracle computes one by one
+(single columns of the converged SimRank of the updated graph, Delta S columns of the
+column-by-column method, edge-weight gradients) and on properties that hold at any size
+(symmetry, range, soundness of the affected areas).
+
+The batch case runs in the configuration bench.py times (n = 50k, m = 1M, K = 15, float32
+value + compensation store, fused passes of 64 blocks), and again with K = 40 so that the
+truncation of the series (bounded by C^(K+1)) is far below the 1e-6 bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as OA
+from oracle import graph as Gr
+from oracle import incremental as OI
+from oracle import simrank as O
+
+from _util import EdgeTracker, maxabs
+
+C = 0.6
+
+
+def _ctx(*a, **kw):
+    from paper_1711_00121_amd import Context
+    return Context(*a, **kw)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("K,bar", [(15, 1e-4), (40, 1e-6)])
+def test_fullsize_batch_n50k(K, bar):
+    cfg = W.WORKLOADS[3]
+    n, m = cfg["n"], cfg["m"]
+    _say(f"batch n={n} m={m} K={K}: generating")
+    s, d = W.chung_lu(n, m, seed=1003)
+    batches, counts = W.batch_stream(n, s, d, 1, cfg["max_batch"], seed=2003)
+    bi, bj, bo = batches[0]
+    ctx = _ctx(n, s, d, C=C, K=K, s_prec="hilo", node_cap=counts[0] + 64,
+               edge_cap=m + len(bi) + 1024, fused_batch=True, batch_chunk=64)
+    st = ctx.apply_batch(bi, bj, bo, stats=True)
+    _say(f"batch of {len(bi)} edges: {st['blocks']} blocks, {st['fused_passes']} passes")
+    plus, minus = OI.net_update(bi, bj, bo)
+    n2, s2, d2 = Gr.apply_edges(n, s, d, [e[0] for e in plus + minus],
+                                [e[1] for e in plus + minus],
+                                [1] * len(plus) + [-1] * len(minus), n_new=counts[0])
+    assert ctx.sizes() == (n2, len(s2))
+    Q = Gr.transition_matrix(n2, s2, d2)
+    hub = int(np.argmax(np.bincount(d2, minlength=n2)))
+    sinks = sorted({int(j) for j in bj})
+    cols = W.column_sample(n2, 3, seed=4003, extra=[hub, sinks[0], sinks[-1], n2 - 1])
+    worst = 0.0
+    for x in cols:
+        ref = O.single_source(Q, int(x), C, tol=1e-13)
+        got = ctx.query_column(int(x)).cpu().numpy()
+        err = maxabs(got, ref)
+        worst = max(worst, err)
+        assert np.all(got >= -1e-12) and np.all(got <= 1.0 + 1e-12)
+        assert got[x] >= 1.0 - C - 1e-9
+    pairs = torch.as_tensor(np.stack([cols, cols[::-1]]), dtype=torch.int32)
+    g1 = ctx.gather_pairs(pairs[0], pairs[1]).cpu().numpy()
+    g2 = ctx.gather_pairs(pairs[1], pairs[0]).cpu().numpy()
+    assert np.array_equal(g1, g2)  # the fused pass mirrors tiles: S stays exactly symmetric
+    _say(f"K={K}: max |S_gpu - S*| over {len(cols)} columns = {worst:.3e} (bar {bar:g})")
+    assert worst < bar
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_fullsize_stream_n20k():
+    cfg = W.WORKLOADS[2]
+    n, m = cfg["n"], cfg["m"]
+    _say(f"stream n={n} m={m}: generating")
+    s, d = W.chung_lu(n, m, seed=1002)
+    oi, oj, oo = W.mixed_stream(n, s, d, cfg["updates"], cfg["p_insert"], seed=2002)
+    ctx = _ctx(n, s, d, C=C, K=cfg["K"], s_prec="hilo", prune=True)
+    tr = EdgeTracker(n, s, d)
+    Q0 = tr.Q()
+    checkpoints = (1, 10, 100, cfg["updates"])
+    for t, (i, j, op) in enumerate(zip(oi.tolist(), oj.tolist(), oo.tolist())):
+        ctx.apply_edge_update(i, j, op)
+        tr.apply(i, j, op)
+        if t + 1 not in checkpoints:
+            continue
+        Q = tr.Q()
+        cols = W.column_sample(n, 3, seed=5000 + t, extra=[i, j])
+        worst = 0.0
+        if t == 0:
+            A, B = (x.cpu().numpy() for x in ctx.get_aff())
+            inA = np.zeros(n, bool)
+            inB = np.zeros(n, bool)
+            inA[A] = True
+            inB[B] = True
+        for x in cols:
+            ref = O.single_source(Q, int(x), C, tol=1e-13)
+            got = ctx.query_column(int(x)).cpu().numpy()
+            worst = max(worst, maxabs(got, ref))
+            if t == 0:
+                # Theorem 4: Delta S vanishes outside A_hat x B_hat u B_hat x A_hat
+                dS = ref - O.single_source(Q0, int(x), C, tol=1e-13)
+                inside = (inA & inB[x]) | (inB & inA[x])
+                assert np.abs(dS[~inside]).max(initial=0.0) < 1e-11
+        _say(f"after {t + 1} updates: max |S_gpu - S*| = {worst:.3e}")
+        assert worst < 1e-6
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_fullsize_columns_n1m():
+    cfg = W.WORKLOADS[4]
+    n, m, K, Kps = cfg["n"], cfg["m"], cfg["K"], cfg["K_ps"]
+    _say(f"column mode n={n} m={m} K={K} K_ps={Kps}: generating")
+    s, d = W.chung_lu(n, m, seed=1004)
+    ii, jj = W.insertion_stream(n, s, d, 1, seed=2004)
+    i, j = int(ii[0]), int(jj[0])
+    block = W.column_sample(n, cfg["block"] - 2, seed=3004, extra=[i, j])[:cfg["block"]]
+    ctx = _ctx(n, s, d, C=C, K=K, K_ps=Kps, mode="column")
+    ctx.apply_edge_update(i, j, 1)
+    out = ctx.query_columns(block)
+    torch.cuda.synchronize()
+    pick = np.unique(np.concatenate([[0, len(block) - 1],
+                                     W.rng(6004).choice(len(block), 6, replace=False)]))
+    pick = np.concatenate([pick, np.nonzero((block == i) | (block == j))[0]])
+    got = out[torch.as_tensor(pick, device="cuda")].double().cpu().numpy().T
+    del out
+    ref = OI.delta_columns_c0(n, s.astype(np.int64), d.astype(np.int64), i, j, block[pick], C,
+                              K, Kps)
+    err = maxabs(got, ref)
+    _say(f"{len(block)}-column block: max |dS_gpu - dS_oracle| over {len(pick)} columns = "
+         f"{err:.3e}; max |dS| = {np.abs(ref).max():.3e}")
+    # both sides run the same K and K_ps in float64; only the float32 output rounding differs
+    # (half an ulp: 2^-24 relative)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) * 1.01 + 1e-13)
+    assert err < 1e-6
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_fullsize_adjoint_n20k():
+    cfg = W.WORKLOADS[5]
+    n, m = cfg["n"], cfg["m"]
+    _say(f"adjoint n={n} m={m}: generating")
+    s, d = W.chung_lu(n, m, seed=1005)
+    w = W.lognormal_weights(m, seed=3005)
+    a, b, _t = W.loss_pairs(n, cfg["pairs"], seed=3105)
+    gp = W.rng(3205).normal(size=len(a))
+    ctx = _ctx(n, s, d, weight=w, C=C, K=cfg["K"], s_prec="fp64")
+    dw = ctx.backward(a, b, gp).cpu().numpy()
+    edges = np.sort(W.rng(3305).choice(m, 16, replace=False))
+    ref = OA.grad_weight_edges(n, s.astype(np.int64), d.astype(np.int64), w, a, b, None, C,
+                               edges, g_pairs=gp)
+    err = maxabs(dw[edges], ref)
+    scale = float(np.abs(ref).max())
+    _say(f"dL/dw on {len(edges)} edges: max abs err {err:.3e}, max |dL/dw| {scale:.3e}")
+    assert scale > 0.0 and err < 1e-7 * scale
+    # Euler identity per sink (row normalisation): sum_y w(y->x) dL/dw(y->x) = 0
+    sums = np.bincount(d, weights=w * dw, minlength=n)
+    assert np.abs(sums).max() < 1e-9 * scale
+    ctx.close()

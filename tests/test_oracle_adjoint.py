@@ -86,6 +86,36 @@ def test_edge_form_equals_dense_form():
     assert np.abs(ge - g).max() < 1e-13
 
 
+def test_edge_form_with_upstream_gradient():
+    """Any upstream dL/dS at the pairs: the edge form equals the dense chain rule taken with
+    that G (pins the g_pairs path used at large n), and a repeated pair adds up."""
+    n, s, d, w, a, b, t = weighted_graph(7, n=11, p=0.3)
+    a = np.concatenate([a, a[:2]])
+    b = np.concatenate([b, b[:2]])
+    rng = np.random.default_rng(8)
+    gp = rng.normal(size=len(a))
+    Q = Gr.transition_matrix(n, s, d, weight=w)
+    S = O.fixed_point(Q, C)
+    G = np.zeros((n, n))
+    np.add.at(G, (a, b), gp)
+    Lam = A.adjoint_dense(Q, G, C)
+    dQ = C * (Lam + Lam.T) @ np.asarray(Q @ S)
+    Qd = Q.toarray()
+    Wx = np.bincount(d, weights=w, minlength=n)
+    ref = (dQ[d, s] - np.sum(Qd * dQ, axis=1)[d]) / Wx[d]
+    ge = A.grad_weight_edges(n, s, d, w, a, b, None, C, list(range(len(s))), g_pairs=gp)
+    assert np.abs(ge - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+    # central differences of the linear functional sum_p gp S[a_p, b_p]
+    for e in (0, len(s) // 2, len(s) - 1):
+        vals = []
+        for sg in (1.0, -1.0):
+            w2 = w.copy()
+            w2[e] += sg * 1e-6
+            S2 = O.fixed_point(Gr.transition_matrix(n, s, d, weight=w2), C)
+            vals.append(float(np.sum(gp * S2[a, b])))
+        assert abs((vals[0] - vals[1]) / 2e-6 - ge[e]) < 1e-8
+
+
 def test_adjoint_solves_transposed_sylvester():
     n, s, d, w, a, b, t = weighted_graph(6)
     Q = Gr.transition_matrix(n, s, d, weight=w, dense=True)
