@@ -51,7 +51,8 @@ typedef enum sr_status {
 /* Storage of the dense S. */
 enum {
   SR_S_FP64 = 0,       /* float64                                                         */
-  SR_S_FP32_HILO = 1,  /* float32 value + float32 compensation; updates add in float64     */
+  SR_S_FP32_HILO = 1,  /* float32 value + float32 compensation, adjacent per entry; updates
+                          add in float64                                                   */
   SR_S_FP32 = 2        /* plain float32 (no compensation), for precision comparisons      */
 };
 /* Context mode. */

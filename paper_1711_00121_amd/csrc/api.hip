@@ -762,15 +762,14 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
     IC(hipMalloc(&ctx->S_mem[0], cells * 8));
     ctx->S.d = (double*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 8));
+  } else if (cfg.s_prec == SR_S_FP32_HILO) {
+    IC(hipMalloc(&ctx->S_mem[0], cells * 8));
+    ctx->S.hl = (float2*)ctx->S_mem[0];
+    IC(hipMemset(ctx->S_mem[0], 0, cells * 8));
   } else {
     IC(hipMalloc(&ctx->S_mem[0], cells * 4));
     ctx->S.hi = (float*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 4));
-    if (cfg.s_prec == SR_S_FP32_HILO) {
-      IC(hipMalloc(&ctx->S_mem[1], cells * 4));
-      ctx->S.lo = (float*)ctx->S_mem[1];
-      IC(hipMemset(ctx->S_mem[1], 0, cells * 4));
-    }
   }
 
   // Initial S: copy S0, or iterate S <- C Q S Q^T + (1 - C) I in float64 (eq (03a)):

@@ -11,20 +11,24 @@ enum { PREC_FP64 = 0, PREC_HILO = 1, PREC_FP32 = 2 };
 
 // A view of the dense S: row-major with leading dimension ld.
 //  FP64:  value = d[a*ld + b]
-//  HILO:  value = (double)hi[a*ld + b] + (double)lo[a*ld + b]; lo holds the rounding error of
-//         hi, so the pair carries about 48 significant bits.
+//  HILO:  value = (double)hl[a*ld + b].x + (double)hl[a*ld + b].y; .y holds the rounding
+//         error of .x, so the pair carries about 48 significant bits. The two floats of an
+//         entry are adjacent, so an update reads and writes one 8-byte stream.
 //  FP32:  value = hi[a*ld + b]
 struct SView {
   int prec;
   double* d;
+  float2* hl;
   float* hi;
-  float* lo;
   int64_t ld;
 };
 
 __device__ __forceinline__ double s_get(const SView& s, int64_t off) {
   if (s.prec == PREC_FP64) return s.d[off];
-  if (s.prec == PREC_HILO) return (double)s.hi[off] + (double)s.lo[off];
+  if (s.prec == PREC_HILO) {
+    const float2 v = s.hl[off];
+    return (double)v.x + (double)v.y;
+  }
   return (double)s.hi[off];
 }
 
@@ -34,9 +38,8 @@ __device__ __forceinline__ void s_put(const SView& s, int64_t off, double t) {
   if (s.prec == PREC_FP64) {
     s.d[off] = t;
   } else if (s.prec == PREC_HILO) {
-    float h = (float)t;
-    s.hi[off] = h;
-    s.lo[off] = (float)(t - (double)h);
+    const float h = (float)t;
+    s.hl[off] = make_float2(h, (float)(t - (double)h));
   } else {
     s.hi[off] = (float)t;
   }

@@ -36,7 +36,8 @@ __device__ __forceinline__ bool pair_in(const uint32_t* Ah, const uint32_t* Bh, 
 template <int PREC>
 struct Raw {
   double d;
-  float h, l;
+  float2 hl;
+  float h;
 };
 
 template <int PREC>
@@ -44,8 +45,7 @@ __device__ __forceinline__ void sload(const SView& S, int64_t off, Raw<PREC>& x)
   if constexpr (PREC == PREC_FP64) {
     x.d = S.d[off];
   } else if constexpr (PREC == PREC_HILO) {
-    x.h = S.hi[off];
-    x.l = S.lo[off];
+    x.hl = S.hl[off];
   } else {
     x.h = S.hi[off];
   }
@@ -54,7 +54,7 @@ __device__ __forceinline__ void sload(const SView& S, int64_t off, Raw<PREC>& x)
 template <int PREC>
 __device__ __forceinline__ double sval(const Raw<PREC>& x) {
   if constexpr (PREC == PREC_FP64) return x.d;
-  else if constexpr (PREC == PREC_HILO) return (double)x.h + (double)x.l;
+  else if constexpr (PREC == PREC_HILO) return (double)x.hl.x + (double)x.hl.y;
   else return (double)x.h;
 }
 
@@ -64,8 +64,7 @@ __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
     S.d[off] = t;
   } else if constexpr (PREC == PREC_HILO) {
     const float h = (float)t;
-    S.hi[off] = h;
-    S.lo[off] = (float)(t - (double)h);
+    S.hl[off] = make_float2(h, (float)(t - (double)h));
   } else {
     S.hi[off] = (float)t;
   }
