@@ -37,14 +37,29 @@ __global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, in
   const int64_t c = ((int64_t)blockIdx.y * kB + threadIdx.x) * 2;
   const int len = out.len[b];
   const int st = out.start[b];
+  // Out-neighbours are taken 8 at a time: the 8 row loads of X are issued together, so a
+  // long row (a hub) costs one memory latency per 8 neighbours instead of one per neighbour.
+  // Columns past n read the zero padding of the leading dimension (c < ldi always).
+  constexpr int U = 8;
   double2 acc = make_double2(0.0, 0.0);
-  if (c < n) {
-    for (int p = 0; p < len; ++p) {
-      const int64_t a = out.idx[st + p];
-      const double qa = q.W ? out.w[st + p] / q.W[a] : 1.0 / (double)q.in.len[a];
-      const double2 v = *reinterpret_cast<const double2*>(X + a * ldi + c);
-      acc.x += qa * v.x;
-      acc.y += qa * v.y;
+  const int64_t cc = c < ldi ? c : 0;
+  for (int p0 = 0; p0 < len; p0 += U) {
+    int64_t a[U];
+    double qa[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u < len ? p0 + u : p0;
+      a[u] = out.idx[st + p];
+      qa[u] = p0 + u < len ? (q.W ? out.w[st + p] / q.W[a[u]] : 1.0 / (double)q.in.len[a[u]])
+                           : 0.0;
+    }
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const double2*>(X + a[u] * ldi + cc);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc.x += qa[u] * v[u].x;
+      acc.y += qa[u] * v[u].y;
     }
   }
   double diff = 0.0;
@@ -69,7 +84,10 @@ __global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, in
     if (threadIdx.x == 0) {
       double m = red[0];
       for (int w = 1; w < kB / 64; ++w) m = fmax(m, red[w]);
-      atomicMax(maxdiff, (unsigned long long)__double_as_longlong(m));
+      // the maximum only grows during a launch: skip the atomic when it is already larger
+      const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+      if (__hip_atomic_load(maxdiff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < mb)
+        atomicMax(maxdiff, mb);
     }
   }
 }

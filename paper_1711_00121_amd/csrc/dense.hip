@@ -18,7 +18,12 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* d
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    // The maximum only grows during a launch, so a block whose value does not exceed the one
+    // already there skips the atomic: with one address and ~10^6 blocks, unconditional
+    // atomics serialise and dominate the launch.
+    const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+    if (__hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < mb)
+      atomicMax(dst, mb);
   }
 }
 
@@ -187,19 +192,27 @@ __global__ __launch_bounds__(kB) void spmm_rows_kernel(DevQ q, int64_t n, int64_
   const int64_t c = ((int64_t)blockIdx.y * kB + threadIdx.x) * 2;
   const int len = q.in.len[a];
   const int st = q.in.start[a];
+  // In-neighbours are taken 8 at a time with their row loads issued together (one memory
+  // latency per 8 neighbours). Columns past n read the padding of the leading dimension.
+  constexpr int U = 8;
   double2 acc = make_double2(0.0, 0.0);
-  if (c < n) {
-    for (int p = 0; p < len; ++p) {
-      const int64_t x = q.in.idx[st + p];
-      const double2 v = *reinterpret_cast<const double2*>(X + x * ldi + c);
-      if (q.in.w) {
-        const double w = q.in.w[st + p];
-        acc.x += w * v.x;
-        acc.y += w * v.y;
-      } else {
-        acc.x += v.x;
-        acc.y += v.y;
-      }
+  const int64_t cc = c < ldi ? c : 0;
+  for (int p0 = 0; p0 < len; p0 += U) {
+    int64_t x[U];
+    double w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u < len ? p0 + u : p0;
+      x[u] = q.in.idx[st + p];
+      w[u] = p0 + u < len ? (q.in.w ? q.in.w[st + p] : 1.0) : 0.0;
+    }
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const double2*>(X + x[u] * ldi + cc);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc.x += w[u] * v[u].x;
+      acc.y += w[u] * v[u].y;
     }
   }
   double diff = 0.0;
