@@ -163,22 +163,18 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
     }
   };
 
-  // A operand of a tile: row (rbase + l16) of the panel. The inner sum over panel columns is
-  // order-free, so k-step ks of lane group lk uses column 8 lk + ks (same permutation on the
-  // B side): each lane's 8 A values are contiguous. No select is applied: positions past the
-  // list read row 0 and their output rows are never stored, and panel columns at or past r
-  // meet zeros on the B side (staged above).
+  // A operand of a tile: row (rbase + l16) of the panel; k-step ks of lane group lk uses
+  // panel column 4 ks + lk, so only ceil(r / 4) k-steps run (r = 22 at K = 10). No select is
+  // applied: positions past the list read row 0 and their output rows are never stored, and
+  // panel columns at or past r meet zeros on the B side (staged above).
   auto load_a = [&](int64_t rt, const int32_t (&e)[5], double (&av)[RC / 4]) {
     const int64_t p0 = rt * TR + wave * 16 + l16;
     const int64_t arow = p0 < nrows ? ((int64_t)e[0] >> (MASK ? 2 : 0)) : 0;
-    const double2* src = reinterpret_cast<const double2*>(g.P + arow * g.pld + 8 * lk);
+    const double* src = g.P + arow * g.pld + lk;
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const double2 v = src[h];
-      av[2 * h] = v.x;
-      av[2 * h + 1] = v.y;
-    }
+    for (int ks = 0; ks < RC / 4; ++ks) av[ks] = src[4 * ks];
   };
+  const int ksteps = (g.r + 3) / 4;
 
   // Pipeline: iteration rt holds the entries, S values and A operand of tile rt (loaded one
   // iteration earlier) and issues those of tile rt + gy (entries: rt + 2 gy) before its MFMAs.
@@ -200,7 +196,8 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
     for (int t = 0; t < ST; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < RC / 4; ++ks) {
-      const int c = (8 * lk + ks) ^ 1;
+      if (ks >= ksteps) break;  // uniform
+      const int c = (4 * ks + lk) ^ 1;
 #pragma unroll
       for (int t = 0; t < ST; ++t)
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], lcol[(t * 16 + l16) * LP + c],
