@@ -49,6 +49,7 @@ struct sr_ctx {
   double *SI = nullptr, *Sj = nullptr, *QSI = nullptr, *zbuf = nullptr, *Qz = nullptr,
          *zsum = nullptr, *ytmp = nullptr;
   double* P = nullptr;
+  double* pairs = nullptr;  // series scratch: two compact (xi_k, eta_k) vectors, node_cap each
   int pld = 0;  // doubles per panel row (one block)
   double* Pb = nullptr;  // fused batch panel: node_cap x (pld * batch_chunk)
   double* wts = nullptr;  // panel-correction weights: 2 * pld * batch_chunk
@@ -420,7 +421,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
     al.b1 = k >= 1 ? B + (int64_t)k * W : nullptr;
     al.bout = B + (int64_t)(k + 1) * W;
     HC(launch_series_step(q_new, hin_new, n_work, P, pld, k, C, 1.0, prune ? &al : nullptr,
-                          s));
+                          s, ctx->pairs, ctx->node_cap));
   }
   if (ft) return SR_OK;  // applied later by the batch's fused pass
   if (prune) HC(launch_aff_compact(aa, ctx->Ahat, ctx->Bhat, ctx->rowlist, ctx->d_cnt, s));
@@ -600,7 +601,7 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)hipFree(ctx->S_mem[0]);
   (void)hipFree(ctx->S_mem[1]);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp,
-                  ctx->P, ctx->Pb, ctx->wts, ctx->xs};
+                  ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs};
   for (double* p : dd) (void)hipFree(p);
   uint32_t* bb[] = {ctx->suppI, ctx->suppJ, ctx->Abits, ctx->Bbits, ctx->Ahat, ctx->Bhat};
   for (uint32_t* p : bb) (void)hipFree(p);
@@ -714,6 +715,7 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   IC(dalloc(&ctx->ytmp, node_cap));
   ctx->p_rows = (node_cap + 127) / 128 * 128;
   IC(dalloc(&ctx->P, ctx->p_rows * ctx->pld));
+  IC(dalloc(&ctx->pairs, 4 * node_cap));
   IC(dalloc(&ctx->suppI, ctx->W));
   IC(dalloc(&ctx->suppJ, ctx->W));
   IC(dalloc(&ctx->Abits, (int64_t)(cfg.K + 1) * ctx->W));
@@ -885,7 +887,7 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
     if (r != SR_OK) return r;
     for (int k = 0; k < ctx->cfg.K; ++k)
       HC(launch_series_step(devq(ctx), heavy_args(ctx->hin), n, ctx->P, ctx->pld, k, C, 1.0,
-                            nullptr, s));
+                            nullptr, s, ctx->pairs, ctx->node_cap));
     ctx->last_r = 2 * (ctx->cfg.K + 1);
     if (stats) {
       HC(hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost, s));

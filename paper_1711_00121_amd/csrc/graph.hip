@@ -37,6 +37,9 @@ struct Op {
   const double* base;
   double* P;            // kind 1 panel
   int pld, k;           // kind 1: columns 2k, 2k+1 -> 2k+2, 2k+3
+  const double* src;    // kind 1: the (xi_k, eta_k) pair of row x at src + x * sld
+  int sld;
+  double* cdst;         // kind 1: optional compact copy of the new pair (row a at 2 a)
   double sx, sy;
   // optional bitmaps (pull form of Theorem 4): out bit b = OR_{x in row b} (in0 | in1)(x)
   const uint32_t* a0;
@@ -79,7 +82,7 @@ __device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const Dev
       double2 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        v[u] = *reinterpret_cast<const double2*>(o.P + (int64_t)x[u] * o.pld + 2 * o.k);
+        v[u] = *reinterpret_cast<const double2*>(o.src + (int64_t)x[u] * o.sld);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         v0 += ok[u] ? w[u] * v[u].x : 0.0;
@@ -130,6 +133,7 @@ __device__ __forceinline__ void finish(const Op& o, const DevQ& q, int64_t row, 
       out.y = o.sy * (v1 * inv);
     }
     *reinterpret_cast<double2*>(o.P + row * o.pld + 2 * (o.k + 1)) = out;
+    if (o.cdst) *reinterpret_cast<double2*>(o.cdst + 2 * row) = out;
   } else if constexpr (KIND == 0) {
     double v = 0.0;
     if (len > 0) v = WT ? v0 / q.W[row] : v0 / (double)len;
@@ -309,12 +313,24 @@ hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, 
 }
 
 hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, double* P, int pld,
-                              int k, double sx, double sy, const AffLevel* aff, hipStream_t s) {
+                              int k, double sx, double sy, const AffLevel* aff, hipStream_t s,
+                              double* pairs, int64_t pairs_cap) {
   Op o = blank();
   o.kind = 1;
   o.P = P;
   o.pld = pld;
   o.k = k;
+  // The gathers of a step read the previous pair of every in-neighbour. From a compact
+  // double-buffered copy (16 B per node, resident in L2) they are cheaper than from the panel
+  // (256-byte rows); step 0 reads the panel's first pair.
+  if (pairs && k > 0) {
+    o.src = pairs + ((k - 1) % 2) * 2 * pairs_cap;
+    o.sld = 2;
+  } else {
+    o.src = P + 2 * k;
+    o.sld = pld;
+  }
+  o.cdst = pairs ? pairs + (k % 2) * 2 * pairs_cap : nullptr;
   o.sx = sx;
   o.sy = sy;
   if (aff) {

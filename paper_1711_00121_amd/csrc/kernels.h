@@ -63,8 +63,11 @@ hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, 
 // One step of eq (16a) on the panel P (row a holds (xi_k, eta_k) pairs for k = 0..K, pld
 // doubles per row): xi_{k+1} = sx * Q xi_k, eta_{k+1} = sy * Q eta_k; optionally one
 // affected-area level in the same pass.
+// pairs (optional): 2 x pairs_cap x 2 doubles of scratch; step k writes its pairs compactly
+// to half k % 2 and step k + 1 gathers from there instead of from the panel.
 hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, double* P, int pld,
-                              int k, double sx, double sy, const AffLevel* aff, hipStream_t s);
+                              int k, double sx, double sy, const AffLevel* aff, hipStream_t s,
+                              double* pairs = nullptr, int64_t pairs_cap = 0);
 
 // ---------------------------------------------------------------------------------------
 // Dense S helpers.
