@@ -92,42 +92,46 @@ __global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, in
   }
 }
 
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < kB / 64; ++w) s += red[w];
-  return s;
-}
-
-__global__ __launch_bounds__(kB) void edge_grad_kernel(DevQ q, int64_t n, int64_t ldi,
-                                                       const double* __restrict__ Sig,
-                                                       const double* __restrict__ T, double C,
-                                                       const int32_t* __restrict__ slot_edge,
-                                                       double* __restrict__ dq,
-                                                       double* __restrict__ dw) {
-  __shared__ double red[kB / 64];
+// One workgroup of 1024 threads per sink x. Each wave takes one in-edge slot at a time and
+// forms dq = C <Sig[x, :], T[y, :]> with a wave-level reduction (no workgroup barrier per
+// edge); then the row term sum_p Q[x][y_p] dq[p] is reduced in slot order and every edge gets
+// its gradient.
+constexpr int kEB = 1024;
+__global__ __launch_bounds__(kEB) void edge_grad_kernel(DevQ q, int64_t n, int64_t ldi,
+                                                        const double* __restrict__ Sig,
+                                                        const double* __restrict__ T, double C,
+                                                        const int32_t* __restrict__ slot_edge,
+                                                        double* __restrict__ dq,
+                                                        double* __restrict__ dw) {
+  __shared__ double red[kEB / 64];
   const int64_t x = blockIdx.x;
   const int len = q.in.len[x];
   if (len == 0) return;
   const int st = q.in.start[x];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const double* sx = Sig + x * ldi;
-  double rowterm = 0.0;
-  for (int p = 0; p < len; ++p) {
+  for (int p = wid; p < len; p += kEB / 64) {
     const int64_t y = q.in.idx[st + p];
     const double* ty = T + y * ldi;
     double part = 0.0;
-    for (int64_t c = threadIdx.x; c < n; c += kB) part += sx[c] * ty[c];
-    const double d = C * block_sum(part, red);
-    if (threadIdx.x == 0) dq[st + p] = d;
-    const double qxy = q.W ? q.in.w[st + p] / q.W[x] : 1.0 / (double)len;
-    rowterm += qxy * d;
+    for (int64_t c = lane; c < n; c += 64) part += sx[c] * ty[c];
+    part = wave_sum(part, 64);
+    if (lane == 0) dq[st + p] = C * part;
   }
   __syncthreads();
+  // row term, in slot order per thread, then a fixed tree over the waves
+  double rt = 0.0;
+  for (int p = threadIdx.x; p < len; p += kEB) {
+    const double qxy = q.W ? q.in.w[st + p] / q.W[x] : 1.0 / (double)len;
+    rt += qxy * dq[st + p];
+  }
+  rt = wave_sum(rt, 64);
+  if (lane == 0) red[wid] = rt;
+  __syncthreads();
+  double rowterm = 0.0;
+  for (int w = 0; w < kEB / 64; ++w) rowterm += red[w];
   const double Wx = q.W ? q.W[x] : (double)len;
-  for (int p = threadIdx.x; p < len; p += kB) {
+  for (int p = threadIdx.x; p < len; p += kEB) {
     const int32_t e = slot_edge[st + p];
     if (e >= 0) dw[e] = (dq[st + p] - rowterm) / Wx;
   }
@@ -154,7 +158,8 @@ hipError_t launch_spmm_qt_rows(const DevQ& q, const DevAdj& out, int64_t n, cons
 hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const double* T,
                             double C, const int32_t* slot_edge, double* dq, double* dw,
                             hipStream_t s) {
-  edge_grad_kernel<<<(unsigned)n, kB, 0, s>>>(q, n, ldi_of(n), Sig, T, C, slot_edge, dq, dw);
+  edge_grad_kernel<<<(unsigned)n, kEB, 0, s>>>(q, n, ldi_of(n), Sig, T, C, slot_edge, dq,
+                                               dw);
   return hipGetLastError();
 }
 
