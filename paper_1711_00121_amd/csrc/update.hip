@@ -354,12 +354,14 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
     __syncthreads();
   }
 
-  // S[a][b] += acc (and S[b][a] += acc off the diagonal), one row sub-tile at a time.
-  // Loads are unconditional from clamped addresses; out-of-range entries are not stored.
+  // S[a][b] += acc (and S[b][a] += acc off the diagonal), one row sub-tile at a time: the
+  // direct and the mirrored loads of a sub-tile are issued together (one memory round trip per
+  // sub-tile), then both stores. Loads are unconditional from clamped addresses (a diagonal
+  // tile's mirrored loads repeat its direct ones); out-of-range entries are not stored.
   const bool mirror = I != J;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    Raw<PREC> x[4][4];
+    Raw<PREC> x[4][4], y[4][4];
     int on[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -368,7 +370,10 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
         const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
         const int64_t b = c0 + wc * 64 + q * 16 + l16;
         on[q][v] = a < g.nrows && b < g.ncols;
-        sload<PREC>(g.S, on[q][v] ? a * g.S.ld + b : 0, x[q][v]);
+        const int64_t da = on[q][v] ? a * g.S.ld + b : 0;
+        const int64_t ma = on[q][v] ? b * g.S.ld + a : 0;
+        sload<PREC>(g.S, da, x[q][v]);
+        sload<PREC>(g.S, mirror ? ma : da, y[q][v]);
       }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -378,26 +383,8 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
         const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
         const int64_t b = c0 + wc * 64 + q * 16 + l16;
         sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + acc[s][q][v]);
+        if (mirror) sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(y[q][v]) + acc[s][q][v]);
       }
-    if (mirror) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
-          const int64_t b = c0 + wc * 64 + q * 16 + l16;
-          sload<PREC>(g.S, on[q][v] ? b * g.S.ld + a : 0, x[q][v]);
-        }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (!on[q][v]) continue;
-          const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
-          const int64_t b = c0 + wc * 64 + q * 16 + l16;
-          sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(x[q][v]) + acc[s][q][v]);
-        }
-    }
   }
 }
 
