@@ -140,6 +140,47 @@ def test_aff_sets_bit_exact_on_insertions():
         cur_d = np.concatenate([cur_d, [j]])
 
 
+def test_aff_sets_bit_exact_mid_size():
+    """The affected areas at n = 2000 over several tiles of the compaction and traversal
+    kernels (light, medium and heavy rows), against the oracle's sets from the exact S."""
+    n = 2000
+    K = 15
+    s, d = W.chung_lu(n, 16000, seed=141)
+    ii, jj = W.insertion_stream(n, s, d, 3, seed=142)
+    ctx = ctx_for(n, s, d, s_prec="fp64", K=K)
+    cur_s, cur_d = s.astype(np.int64), d.astype(np.int64)
+    for i, j in zip(ii.tolist(), jj.tolist()):
+        S_or = O.fixed_point(Gr.transition_matrix(n, cur_s, cur_d), C)
+        A, B, Ah, Bh = OI.aff_for_update(n, cur_s, cur_d, S_or, [i], j, 1, K)
+        ctx.apply_edge_update(i, j, 1)
+        for lvl in (0, 1, 2, K):
+            ga, gb = ctx.get_aff(lvl)
+            assert np.array_equal(ga.cpu().numpy(), A[lvl]), ("A", lvl)
+            assert np.array_equal(gb.cpu().numpy(), B[lvl]), ("B", lvl)
+        ga, gb = ctx.get_aff(-1)
+        assert np.array_equal(ga.cpu().numpy(), Ah)
+        assert np.array_equal(gb.cpu().numpy(), Bh)
+        cur_s = np.append(cur_s, i)
+        cur_d = np.append(cur_d, j)
+    # deletions, each as the first update of a fresh context (its S is the converged one, so
+    # both sides take supports from the same S): an edge into a sink with several in-edges,
+    # and the only in-edge of a sink (F2 empty)
+    S_or = O.fixed_point(Gr.transition_matrix(n, s, d), C)
+    indeg = np.bincount(d, minlength=n)
+    e_multi = int(np.nonzero(indeg[d] > 1)[0][0])
+    e_single = int(np.nonzero(indeg[d] == 1)[0][0])
+    for e in (e_multi, e_single):
+        i, j = int(s[e]), int(d[e])
+        A, B, Ah, Bh = OI.aff_for_update(n, s.astype(np.int64), d.astype(np.int64), S_or, [i],
+                                         j, -1, K)
+        ctx = ctx_for(n, s, d, s_prec="fp64", K=K)
+        ctx.apply_edge_update(i, j, -1)
+        ga, gb = ctx.get_aff(-1)
+        assert np.array_equal(ga.cpu().numpy(), Ah), ("deletion", e)
+        assert np.array_equal(gb.cpu().numpy(), Bh), ("deletion", e)
+        ctx.close()
+
+
 def test_node_insertion_cases_unit():
     n = 300
     s, d = W.chung_lu(n, 1200, seed=51)
