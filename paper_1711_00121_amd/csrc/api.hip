@@ -17,12 +17,19 @@ using namespace sr;
 // Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
 // process them in chunks (see graph.hip).
 struct HeavySet {
-  std::map<int32_t, int8_t> rows;  // listed row -> tier (1 medium, 2 heavy)
-  std::vector<int32_t> med, heavy;
+  std::map<int32_t, int8_t> rows;    // listed row -> tier (1 medium, 2 heavy, 3 huge)
+  std::map<int32_t, int32_t> cover;  // huge row -> entries its chunks cover
+  std::vector<int32_t> med, heavy, huge, hfirst;
+  std::vector<int2> chunk;           // (row, first entry) per chunk of the huge rows
   bool dirty = true;
   int32_t* d_med = nullptr;
   int32_t* d_heavy = nullptr;
-  int64_t cap_med = 0, cap_heavy = 0;
+  int32_t* d_huge = nullptr;
+  int32_t* d_hfirst = nullptr;
+  int2* d_chunk = nullptr;
+  double2* d_part = nullptr;   // per-chunk partial sums (traversal scratch)
+  uint32_t* d_pflag = nullptr;
+  int64_t cap_med = 0, cap_heavy = 0, cap_huge = 0, cap_hfirst = 0, cap_chunk = 0;
 };
 
 struct sr_ctx {
@@ -69,6 +76,7 @@ struct sr_ctx {
   std::vector<int32_t> last_plan;
 
   double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) x node_cap
+  double* xd = nullptr;    // PartialSim: two vectors x_t / d (d: row weight of Q), node_cap each
 
   HeavySet hin, hout;      // heavy in-rows (Q) and out-rows (Q^T)
 
@@ -130,48 +138,96 @@ void heavy_touch(HeavySet& H, const SlotList& L, int32_t r) {
   if (len <= kLight) {
     if (it != H.rows.end()) {
       H.rows.erase(it);
+      H.cover.erase(r);
       H.dirty = true;
     }
     return;
   }
-  const int8_t tier = len > kMedium ? 2 : 1;
+  const int8_t tier = len > kHuge ? 3 : (len > kMedium ? 2 : 1);
   if (it == H.rows.end() || it->second != tier) {
     H.rows[r] = tier;
     H.dirty = true;
+  }
+  // a huge row's chunks must cover all its entries
+  if (tier == 3) {
+    auto c = H.cover.find(r);
+    if (c == H.cover.end() || len > c->second) H.dirty = true;
   }
 }
 
 void heavy_free(HeavySet& H) {
   (void)hipFree(H.d_med);
   (void)hipFree(H.d_heavy);
-  H.d_med = nullptr;
-  H.d_heavy = nullptr;
-  H.cap_med = H.cap_heavy = 0;
+  (void)hipFree(H.d_huge);
+  (void)hipFree(H.d_hfirst);
+  (void)hipFree(H.d_chunk);
+  (void)hipFree(H.d_part);
+  (void)hipFree(H.d_pflag);
+  H.d_med = H.d_heavy = H.d_huge = H.d_hfirst = nullptr;
+  H.d_chunk = nullptr;
+  H.d_part = nullptr;
+  H.d_pflag = nullptr;
+  H.cap_med = H.cap_heavy = H.cap_huge = H.cap_hfirst = H.cap_chunk = 0;
 }
 
-hipError_t upload_list(const std::vector<int32_t>& v, int32_t** d, int64_t* cap) {
+template <typename T>
+hipError_t upload_list(const std::vector<T>& v, T** d, int64_t* cap) {
   const int64_t cnt = (int64_t)v.size();
   if (cnt > *cap) {
     (void)hipFree(*d);
     *d = nullptr;
     const int64_t c = std::max<int64_t>(64, 2 * cnt);
-    hipError_t e = hipMalloc((void**)d, (size_t)c * 4);
+    hipError_t e = hipMalloc((void**)d, (size_t)c * sizeof(T));
     if (e != hipSuccess) return e;
     *cap = c;
   }
-  if (cnt) return hipMemcpy(*d, v.data(), (size_t)cnt * 4, hipMemcpyHostToDevice);
+  if (cnt) return hipMemcpy(*d, v.data(), (size_t)cnt * sizeof(T), hipMemcpyHostToDevice);
   return hipSuccess;
 }
 
-// Uploads the medium and heavy lists when they changed.
-sr_status heavy_sync(sr_ctx* ctx, HeavySet& H) {
+// Uploads the medium, heavy and huge lists and the chunk table when they changed. A huge row
+// gets len / kChunk + 1 chunks, so it can grow by at least one entry (and up to kChunk)
+// before the table must be rebuilt; chunks past the row's current length add nothing.
+sr_status heavy_sync(sr_ctx* ctx, HeavySet& H, const SlotList& L) {
   if (!H.dirty) return SR_OK;
   HC(hipStreamSynchronize(ctx->stream));
   H.med.clear();
   H.heavy.clear();
-  for (const auto& rt : H.rows) (rt.second == 2 ? H.heavy : H.med).push_back(rt.first);
+  H.huge.clear();
+  H.hfirst.clear();
+  H.chunk.clear();
+  H.cover.clear();
+  for (const auto& rt : H.rows) {
+    if (rt.second == 1) {
+      H.med.push_back(rt.first);
+    } else if (rt.second == 2) {
+      H.heavy.push_back(rt.first);
+    } else {
+      const int32_t nc = L.len[rt.first] / kChunk + 1;
+      H.huge.push_back(rt.first);
+      H.hfirst.push_back((int32_t)H.chunk.size());
+      for (int32_t c = 0; c < nc; ++c) H.chunk.push_back(make_int2(rt.first, c * kChunk));
+      H.cover[rt.first] = nc * kChunk;
+    }
+  }
+  H.hfirst.push_back((int32_t)H.chunk.size());
   hipError_t e = upload_list(H.med, &H.d_med, &H.cap_med);
   if (e == hipSuccess) e = upload_list(H.heavy, &H.d_heavy, &H.cap_heavy);
+  if (e == hipSuccess) e = upload_list(H.huge, &H.d_huge, &H.cap_huge);
+  if (e == hipSuccess) e = upload_list(H.hfirst, &H.d_hfirst, &H.cap_hfirst);
+  if (e == hipSuccess) {
+    const int64_t old_cap = H.cap_chunk;
+    e = upload_list(H.chunk, &H.d_chunk, &H.cap_chunk);
+    if (e == hipSuccess && (H.cap_chunk != old_cap || H.d_part == nullptr)) {
+      (void)hipFree(H.d_part);
+      (void)hipFree(H.d_pflag);
+      H.d_part = nullptr;
+      H.d_pflag = nullptr;
+      e = hipMalloc((void**)&H.d_part, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 16);
+      if (e == hipSuccess)
+        e = hipMalloc((void**)&H.d_pflag, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 4);
+    }
+  }
   if (e == hipErrorOutOfMemory) return SR_ENOMEM;
   HC(e);
   H.dirty = false;
@@ -184,12 +240,19 @@ HeavyArgs heavy_args(const HeavySet& H) {
   h.nmed = (int32_t)H.med.size();
   h.heavy = H.d_heavy;
   h.nheavy = (int32_t)H.heavy.size();
+  h.huge = H.d_huge;
+  h.nhuge = (int32_t)H.huge.size();
+  h.chunk = H.d_chunk;
+  h.nchunk = (int32_t)H.chunk.size();
+  h.hfirst = H.d_hfirst;
+  h.part = H.d_part;
+  h.pflag = H.d_pflag;
   return h;
 }
 
 sr_status heavy_refresh(sr_ctx* ctx) {
-  sr_status r = heavy_sync(ctx, ctx->hin);
-  if (r == SR_OK) r = heavy_sync(ctx, ctx->hout);
+  sr_status r = heavy_sync(ctx, ctx->hin, ctx->g.in);
+  if (r == SR_OK) r = heavy_sync(ctx, ctx->hout, ctx->g.out);
   return r;
 }
 
@@ -524,6 +587,7 @@ sr_status c3_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j) {
 
 // PartialSim (section 7): column q of the K_ps-term SimRank into out (n values).
 // x_0 = e_q, x_t = Q^T x_{t-1} (t = 1..K); y = x_K, y <- x_{K-t} + C Q y (t = 1..K); (1 - C) y.
+// The Q^T products read x_{t-1} divided by the row weights of Q (two alternating buffers).
 sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
   const int64_t n = ctx->g.n;
   const int Kp = ctx->cfg.K_ps > 0 ? ctx->cfg.K_ps : ctx->cfg.K;
@@ -532,10 +596,11 @@ sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
   const DevQ dq = devq(ctx);
   const DevAdj out_l = devout(ctx);
   auto x = [&](int t) { return ctx->xs + (int64_t)t * ctx->node_cap; };
-  HC(launch_unit_vector(x(0), n, q, s));
+  auto xd = [&](int t) { return ctx->xd + (int64_t)(t & 1) * ctx->node_cap; };
+  HC(launch_unit_vector(x(0), n, q, s, &dq, xd(0)));
   const HeavyArgs hin = heavy_args(ctx->hin), hout = heavy_args(ctx->hout);
   for (int t = 1; t <= Kp; ++t)
-    HC(launch_spmv_qt(dq, out_l, hout, n, x(t - 1), x(t), 1.0, s));
+    HC(launch_spmv_qt(dq, out_l, hout, n, xd(t - 1), x(t), t < Kp ? xd(t) : nullptr, 1.0, s));
   const double* y = x(Kp);
   for (int t = 1; t <= Kp; ++t) {
     double* dst = (t == Kp) ? out : ((t & 1) ? ctx->ytmp : ctx->zbuf);
@@ -601,7 +666,7 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)hipFree(ctx->S_mem[0]);
   (void)hipFree(ctx->S_mem[1]);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp,
-                  ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs};
+                  ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd};
   for (double* p : dd) (void)hipFree(p);
   uint32_t* bb[] = {ctx->suppI, ctx->suppJ, ctx->Abits, ctx->Bbits, ctx->Ahat, ctx->Bhat};
   for (uint32_t* p : bb) (void)hipFree(p);
@@ -751,6 +816,7 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   if (cfg.mode == SR_COLUMN) {
     const int Kp = cfg.K_ps > 0 ? cfg.K_ps : cfg.K;
     IC(dalloc(&ctx->xs, (int64_t)(Kp + 1) * node_cap));
+    IC(dalloc(&ctx->xd, 2 * node_cap));
     *out = ctx;
     return SR_OK;
   }
@@ -814,7 +880,11 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
       return SR_EHIP;
     }
   }
-  hipError_t e = launch_to_store(ctx->S, n, A, ctx->stream);
+  // The two gathers of an iteration sum in different orders for (a, b) and (b, a); the
+  // stored S is made exactly symmetric, (A + A^T) / 2, which the mirrored updates keep.
+  hipError_t e = hipSuccess;
+  if (B) e = launch_transpose(n, A, B, ctx->stream);
+  if (e == hipSuccess) e = launch_to_store(ctx->S, n, A, ctx->stream, B);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   (void)hipFree(A);
   (void)hipFree(B);

@@ -244,10 +244,14 @@ __global__ __launch_bounds__(1024) void transpose_kernel(int64_t n, int64_t ldi,
 }
 
 __global__ __launch_bounds__(kB) void to_store_kernel(SView dst, int64_t n, int64_t ldi,
-                                                      const double* __restrict__ src) {
+                                                      const double* __restrict__ src,
+                                                      const double* __restrict__ srcT) {
   const int64_t a = blockIdx.x;
   const int64_t c = (int64_t)blockIdx.y * kB + threadIdx.x;
-  if (c < n) s_put(dst, a * dst.ld + c, src[a * ldi + c]);
+  if (c >= n) return;
+  // with the transpose: (x + y) / 2 rounds the same for (a, c) and (c, a)
+  const double v = srcT ? 0.5 * (src[a * ldi + c] + srcT[a * ldi + c]) : src[a * ldi + c];
+  s_put(dst, a * dst.ld + c, v);
 }
 
 __global__ __launch_bounds__(kB) void from_store_kernel(SView src, int64_t n,
@@ -281,9 +285,19 @@ __global__ __launch_bounds__(kB) void rows_to_f32_kernel(SView S, int64_t n,
   if (a < n) out[t * ld_out + a] = (float)s_get(S, (int64_t)rows[t] * S.ld + a);
 }
 
-__global__ __launch_bounds__(kB) void unit_vector_kernel(double* x, int64_t n, int32_t q) {
+__global__ __launch_bounds__(kB) void unit_vector_kernel(double* x, int64_t n, int32_t q,
+                                                         DevQ dq, double* xd) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (a < n) x[a] = (a == q) ? 1.0 : 0.0;
+  if (a >= n) return;
+  x[a] = (a == q) ? 1.0 : 0.0;
+  if (xd) {
+    double v = 0.0;
+    if (a == q) {
+      const double d = dq.W ? dq.W[a] : (double)dq.in.len[a];
+      v = d > 0.0 ? 1.0 / d : 0.0;
+    }
+    xd[a] = v;
+  }
 }
 
 __global__ __launch_bounds__(kB) void fill_diag_kernel(double* A, int64_t n, int64_t ld,
@@ -302,9 +316,10 @@ inline unsigned g1(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
 }  // namespace
 
-hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s) {
+hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s, const DevQ* dq,
+                              double* xd) {
   if (n <= 0) return hipSuccess;
-  unit_vector_kernel<<<g1(n), kB, 0, s>>>(x, n, q);
+  unit_vector_kernel<<<g1(n), kB, 0, s>>>(x, n, q, dq ? *dq : DevQ{}, dq ? xd : nullptr);
   return hipGetLastError();
 }
 
@@ -376,9 +391,10 @@ hipError_t launch_transpose(int64_t n, const double* X, double* Y, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_to_store(SView dst, int64_t n, const double* src, hipStream_t s) {
+hipError_t launch_to_store(SView dst, int64_t n, const double* src, hipStream_t s,
+                           const double* srcT) {
   dim3 grid((unsigned)n, g1(n));
-  to_store_kernel<<<grid, kB, 0, s>>>(dst, n, init_ld(n), src);
+  to_store_kernel<<<grid, kB, 0, s>>>(dst, n, init_ld(n), src, srcT);
   return hipGetLastError();
 }
 

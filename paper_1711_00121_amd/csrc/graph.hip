@@ -5,13 +5,16 @@
 // Q[a][x] = 1/indeg(a) for an edge x -> a (section 3.1). Rows are in-lists by sink, so
 // (Q x)[a] gathers over a's in-neighbours and (Q^T x)[b] over b's out-neighbours.
 //
-// Power-law rows, three tiers, all in 1024-thread workgroups of one launch: a row of at most
+// Power-law rows, four tiers, all in 1024-thread workgroups of one launch: a row of at most
 // kLight entries is handled by a group of 8 lanes, a medium row (at most kMedium entries,
-// listed by the host) by one wave, a heavy row (listed) by a whole workgroup. Each lane takes
-// its entries 8 or 16 at a time with all loads issued together, since the traversal is bound
-// by memory latency; every row is reduced inside one workgroup in a fixed order, so there is
-// no cross-workgroup combine (whose device-scope fences write back the L2 of an XCD) and the
-// results do not depend on scheduling.
+// listed by the host) by one wave, a heavy row (at most kHuge) by a whole workgroup, and a
+// huge row is cut into chunks of kChunk entries, one workgroup each, whose partial sums a
+// second small launch adds in chunk order. Workgroups are ordered longest work first (chunks,
+// heavy, medium, light) so that the long rows do not trail the launch. Each lane takes its
+// entries 8 or 16 at a time with all loads issued together, since the traversal is bound by
+// memory latency; every sum is reduced in a fixed order, with no cross-workgroup combine
+// inside a launch (whose device-scope fences write back the L2 of an XCD), so the results do
+// not depend on scheduling.
 #include "kernels.h"
 
 namespace sr {
@@ -31,8 +34,9 @@ __global__ __launch_bounds__(64) void patch_kernel(AdjPtrs t, Patch p) {
 // What one traversal computes. Values per entry: NV = 1 (x) or 2 (xi, eta pair).
 struct Op {
   int kind;             // 0: y = post*(base + scale*Q x); 1: series step; 2: y = scale*Q^T x
-  const double* x;      // kind 0/2 input vector
+  const double* x;      // kind 0/2 input vector (kind 2: divided by the row weight of Q)
   double* y;            // kind 0/2 output vector
+  double* yd;           // kind 2: optional output divided by the row weight of Q
   double scale, post;
   const double* base;
   double* P;            // kind 1 panel
@@ -95,15 +99,13 @@ __device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const Dev
 #pragma unroll
       for (int u = 0; u < U; ++u) v0 += ok[u] ? w[u] * v[u] : 0.0;
     } else {
-      // (Q^T x)[b] = sum over out-neighbours a of Q[a][b] x[a], Q[a][b] = w / W_a or 1 / indeg(a)
-      double v[U], d[U];
+      // (Q^T x)[b] = sum over out-neighbours a of Q[a][b] x[a], Q[a][b] = w / W_a or 1 / indeg(a);
+      // the input holds x[a] / W_a (or x[a] / indeg(a)) already
+      double v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        v[u] = o.x[x[u]];
-        d[u] = WT ? q.W[x[u]] : (double)q.in.len[x[u]];
-      }
+      for (int u = 0; u < U; ++u) v[u] = o.x[x[u]];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v0 += ok[u] ? (w[u] / d[u]) * v[u] : 0.0;
+      for (int u = 0; u < U; ++u) v0 += ok[u] ? w[u] * v[u] : 0.0;
     }
     if constexpr (AFF == 2) {
 #pragma unroll
@@ -141,52 +143,92 @@ __device__ __forceinline__ void finish(const Op& o, const DevQ& q, int64_t row, 
     if (o.base) v += o.base[row];
     o.y[row] = o.post * v;
   } else {
-    o.y[row] = o.scale * v0;
+    const double v = o.scale * v0;
+    o.y[row] = v;
+    if (o.yd) {
+      const double d = WT ? q.W[row] : (double)q.in.len[row];
+      o.yd[row] = d > 0.0 ? v / d : 0.0;
+    }
   }
 }
 
+// Sums of a whole workgroup in a fixed order (shuffles, then the wave sums in wave order);
+// the result is valid in thread 0.
+__device__ __forceinline__ void block_reduce(double& v0, double& v1, int& fw, double* red0,
+                                             double* red1, int* redf) {
+  const int lane64 = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  v0 = wave_sum(v0, 64);
+  v1 = wave_sum(v1, 64);
+  for (int sh = 32; sh > 0; sh >>= 1) fw |= __shfl_xor(fw, sh, 64);
+  if (lane64 == 0) {
+    red0[wid] = v0;
+    red1[wid] = v1;
+    redf[wid] = fw;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    int ff = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      s0 += red0[w];
+      s1 += red1[w];
+      ff |= redf[w];
+    }
+    v0 = s0;
+    v1 = s1;
+    fw = ff;
+  }
+}
+
+// Workgroup roles by block index, longest work first: [0, nchunk) chunks of huge rows,
+// then one workgroup per heavy row, then medium blocks (kWaves rows each), then light blocks
+// (kRowsPerBlock consecutive rows each; rows of other tiers are skipped there).
 template <int KIND, bool WT, int AFF>
 __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, int64_t n,
-                                                      int64_t n_light_blocks,
                                                       int64_t n_med_blocks, HeavyArgs h) {
   __shared__ double red0[kWaves], red1[kWaves];
   __shared__ int redf[kWaves];
-  const int64_t bid = blockIdx.x;
+  int64_t bid = blockIdx.x;
   const int lane64 = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   double v0 = 0.0, v1 = 0.0;
   uint32_t fa = 0, fb = 0;
-  if (bid < n_light_blocks) {
-    // light rows (<= kLight entries): 8 lanes per row, one pass of 8 entries per lane
-    const int64_t row = bid * kRowsPerBlock + threadIdx.x / kG;
-    const int lane = threadIdx.x % kG;
-    int len = 0;
-    bool mine = false;
-    if (row < n) {
-      len = L.len[row];
-      mine = len <= kLight;
-      if (mine)
-        accumulate<kLight / kG, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, lane, kG, v0,
-                                               v1, fa, fb);
-    }
-    v0 = wave_sum(v0, kG);
-    v1 = wave_sum(v1, kG);
-    if constexpr (AFF > 0) {
-      for (int s = kG >> 1; s > 0; s >>= 1) {
-        fa |= (uint32_t)__shfl_xor((int)fa, s, kG);
-        fb |= (uint32_t)__shfl_xor((int)fb, s, kG);
-      }
-    }
-    if (mine && lane == 0) {
-      finish<KIND, WT>(o, q, row, len, v0, v1);
-      if (AFF == 2 && fa) bit_set_atomic(o.aout, row);
-      if (AFF >= 1 && fb) bit_set_atomic(o.bout, row);
+  if (bid < h.nchunk) {
+    // one chunk of a huge row: kChunk entries, 8 per thread, partial sums to the scratch
+    const int2 c = h.chunk[bid];
+    const int len = L.len[c.x];
+    const int p1 = min(len, c.y + kChunk);
+    accumulate<kChunk / kB, KIND, WT, AFF>(o, q, L, L.start[c.x], c.y, p1, threadIdx.x, kB, v0,
+                                           v1, fa, fb);
+    int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
+    block_reduce(v0, v1, fw, red0, red1, redf);
+    if (threadIdx.x == 0) {
+      h.part[bid] = make_double2(v0, v1);
+      h.pflag[bid] = (uint32_t)fw;
     }
     return;
   }
-  if (bid < n_light_blocks + n_med_blocks) {
+  bid -= h.nchunk;
+  if (bid < h.nheavy) {
+    // heavy row (kMedium < len <= kHuge): the whole workgroup, 8 entries per thread per pass
+    const int64_t row = h.heavy[bid];
+    const int len = L.len[row];
+    accumulate<8, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, threadIdx.x, kB, v0, v1, fa,
+                                 fb);
+    int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
+    block_reduce(v0, v1, fw, red0, red1, redf);
+    if (threadIdx.x == 0) {
+      finish<KIND, WT>(o, q, row, len, v0, v1);
+      if (AFF == 2 && (fw & 1)) bit_set_atomic(o.aout, row);
+      if (AFF >= 1 && (fw & 2)) bit_set_atomic(o.bout, row);
+    }
+    return;
+  }
+  bid -= h.nheavy;
+  if (bid < n_med_blocks) {
     // medium rows (kLight < len <= kMedium): one wave per row, 16 entries per lane per pass
-    const int64_t mi = (bid - n_light_blocks) * kWaves + wid;
+    const int64_t mi = bid * kWaves + wid;
     if (mi >= h.nmed) return;
     const int64_t row = h.med[mi];
     const int len = L.len[row];
@@ -208,37 +250,53 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
     }
     return;
   }
-  // heavy row (len > kMedium): the whole workgroup, 8 entries per thread per pass, then a
-  // fixed-order reduction (shuffles, then the wave sums in order)
-  const int64_t hi = bid - n_light_blocks - n_med_blocks;
-  if (hi >= h.nheavy) return;
-  const int64_t row = h.heavy[hi];
-  const int len = L.len[row];
-  accumulate<8, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, threadIdx.x, kB, v0, v1, fa, fb);
-  v0 = wave_sum(v0, 64);
-  v1 = wave_sum(v1, 64);
-  int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
+  bid -= n_med_blocks;
+  // light rows (<= kLight entries): 8 lanes per row, one pass of 8 entries per lane
+  const int64_t row = bid * kRowsPerBlock + threadIdx.x / kG;
+  const int lane = threadIdx.x % kG;
+  int len = 0;
+  bool mine = false;
+  if (row < n) {
+    len = L.len[row];
+    mine = len <= kLight;
+    if (mine)
+      accumulate<kLight / kG, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, lane, kG, v0, v1,
+                                             fa, fb);
+  }
+  v0 = wave_sum(v0, kG);
+  v1 = wave_sum(v1, kG);
   if constexpr (AFF > 0) {
-    for (int sh = 32; sh > 0; sh >>= 1) fw |= __shfl_xor(fw, sh, 64);
-  }
-  if (lane64 == 0) {
-    red0[wid] = v0;
-    red1[wid] = v1;
-    redf[wid] = fw;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    int ff = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      s0 += red0[w];
-      s1 += red1[w];
-      ff |= redf[w];
+    for (int s = kG >> 1; s > 0; s >>= 1) {
+      fa |= (uint32_t)__shfl_xor((int)fa, s, kG);
+      fb |= (uint32_t)__shfl_xor((int)fb, s, kG);
     }
-    finish<KIND, WT>(o, q, row, len, s0, s1);
-    if (AFF == 2 && (ff & 1)) bit_set_atomic(o.aout, row);
-    if (AFF >= 1 && (ff & 2)) bit_set_atomic(o.bout, row);
   }
+  if (mine && lane == 0) {
+    finish<KIND, WT>(o, q, row, len, v0, v1);
+    if (AFF == 2 && fa) bit_set_atomic(o.aout, row);
+    if (AFF >= 1 && fb) bit_set_atomic(o.bout, row);
+  }
+}
+
+// Second launch for huge rows: one thread per row adds its chunks' partial sums in chunk
+// order and finishes the row as the traversal does.
+template <int KIND, bool WT, int AFF>
+__global__ __launch_bounds__(64) void traverse_combine_kernel(Op o, DevQ q, DevAdj L,
+                                                              HeavyArgs h) {
+  const int hi = blockIdx.x * 64 + threadIdx.x;
+  if (hi >= h.nhuge) return;
+  double s0 = 0.0, s1 = 0.0;
+  uint32_t ff = 0;
+  for (int c = h.hfirst[hi]; c < h.hfirst[hi + 1]; ++c) {
+    const double2 p = h.part[c];
+    s0 += p.x;
+    s1 += p.y;
+    ff |= h.pflag[c];
+  }
+  const int64_t row = h.huge[hi];
+  finish<KIND, WT>(o, q, row, L.len[row], s0, s1);
+  if (AFF == 2 && (ff & 1)) bit_set_atomic(o.aout, row);
+  if (AFF >= 1 && (ff & 2)) bit_set_atomic(o.bout, row);
 }
 
 template <int KIND, bool WT, int AFF>
@@ -246,8 +304,11 @@ hipError_t run_shape(const Op& o, const DevQ& q, const DevAdj& L, int64_t n,
                      const HeavyArgs& h, hipStream_t s) {
   const int64_t nlb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
   const int64_t nmb = ((int64_t)h.nmed + kWaves - 1) / kWaves;
-  const int64_t grid = nlb + nmb + (int64_t)h.nheavy;
-  traverse_kernel<KIND, WT, AFF><<<(unsigned)grid, kB, 0, s>>>(o, q, L, n, nlb, nmb, h);
+  const int64_t grid = (int64_t)h.nchunk + h.nheavy + nmb + nlb;
+  traverse_kernel<KIND, WT, AFF><<<(unsigned)grid, kB, 0, s>>>(o, q, L, n, nmb, h);
+  if (h.nhuge > 0)
+    traverse_combine_kernel<KIND, WT, AFF><<<(unsigned)((h.nhuge + 63) / 64), 64, 0, s>>>(
+        o, q, L, h);
   return hipGetLastError();
 }
 
@@ -303,11 +364,13 @@ hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const dou
 }
 
 hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
-                          const double* x, double* y, double scale, hipStream_t s) {
+                          const double* xd, double* y, double* yd, double scale,
+                          hipStream_t s) {
   Op o = blank();
   o.kind = 2;
-  o.x = x;
+  o.x = xd;
   o.y = y;
+  o.yd = yd;
   o.scale = scale;
   return run(o, q, out, n, h, s);
 }

@@ -32,14 +32,25 @@ struct IdList {
 
 // ---------------------------------------------------------------------------------------
 // Sparse traversals. Rows with more than kLight entries are listed by the host: "medium"
-// rows (at most kMedium entries) are handled by one wave each, "heavy" rows by a workgroup.
+// rows (at most kMedium entries) are handled by one wave each, "heavy" rows (at most kHuge)
+// by a workgroup, and "huge" rows are cut into chunks of kChunk entries, one workgroup per
+// chunk, whose partial sums a second small launch adds up in chunk order.
 constexpr int kLight = 64;
 constexpr int kMedium = 2048;
+constexpr int kHuge = 16384;
+constexpr int kChunk = 8192;
 struct HeavyArgs {
   const int32_t* med;    // medium row ids (device), ascending
   int32_t nmed;
   const int32_t* heavy;  // heavy row ids (device), ascending
   int32_t nheavy;
+  const int32_t* huge;   // huge row ids (device), ascending
+  int32_t nhuge;
+  const int2* chunk;     // (row, first entry) per chunk, grouped by huge row in list order
+  int32_t nchunk;
+  const int32_t* hfirst;  // chunks of huge row h: [hfirst[h], hfirst[h + 1])
+  double2* part;          // per chunk: partial sums (scratch, nchunk entries)
+  uint32_t* pflag;        // per chunk: affected-area bits (scratch)
 };
 // Pull form of one affected-area level (Theorem 4): out bit b is set when some in-neighbour x
 // of b (new graph) has (s0 | s1)(x). Null sets are empty.
@@ -58,8 +69,12 @@ hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const dou
                          double post = 1.0, const uint32_t* fin = nullptr,
                          uint32_t* fout = nullptr);
 // y[b] = scale * (Q^T x)[b] = scale * sum_{a in out(b)} Q[a][b] x[a] (h: heavy out-rows).
+// The input comes pre-divided by the row weight of Q, xd[a] = x[a] / d[a] (d = in-degree, or
+// the in-weight sum when weighted; 0 where d[a] = 0), so an entry costs one gather; the
+// output is written both plain (y) and divided (yd) for the next product.
 hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
-                          const double* x, double* y, double scale, hipStream_t s);
+                          const double* xd, double* y, double* yd, double scale,
+                          hipStream_t s);
 // One step of eq (16a) on the panel P (row a holds (xi_k, eta_k) pairs for k = 0..K, pld
 // doubles per row): xi_{k+1} = sx * Q xi_k, eta_{k+1} = sy * Q eta_k; optionally one
 // affected-area level in the same pass.
@@ -122,8 +137,10 @@ hipError_t launch_spmm_rows(const DevQ& q, int64_t n, const double* X, double* Y
                             double scale, double add_diag, const double* prev,
                             unsigned long long* maxdiff, hipStream_t s);
 hipError_t launch_transpose(int64_t n, const double* X, double* Y, hipStream_t s);
-// dst (store format, leading dim ld) = src (float64, leading dim n), rows/cols < n.
-hipError_t launch_to_store(SView dst, int64_t n, const double* src, hipStream_t s);
+// dst (store format, leading dim ld) = src (float64, leading dim n), rows/cols < n; with
+// srcT = src^T, dst = (src + src^T) / 2, which is exactly symmetric.
+hipError_t launch_to_store(SView dst, int64_t n, const double* src, hipStream_t s,
+                           const double* srcT = nullptr);
 hipError_t launch_from_store(SView src, int64_t n, double* dst, int64_t ld_dst,
                              hipStream_t s);
 hipError_t launch_copy_row(SView S, int64_t n, int32_t x, double* out, hipStream_t s);
@@ -217,7 +234,9 @@ hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const d
                             double C, const int32_t* slot_edge, double* dq, double* dw,
                             hipStream_t s);
 // Small helpers.
-hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s);
+// x = e_q; with dq, also xd = e_q / d[q] (d as for launch_spmv_qt; 0 when d[q] = 0).
+hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s,
+                              const DevQ* dq = nullptr, double* xd = nullptr);
 hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
 hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);

@@ -354,11 +354,13 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
     __syncthreads();
   }
 
-  // S[a][b] += acc (and S[b][a] += acc off the diagonal), one row sub-tile at a time: the
-  // direct and the mirrored loads of a sub-tile are issued together (one memory round trip per
-  // sub-tile), then both stores. Loads are unconditional from clamped addresses (a diagonal
-  // tile's mirrored loads repeat its direct ones); out-of-range entries are not stored.
-  const bool mirror = I != J;
+  // S[a][b] += acc and S[b][a] += acc, one row sub-tile at a time: the direct and the
+  // mirrored loads of a sub-tile are issued together (one memory round trip per sub-tile),
+  // then both stores. A diagonal tile computes both (a, b) and (b, a), whose sums the matrix
+  // cores may round differently; there only a <= b is stored, with its mirror, so S stays
+  // exactly symmetric. Loads are unconditional from clamped addresses; out-of-range entries
+  // are not stored.
+  const bool diag = I == J;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     Raw<PREC> x[4][4], y[4][4];
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
         const int64_t da = on[q][v] ? a * g.S.ld + b : 0;
         const int64_t ma = on[q][v] ? b * g.S.ld + a : 0;
         sload<PREC>(g.S, da, x[q][v]);
-        sload<PREC>(g.S, mirror ? ma : da, y[q][v]);
+        sload<PREC>(g.S, ma, y[q][v]);
       }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -382,8 +384,9 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
         if (!on[q][v]) continue;
         const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
         const int64_t b = c0 + wc * 64 + q * 16 + l16;
-        sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + acc[s][q][v]);
-        if (mirror) sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(y[q][v]) + acc[s][q][v]);
+        const double d = acc[s][q][v];
+        if (!diag || a <= b) sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + d);
+        if (!diag || a < b) sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(y[q][v]) + d);
       }
   }
 }

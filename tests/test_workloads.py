@@ -1,5 +1,6 @@
 """The seeded generators: determinism, simple-digraph properties, valid update streams."""
 import numpy as np
+import pytest
 
 import workloads as W
 
@@ -46,3 +47,19 @@ def test_loss_pairs_unique():
     assert (a < b).all()
     assert len(set(zip(a.tolist(), b.tolist()))) == 500
     assert (t >= 0).all() and (t < 0.2).all()
+
+
+def test_with_hubs_exact_degrees():
+    n = 3000
+    s, d = W.chung_lu(n, 9000, seed=91)
+    s2, d2 = W.with_hubs(n, s, d, [(3, 2500, 1200), (4, 700, 10)], seed=92)
+    assert np.array_equal(s2[:len(s)], s) and np.array_equal(d2[:len(d)], d)
+    assert len(set(zip(s2.tolist(), d2.tolist()))) == len(s2)
+    assert np.all(s2 != d2)
+    ind = np.bincount(d2, minlength=n)
+    outd = np.bincount(s2, minlength=n)
+    assert (ind[3], outd[3], ind[4], outd[4]) == (2500, 1200, 700, 10)
+    s3, d3 = W.with_hubs(n, s, d, [(3, 2500, 1200), (4, 700, 10)], seed=92)
+    assert np.array_equal(s2, s3) and np.array_equal(d2, d3)
+    with pytest.raises(ValueError):
+        W.with_hubs(n, s2, d2, [(3, 10, 10)], seed=93)

@@ -32,6 +32,7 @@ __all__ = [
     "lognormal_weights",
     "loss_pairs",
     "column_sample",
+    "with_hubs",
     "rng",
 ]
 
@@ -310,3 +311,36 @@ def column_sample(n, k, seed, extra=()):
     g = rng(seed)
     base = g.choice(n, size=min(k, n), replace=False)
     return np.unique(np.concatenate([base, np.asarray(extra, dtype=np.int64)])).astype(np.int32)
+
+
+def with_hubs(n, src, dst, hubs, seed):
+    """Adds edges so that every hub ``(node, in_degree, out_degree)`` has exactly those
+    degrees: the new in-neighbours (out-neighbours) of a hub are drawn uniformly, without
+    replacement, from the nodes that are neither hubs nor linked to it yet. Raises
+    ``ValueError`` when a hub already has more edges than asked. Returns ``(src, dst)`` int32
+    arrays: the input edges, then the added ones in generation order."""
+    g = rng(seed)
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    hub_ids = np.asarray(sorted({int(h) for h, _, _ in hubs}), dtype=np.int64)
+    add_s, add_d = [], []
+    for h, want_in, want_out in hubs:
+        for want, into in ((want_in, True), (want_out, False)):
+            cur = src[dst == h] if into else dst[src == h]
+            extra = np.asarray(add_s if into else add_d, dtype=np.int64)
+            other = np.asarray(add_d if into else add_s, dtype=np.int64)
+            cur = np.concatenate([cur, extra[other == h]]) if len(extra) else cur
+            need = want - len(np.unique(cur))
+            if need < 0:
+                raise ValueError(f"hub {h} already has more than {want} edges")
+            cand = np.setdiff1d(np.arange(n, dtype=np.int64),
+                                np.concatenate([cur, hub_ids]))
+            pick = g.choice(cand, size=need, replace=False)
+            if into:
+                add_s.extend(pick.tolist())
+                add_d.extend([h] * need)
+            else:
+                add_s.extend([h] * need)
+                add_d.extend(pick.tolist())
+    return (np.concatenate([src, np.asarray(add_s, dtype=np.int64)]).astype(np.int32),
+            np.concatenate([dst, np.asarray(add_d, dtype=np.int64)]).astype(np.int32))
