@@ -297,8 +297,18 @@ def run_columns(args):
                             "output": "float32"})
     out["metric"] = "ΔS column values/s, column-by-column mode (no stored S)"
     out["columns_per_s"] = len(cols) * steps / dt
-    out["roofline"] = hbm_roof(4.0 * values, kern_ms, "lowrank_strip_kernel (column output)",
-                               launches, "4 B written per output value")
+    # each output value is a 2 (K + 1)-term dot product (4 (K + 1) flop) written as 4 bytes;
+    # at the peaks the flops take longer than the writes, so the kernel is bound by FP64 MFMA
+    flops = 4.0 * (K + 1) * values
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                       "traffic": traffic("lowrank_cols_kernel"),
+                       "kernel": "lowrank_cols_kernel", "launches": launches,
+                       "avg_ms": round(kern_ms / max(launches, 1), 3),
+                       "algorithmic": "4 (K + 1) flop and 4 B written per output value",
+                       "write_gbs": round(4.0 * values / (kern_ms / 1e3) / 1e9, 1)}
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_delta_columns(n, s, d, int(ii[0]), int(jj[0]), cols,

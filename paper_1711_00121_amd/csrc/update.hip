@@ -5,10 +5,12 @@
 // with panel rows P[a] = (xi_0[a], eta_0[a], xi_1[a], eta_1[a], ...). Several blocks of a batch
 // stack their pairs along c, so the same product applies a rank-2(K+1)B update in one pass.
 //
-// Two kernels, both on v_mfma_f64_16x16x4_f64 (lane l supplies A[l%16][l/16] and
+// Three kernels, all on v_mfma_f64_16x16x4_f64 (lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator slot v of lane l is D[4v + l/16][l%16]):
 //  - lowrank_strip_kernel, one block (r <= 32): bound by HBM. S streams through once; the
 //    S loads of the next row tile are in flight while the current tile multiplies and stores.
+//  - lowrank_cols_kernel, columns of Delta S for the column-by-column method (r <= 32, float32
+//    output): bound by FP64 matrix throughput and the output writes.
 //  - lowrank_gemm_kernel, fused batches (r = 32 B): bound by FP64 matrix throughput. Only
 //    the upper triangle of tiles is computed (the update is symmetric).
 #include "kernels.h"
@@ -85,7 +87,7 @@ __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
 constexpr int SC = 64;
 constexpr int ST = SC / 16;
 
-template <int PREC, bool MASK, bool COLOUT, bool HASROWS>
+template <int PREC, bool MASK, bool HASROWS>
 __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
   __shared__ double lcol[SC * LP];
   const int tid = threadIdx.x;
@@ -148,10 +150,10 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
     }
   };
   // Output row of accumulator slot v: the node (with a mask the entry is packed as
-  // (node << 2) | (in A_hat << 1) | in B_hat), or the list position in column-output form.
+  // (node << 2) | (in A_hat << 1) | in B_hat).
   auto out_row = [&](int64_t rt, const int32_t (&e)[5], int v) -> int64_t {
     const int64_t pc = rt * TR + wave * 16 + v * 4 + lk;
-    const int64_t rr = COLOUT ? pc : (MASK ? ((int64_t)e[1 + v] >> 2) : (int64_t)e[1 + v]);
+    const int64_t rr = MASK ? ((int64_t)e[1 + v] >> 2) : (int64_t)e[1 + v];
     return pc < nrows ? rr : 0;
   };
   auto load_tile = [&](int64_t rt, const int32_t (&e)[5], Raw<PREC> (&x)[ST][4]) {
@@ -183,13 +185,13 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
   double a0[RC / 4], a1[RC / 4];
   int64_t rt = blockIdx.y;
   fetch(rt, e0);
-  if (!COLOUT) load_tile(rt, e0, x0);
+  load_tile(rt, e0, x0);
   load_a(rt, e0, a0);
   fetch(rt + gy, e1);
   for (; rt < nrt; rt += gy) {
     const int64_t rbase = rt * TR + wave * 16;
     load_a(rt + gy, e1, a1);
-    if (!COLOUT) load_tile(rt + gy, e1, x1);
+    load_tile(rt + gy, e1, x1);
     fetch(rt + 2 * gy, e2);
     dbl4 acc[ST];
 #pragma unroll
@@ -216,11 +218,7 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
       for (int t = 0; t < ST; ++t) {
         if (!((on >> t) & 1)) continue;
         const int64_t b = c0 + t * 16 + l16;
-        if (COLOUT) {
-          g.out[row * g.ld_out + b] = (float)acc[t][v];
-        } else {
-          sput<PREC>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
-        }
+        sput<PREC>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
       }
     }
 #pragma unroll
@@ -230,12 +228,10 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
     }
 #pragma unroll
     for (int q = 0; q < RC / 4; ++q) a0[q] = a1[q];
-    if (!COLOUT) {
 #pragma unroll
-      for (int t = 0; t < ST; ++t)
+    for (int t = 0; t < ST; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x0[t][v] = x1[t][v];
-    }
+      for (int v = 0; v < 4; ++v) x0[t][v] = x1[t][v];
   }
 }
 
@@ -459,6 +455,99 @@ __global__ __launch_bounds__(256) void panel_gemv_kernel(const double* __restric
   }
 }
 
+// Column output for one block (r <= RC panel columns, float32):
+//     out[p][b] = sum_{c < r} P[rows[p]][c] P[b][c ^ 1]   (Delta S[b][rows[p]], eq (71))
+// for list positions p < nrows and nodes b < ncols. The tiling is the streaming kernel's
+// without S: workgroup = strip of SC nodes, wave w = positions [16 w, 16 w + 16) of each TR
+// tile. A strip's B fragments are the same for every tile, so each lane keeps them in
+// registers for the whole kernel (KS k-steps of 4 panel columns; columns at or past r are
+// zero there); a tile then costs ST KS MFMAs, KS loads of A fragments issued one tile ahead,
+// and its float32 stores, with no LDS traffic. With VEC, accumulator t of lane column l holds
+// node c0 + 4 l + t, so a lane's four accumulators of one row are adjacent and go out as one
+// 16-byte store (a quarter of the store instructions); otherwise node c0 + 16 t + l. Full
+// tiles store without per-entry checks.
+template <int KS, bool VEC>
+__global__ __launch_bounds__(NT, KS <= 6 ? 4 : 3) void lowrank_cols_kernel(LowRankArgs g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int lk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.x * SC;
+  auto node = [&](int t) -> int64_t { return VEC ? c0 + 4 * l16 + t : c0 + 16 * t + l16; };
+  // B[k][j] = P[node][k ^ 1], k = 4 ks + lk (k ^ 1 < 4 KS <= pld: in bounds)
+  double bv[ST][KS];
+#pragma unroll
+  for (int t = 0; t < ST; ++t) {
+    const int64_t b = node(t);
+    const bool okb = b < g.ncols;
+    const double* src = g.P + (okb ? b : 0) * g.pld;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + lk;
+      const double v = src[k ^ 1];
+      bv[t][ks] = (okb && k < g.r) ? v : 0.0;
+    }
+  }
+  const int64_t nrows = g.nrows;
+  const int64_t nrt = (nrows + TR - 1) / TR;
+  const int64_t gy = gridDim.y;
+  const bool full_cols = c0 + SC <= g.ncols;
+  // A operand row of a tile: the node at list position (tile base + l16), clamped to the
+  // last position (any listed node is an in-bounds panel row)
+  auto fetch = [&](int64_t rt) -> int32_t {
+    const int64_t p = rt * TR + wave * 16 + l16;
+    return g.rows[p < nrows ? p : nrows - 1];
+  };
+  auto load_a = [&](int32_t nd, double (&av)[KS]) {
+    const double* src = g.P + (int64_t)nd * g.pld + lk;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) av[ks] = src[4 * ks];
+  };
+  int64_t rt = blockIdx.y;
+  double a0[KS], a1[KS];
+  load_a(fetch(rt), a0);
+  int32_t e1 = fetch(rt + gy);
+  for (; rt < nrt; rt += gy) {
+    load_a(e1, a1);
+    e1 = fetch(rt + 2 * gy);
+    dbl4 acc[ST];
+#pragma unroll
+    for (int t = 0; t < ST; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < ST; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], bv[t][ks], acc[t], 0, 0, 0);
+    const int64_t rb = rt * TR + wave * 16;
+    if (full_cols && rb + 16 <= nrows) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float* orow = g.out + (rb + v * 4 + lk) * g.ld_out + c0;
+        if (VEC) {
+          *reinterpret_cast<float4*>(orow + 4 * l16) =
+              make_float4((float)acc[0][v], (float)acc[1][v], (float)acc[2][v],
+                          (float)acc[3][v]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < ST; ++t) orow[16 * t + l16] = (float)acc[t][v];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t pc = rb + v * 4 + lk;
+        if (pc >= nrows) continue;
+        float* orow = g.out + pc * g.ld_out;
+#pragma unroll
+        for (int t = 0; t < ST; ++t)
+          if (node(t) < g.ncols) orow[node(t)] = (float)acc[t][v];
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a0[ks] = a1[ks];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_panel_correct(const double* P, int pld, int64_t gstride, int r, int64_t n,
@@ -482,12 +571,21 @@ hipError_t launch_delta_col(const double* P, int pld, int r, int64_t n, int32_t 
   return hipGetLastError();
 }
 
-template <int PREC, bool MASK, bool COLOUT>
+template <int KS>
+static void cols_launch(const LowRankArgs& a, dim3 grid, hipStream_t s) {
+  // 16-byte stores need ld_out and the base address aligned to 4 floats
+  if (a.ld_out % 4 == 0 && reinterpret_cast<uintptr_t>(a.out) % 16 == 0)
+    lowrank_cols_kernel<KS, true><<<grid, NT, 0, s>>>(a);
+  else
+    lowrank_cols_kernel<KS, false><<<grid, NT, 0, s>>>(a);
+}
+
+template <int PREC, bool MASK>
 static void strip_launch(const LowRankArgs& a, dim3 grid, hipStream_t s) {
   if (a.rows)
-    lowrank_strip_kernel<PREC, MASK, COLOUT, true><<<grid, NT, 0, s>>>(a);
+    lowrank_strip_kernel<PREC, MASK, true><<<grid, NT, 0, s>>>(a);
   else
-    lowrank_strip_kernel<PREC, MASK, COLOUT, false><<<grid, NT, 0, s>>>(a);
+    lowrank_strip_kernel<PREC, MASK, false><<<grid, NT, 0, s>>>(a);
 }
 
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
@@ -514,16 +612,31 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     dim3 grid((unsigned)strips, (unsigned)gy);
     const bool mask = a.Ahat != nullptr && a.out == nullptr;
     if (a.out) {
-      strip_launch<PREC_FP64, false, true>(a, grid, s);
+      // column output: list rows on the host count only; r even, so ceil(r / 4) is 1..8
+      if (a.rows == nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr) {
+        return hipErrorInvalidValue;
+      }
+      // at least two workgroups per strip: shorter row loops balance the tail better
+      if (grid.y < 2 && rtiles >= 2) grid.y = 2;
+      switch ((a.r + 3) / 4) {
+        case 1: cols_launch<1>(a, grid, s); break;
+        case 2: cols_launch<2>(a, grid, s); break;
+        case 3: cols_launch<3>(a, grid, s); break;
+        case 4: cols_launch<4>(a, grid, s); break;
+        case 5: cols_launch<5>(a, grid, s); break;
+        case 6: cols_launch<6>(a, grid, s); break;
+        case 7: cols_launch<7>(a, grid, s); break;
+        default: cols_launch<8>(a, grid, s); break;
+      }
     } else if (a.S.prec == PREC_FP64) {
-      mask ? strip_launch<PREC_FP64, true, false>(a, grid, s)
-           : strip_launch<PREC_FP64, false, false>(a, grid, s);
+      mask ? strip_launch<PREC_FP64, true>(a, grid, s)
+           : strip_launch<PREC_FP64, false>(a, grid, s);
     } else if (a.S.prec == PREC_HILO) {
-      mask ? strip_launch<PREC_HILO, true, false>(a, grid, s)
-           : strip_launch<PREC_HILO, false, false>(a, grid, s);
+      mask ? strip_launch<PREC_HILO, true>(a, grid, s)
+           : strip_launch<PREC_HILO, false>(a, grid, s);
     } else {
-      mask ? strip_launch<PREC_FP32, true, false>(a, grid, s)
-           : strip_launch<PREC_FP32, false, false>(a, grid, s);
+      mask ? strip_launch<PREC_FP32, true>(a, grid, s)
+           : strip_launch<PREC_FP32, false>(a, grid, s);
     }
     return hipGetLastError();
   }

@@ -258,6 +258,26 @@ def test_column_mode_delta_columns():
         cur_s, cur_d = s2.astype(np.int64), d2.astype(np.int64)
 
 
+@pytest.mark.parametrize("K,n", [(0, 700), (3, 701), (4, 700), (6, 702), (8, 700), (10, 703),
+                                 (12, 700), (15, 701)])
+def test_column_kernel_every_depth(K, n):
+    """Delta S columns at every series depth the column kernel specialises on (ceil(2 (K + 1)
+    / 4) = 1 .. 8 k-steps), on ragged shapes: n = 700 .. 703 nodes (the last 64-node strip is
+    partial; rows of n floats are 16-byte aligned only for n = 700, the other sizes take the
+    4-byte stores) and 70 columns (the last row tile is partial)."""
+    s, d = W.chung_lu(n, 4200, seed=81)
+    ii, jj = W.insertion_stream(n, s, d, 1, seed=82)
+    i, j = int(ii[0]), int(jj[0])
+    c = W.column_sample(n, 68, seed=83, extra=[i, j])
+    ctx = ctx_for(n, s, d, mode="column", K=K, K_ps=12)
+    ctx.apply_edge_update(i, j, 1)
+    got = ctx.query_columns(c).double().cpu().numpy().T
+    ref = OI.delta_columns_c0(n, s.astype(np.int64), d.astype(np.int64), i, j, c, C, K, 12)
+    # same K and K_ps on both sides in float64; the output is rounded to float32
+    assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) * 1.01 + 1e-13)
+    ctx.close()
+
+
 def test_backward_matches_oracle_gradient():
     n = 200
     s, d = W.chung_lu(n, 1000, seed=81)
