@@ -25,16 +25,18 @@ __global__ __launch_bounds__(kB) void scatter_sym_kernel(double* G, int64_t ldi,
   atomicAdd(G + b * ldi + a, g[p]);
 }
 
-__global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, int64_t n,
+constexpr int kRowT = 128;  // threads of a row-gather workgroup (2 columns each)
+
+__global__ __launch_bounds__(kRowT) void spmm_qt_rows_kernel(DevQ q, DevAdj out, int64_t n,
                                                           int64_t ldi,
                                                           const double* __restrict__ X,
                                                           double* __restrict__ Y, double scale,
                                                           const double* __restrict__ Gadd,
                                                           const double* __restrict__ prev,
                                                           unsigned long long* maxdiff) {
-  __shared__ double red[kB / 64];
+  __shared__ double red[kRowT / 64];
   const int64_t b = blockIdx.x;
-  const int64_t c = ((int64_t)blockIdx.y * kB + threadIdx.x) * 2;
+  const int64_t c = ((int64_t)blockIdx.y * kRowT + threadIdx.x) * 2;
   const int len = out.len[b];
   const int st = out.start[b];
   // Out-neighbours are taken 8 at a time: the 8 row loads of X are issued together, so a
@@ -66,14 +68,14 @@ __global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, in
   if (c < n) {
     double2 o = make_double2(scale * acc.x, scale * acc.y);
     if (Gadd) {
-      const double2 gv = *reinterpret_cast<const double2*>(Gadd + b * ldi + c);
+      const double2 gv = load_stream(Gadd + b * ldi + c);
       o.x += gv.x;
       o.y += gv.y;
     }
     if (c + 1 >= n) o.y = 0.0;
-    *reinterpret_cast<double2*>(Y + b * ldi + c) = o;
+    store_stream(Y + b * ldi + c, o);
     if (prev) {
-      const double2 pv = *reinterpret_cast<const double2*>(prev + b * ldi + c);
+      const double2 pv = load_stream(prev + b * ldi + c);
       diff = fmax(fabs(o.x - pv.x), (c + 1 < n) ? fabs(o.y - pv.y) : 0.0);
     }
   }
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(kB) void spmm_qt_rows_kernel(DevQ q, DevAdj out, in
     __syncthreads();
     if (threadIdx.x == 0) {
       double m = red[0];
-      for (int w = 1; w < kB / 64; ++w) m = fmax(m, red[w]);
+      for (int w = 1; w < kRowT / 64; ++w) m = fmax(m, red[w]);
       // the maximum only grows during a launch: skip the atomic when it is already larger
       const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
       if (__hip_atomic_load(maxdiff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < mb)
@@ -149,8 +151,8 @@ hipError_t launch_scatter_pairs_sym(double* G, int64_t n, int64_t np, const int3
 hipError_t launch_spmm_qt_rows(const DevQ& q, const DevAdj& out, int64_t n, const double* X,
                                double* Y, double scale, const double* Gadd, const double* prev,
                                unsigned long long* maxdiff, hipStream_t s) {
-  dim3 grid((unsigned)n, (unsigned)((n + 2 * kB - 1) / (2 * kB)));
-  spmm_qt_rows_kernel<<<grid, kB, 0, s>>>(q, out, n, ldi_of(n), X, Y, scale, Gadd, prev,
+  dim3 grid((unsigned)n, (unsigned)((n + 2 * kRowT - 1) / (2 * kRowT)));
+  spmm_qt_rows_kernel<<<grid, kRowT, 0, s>>>(q, out, n, ldi_of(n), X, Y, scale, Gadd, prev,
                                           maxdiff);
   return hipGetLastError();
 }

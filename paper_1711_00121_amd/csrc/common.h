@@ -60,6 +60,18 @@ struct DevQ {
   const double* W;  // row weight sums (weighted), or null
 };
 
+// Streaming (non-temporal) access to dense rows that are touched once per launch, so that
+// they do not displace gathered data from the caches.
+typedef double stream_dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 load_stream(const double* p) {
+  const stream_dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const stream_dbl2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void store_stream(double* p, double2 v) {
+  const stream_dbl2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<stream_dbl2*>(p));
+}
+
 __device__ __forceinline__ double wave_sum(double v, int width) {
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
   return v;

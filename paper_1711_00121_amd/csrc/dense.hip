@@ -182,14 +182,16 @@ __global__ void set_diag_kernel(SView S, DiagList dl) {
 
 // Y[a][c] = scale * (1/d_a) sum_{x in in(a)} X[x][c] (+ add_diag at c == a). X and Y use the
 // leading dimension ldi (a multiple of 64), rows and columns < n.
-__global__ __launch_bounds__(kB) void spmm_rows_kernel(DevQ q, int64_t n, int64_t ldi,
+constexpr int kRowT = 128;  // threads of a row-gather workgroup (2 columns each)
+
+__global__ __launch_bounds__(kRowT) void spmm_rows_kernel(DevQ q, int64_t n, int64_t ldi,
                                                        const double* __restrict__ X,
                                                        double* __restrict__ Y, double scale,
                                                        double add_diag,
                                                        const double* __restrict__ prev,
                                                        unsigned long long* maxdiff) {
   const int64_t a = blockIdx.x;
-  const int64_t c = ((int64_t)blockIdx.y * kB + threadIdx.x) * 2;
+  const int64_t c = ((int64_t)blockIdx.y * kRowT + threadIdx.x) * 2;
   const int len = q.in.len[a];
   const int st = q.in.start[a];
   // In-neighbours are taken 8 at a time with their row loads issued together (one memory
@@ -223,9 +225,9 @@ __global__ __launch_bounds__(kB) void spmm_rows_kernel(DevQ q, int64_t n, int64_
     if (c == a) o.x += add_diag;
     if (c + 1 == a) o.y += add_diag;
     if (c + 1 >= n) o.y = 0.0;
-    *reinterpret_cast<double2*>(Y + a * ldi + c) = o;
+    store_stream(Y + a * ldi + c, o);
     if (prev) {
-      const double2 pv = *reinterpret_cast<const double2*>(prev + a * ldi + c);
+      const double2 pv = load_stream(prev + a * ldi + c);
       diff = fmax(fabs(o.x - pv.x), (c + 1 < n) ? fabs(o.y - pv.y) : 0.0);
     }
   }
@@ -379,8 +381,8 @@ hipError_t launch_spmm_rows(const DevQ& q, int64_t n, const double* X, double* Y
                             double add_diag, const double* prev, unsigned long long* maxdiff,
                             hipStream_t s) {
   const int64_t ldi = init_ld(n);
-  dim3 grid((unsigned)n, (unsigned)((n + 2 * kB - 1) / (2 * kB)));
-  spmm_rows_kernel<<<grid, kB, 0, s>>>(q, n, ldi, X, Y, scale, add_diag, prev, maxdiff);
+  dim3 grid((unsigned)n, (unsigned)((n + 2 * kRowT - 1) / (2 * kRowT)));
+  spmm_rows_kernel<<<grid, kRowT, 0, s>>>(q, n, ldi, X, Y, scale, add_diag, prev, maxdiff);
   return hipGetLastError();
 }
 
