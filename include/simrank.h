@@ -80,7 +80,10 @@ typedef struct sr_config {
   int32_t batch_chunk;   /* low-rank blocks applied per fused pass of apply_batch (>= 1)   */
   int32_t fused_batch;   /* 1: apply_batch defers low-rank blocks into fused passes;
                             0: each block updates S on its own                              */
-  int32_t reserved;
+  int32_t split_rows;    /* graph rows (in- or out-lists) with more entries are traversed in
+                            chunks of 8192 entries, one workgroup each, whose partial sums a
+                            second small launch adds; rows of 2049 .. split_rows entries take
+                            one workgroup. 0 means 65536; otherwise at least 2048            */
 } sr_config;
 
 /* Per-update statistics (filled when a non-null pointer is passed; the call then

@@ -35,7 +35,7 @@ class sr_config(C.Structure):
         ("init_max_iter", C.c_int32),
         ("batch_chunk", C.c_int32),
         ("fused_batch", C.c_int32),
-        ("reserved", C.c_int32),
+        ("split_rows", C.c_int32),
     ]
 
 

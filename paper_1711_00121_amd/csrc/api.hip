@@ -17,6 +17,7 @@ using namespace sr;
 // Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
 // process them in chunks (see graph.hip).
 struct HeavySet {
+  int32_t split = kSplitRows;        // rows with more entries are huge (chunked)
   std::map<int32_t, int8_t> rows;    // listed row -> tier (1 medium, 2 heavy, 3 huge)
   std::map<int32_t, int32_t> cover;  // huge row -> entries its chunks cover
   std::vector<int32_t> med, heavy, huge, hfirst;
@@ -143,7 +144,7 @@ void heavy_touch(HeavySet& H, const SlotList& L, int32_t r) {
     }
     return;
   }
-  const int8_t tier = len > kHuge ? 3 : (len > kMedium ? 2 : 1);
+  const int8_t tier = len > H.split ? 3 : (len > kMedium ? 2 : 1);
   if (it == H.rows.end() || it->second != tier) {
     H.rows[r] = tier;
     H.dirty = true;
@@ -448,7 +449,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   if (case_id == 0) {
     // Q_old S[:, I]; in the same traversal F1 = out_old(supp S[I, :]) goes into B_0.
     HC(launch_spmv_q(q, hin, n_work, ctx->SI, ctx->QSI, 1.0, s, nullptr, 1.0,
-                     prune ? ctx->suppI : nullptr, prune ? B : nullptr));
+                     prune ? ctx->suppI : nullptr, prune ? B : nullptr, W));
     if (direct) {
       if (dj > 0) HC(launch_gather_inrows(ctx->S, n_work, q, j, ctx->zsum, s));
       HC(launch_direct_z(ga, n_work, ctx->SI, ctx->zsum, ctx->zbuf, s));
@@ -483,6 +484,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
     al.b0 = B;
     al.b1 = k >= 1 ? B + (int64_t)k * W : nullptr;
     al.bout = B + (int64_t)(k + 1) * W;
+    al.nwords = W;
     HC(launch_series_step(q_new, hin_new, n_work, P, pld, k, C, 1.0, prune ? &al : nullptr,
                           s, ctx->pairs, ctx->node_cap));
   }
@@ -649,6 +651,7 @@ sr_status sr_default_config(sr_config* cfg) {
   cfg->init_max_iter = 400;
   cfg->batch_chunk = 64;
   cfg->fused_batch = 1;
+  cfg->split_rows = kSplitRows;
   return SR_OK;
 }
 
@@ -695,8 +698,10 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   }
   if (!(cfg.C > 0.0 && cfg.C < 1.0) || cfg.K < 0 || cfg.K > 200 || cfg.K_ps < 0 ||
       cfg.s_prec < 0 || cfg.s_prec > 2 || (cfg.mode != SR_DENSE && cfg.mode != SR_COLUMN) ||
-      cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0)
+      cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0 ||
+      (cfg.split_rows != 0 && cfg.split_rows < kMedium))
     return SR_EINVAL;
+  if (cfg.split_rows == 0) cfg.split_rows = kSplitRows;
   if (cfg.batch_chunk == 0) cfg.batch_chunk = 64;
   if (cfg.init_max_iter <= 0) cfg.init_max_iter = 400;
   if (cfg.mode == SR_COLUMN && S0) return SR_EINVAL;
@@ -711,6 +716,7 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   sr_ctx* ctx = new (std::nothrow) sr_ctx();
   if (!ctx) return SR_ENOMEM;
   ctx->cfg = cfg;
+  ctx->hin.split = ctx->hout.split = cfg.split_rows;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->node_cap = node_cap;
   ctx->edge_cap = edge_cap;

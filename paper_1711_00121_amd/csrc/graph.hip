@@ -7,9 +7,9 @@
 //
 // Power-law rows, four tiers, all in 1024-thread workgroups of one launch: a row of at most
 // kLight entries is handled by a group of 8 lanes, a medium row (at most kMedium entries,
-// listed by the host) by one wave, a heavy row (at most kHuge) by a whole workgroup, and a
-// huge row is cut into chunks of kChunk entries, one workgroup each, whose partial sums a
-// second small launch adds in chunk order. Workgroups are ordered longest work first (chunks,
+// listed by the host) by one wave, a heavy row (up to the split threshold) by a whole
+// workgroup, and a huge row is cut into chunks of kChunk entries, one workgroup each, whose
+// partial sums a second small launch adds in chunk order. Workgroups are ordered longest work first (chunks,
 // heavy, medium, light) so that the long rows do not trail the launch. Each lane takes its
 // entries 8 or 16 at a time with all loads issued together, since the traversal is bound by
 // memory latency; every sum is reduced in a fixed order, with no cross-workgroup combine
@@ -52,11 +52,16 @@ struct Op {
   const uint32_t* b0;
   const uint32_t* b1;
   uint32_t* bout;
+  int64_t nwords;       // bitmap words, ceil(n / 32)
 };
+
+// Bitmaps are staged in LDS when the (a0 | a1, b0 | b1) words of all nodes fit in this many
+// bytes; a gather then reads LDS instead of four scattered global words.
+constexpr int64_t kLdsBitmapBytes = 48 * 1024;
 
 // Compile-time shape of one traversal: KIND (0: y = post (base + scale Q x); 1: series step;
 // 2: y = scale Q^T x), WT (weighted graph), AFF (0: no bitmaps; 1: bout only, from b0 | b1;
-// 2: aout and bout). Every instantiation is straight-line: no load sits under a branch, so
+// 2: aout and bout), LDSB (bitmaps staged in LDS). Every instantiation is straight-line: no load sits under a branch, so
 // no load waits for another that it does not depend on.
 template <int KIND, bool WT, int AFF>
 struct Shape {};
@@ -66,10 +71,11 @@ struct Shape {};
 // gathers (and bitmap words), are issued together; positions past p1 read entry p0 and are
 // masked out. A lane thus waits for two memory latencies per U entries instead of two per
 // entry.
-template <int U, int KIND, bool WT, int AFF>
+template <int U, int KIND, bool WT, int AFF, bool LDSB>
 __device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const DevAdj& L,
-                                           int64_t st, int p0, int p1, int lane, int step,
-                                           double& v0, double& v1, uint32_t& fa, uint32_t& fb) {
+                                           const uint32_t* lbits, int64_t st, int p0, int p1,
+                                           int lane, int step, double& v0, double& v1,
+                                           uint32_t& fa, uint32_t& fb) {
   for (int base = p0 + lane; base < p1; base += U * step) {
     int32_t x[U];
     double w[U];
@@ -108,16 +114,26 @@ __device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const Dev
       for (int u = 0; u < U; ++u) v0 += ok[u] ? w[u] * v[u] : 0.0;
     }
     if constexpr (AFF == 2) {
+      // staged words: lbits[2 w] = (a0 | a1)[w], lbits[2 w + 1] = (b0 | b1)[w]
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t wa = o.a0[x[u] >> 5] | o.a1[x[u] >> 5];
+        uint32_t wa, wb;
+        if constexpr (LDSB) {
+          const uint2 ab = reinterpret_cast<const uint2*>(lbits)[x[u] >> 5];
+          wa = ab.x;
+          wb = ab.y;
+        } else {
+          wa = o.a0[x[u] >> 5] | o.a1[x[u] >> 5];
+          wb = o.b0[x[u] >> 5] | o.b1[x[u] >> 5];
+        }
         fa |= ok[u] ? (wa >> (x[u] & 31)) & 1u : 0u;
+        fb |= ok[u] ? (wb >> (x[u] & 31)) & 1u : 0u;
       }
-    }
-    if constexpr (AFF >= 1) {
+    } else if constexpr (AFF == 1) {
+      // staged words: lbits[w] = (b0 | b1)[w]
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t wb = o.b0[x[u] >> 5] | o.b1[x[u] >> 5];
+        const uint32_t wb = LDSB ? lbits[x[u] >> 5] : (o.b0[x[u] >> 5] | o.b1[x[u] >> 5]);
         fb |= ok[u] ? (wb >> (x[u] & 31)) & 1u : 0u;
       }
     }
@@ -184,23 +200,40 @@ __device__ __forceinline__ void block_reduce(double& v0, double& v1, int& fw, do
 // Workgroup roles by block index, longest work first: [0, nchunk) chunks of huge rows,
 // then one workgroup per heavy row, then medium blocks (kWaves rows each), then light blocks
 // (kRowsPerBlock consecutive rows each; rows of other tiers are skipped there).
-template <int KIND, bool WT, int AFF>
+//
+// Affected-area bits: with LDSB every workgroup first copies the OR-ed source bitmaps of all
+// nodes into LDS (coalesced), so a gather reads one LDS word (pair) instead of two (four)
+// scattered global words. A light wave sets the bits of its 8 rows with one atomic per
+// bitmap; medium, heavy and huge rows set theirs one atomic per row.
+template <int KIND, bool WT, int AFF, bool LDSB>
 __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, int64_t n,
                                                       int64_t n_med_blocks, HeavyArgs h) {
   __shared__ double red0[kWaves], red1[kWaves];
   __shared__ int redf[kWaves];
+  extern __shared__ uint32_t lbits[];
   int64_t bid = blockIdx.x;
   const int lane64 = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   double v0 = 0.0, v1 = 0.0;
   uint32_t fa = 0, fb = 0;
+  if constexpr (LDSB && AFF > 0) {
+    for (int64_t w = threadIdx.x; w < o.nwords; w += kB) {
+      if constexpr (AFF == 2) {
+        lbits[2 * w] = o.a0[w] | o.a1[w];
+        lbits[2 * w + 1] = o.b0[w] | o.b1[w];
+      } else {
+        lbits[w] = o.b0[w] | o.b1[w];
+      }
+    }
+    __syncthreads();
+  }
   if (bid < h.nchunk) {
     // one chunk of a huge row: kChunk entries, 8 per thread, partial sums to the scratch
     const int2 c = h.chunk[bid];
     const int len = L.len[c.x];
     const int p1 = min(len, c.y + kChunk);
-    accumulate<kChunk / kB, KIND, WT, AFF>(o, q, L, L.start[c.x], c.y, p1, threadIdx.x, kB, v0,
-                                           v1, fa, fb);
+    accumulate<kChunk / kB, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[c.x], c.y, p1,
+                                                 threadIdx.x, kB, v0, v1, fa, fb);
     int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
     block_reduce(v0, v1, fw, red0, red1, redf);
     if (threadIdx.x == 0) {
@@ -211,11 +244,12 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
   }
   bid -= h.nchunk;
   if (bid < h.nheavy) {
-    // heavy row (kMedium < len <= kHuge): the whole workgroup, 8 entries per thread per pass
+    // heavy row (kMedium < len <= split threshold): the whole workgroup, 8 entries per thread
+    // per pass
     const int64_t row = h.heavy[bid];
     const int len = L.len[row];
-    accumulate<8, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, threadIdx.x, kB, v0, v1, fa,
-                                 fb);
+    accumulate<8, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len, threadIdx.x, kB,
+                                       v0, v1, fa, fb);
     int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
     block_reduce(v0, v1, fw, red0, red1, redf);
     if (threadIdx.x == 0) {
@@ -233,8 +267,8 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
     const int64_t row = h.med[mi];
     const int len = L.len[row];
     // (8 at a time with bitmaps, which would otherwise spill registers)
-    accumulate<AFF == 2 ? 8 : 16, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, lane64, 64,
-                                                 v0, v1, fa, fb);
+    accumulate<AFF == 2 ? 8 : 16, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len,
+                                                       lane64, 64, v0, v1, fa, fb);
     v0 = wave_sum(v0, 64);
     v1 = wave_sum(v1, 64);
     if constexpr (AFF > 0) {
@@ -260,8 +294,8 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
     len = L.len[row];
     mine = len <= kLight;
     if (mine)
-      accumulate<kLight / kG, KIND, WT, AFF>(o, q, L, L.start[row], 0, len, lane, kG, v0, v1,
-                                             fa, fb);
+      accumulate<kLight / kG, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len, lane,
+                                                   kG, v0, v1, fa, fb);
   }
   v0 = wave_sum(v0, kG);
   v1 = wave_sum(v1, kG);
@@ -271,10 +305,23 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
       fb |= (uint32_t)__shfl_xor((int)fb, s, kG);
     }
   }
-  if (mine && lane == 0) {
-    finish<KIND, WT>(o, q, row, len, v0, v1);
-    if (AFF == 2 && fa) bit_set_atomic(o.aout, row);
-    if (AFF >= 1 && fb) bit_set_atomic(o.bout, row);
+  if (mine && lane == 0) finish<KIND, WT>(o, q, row, len, v0, v1);
+  if constexpr (AFF > 0) {
+    // the wave's 8 rows start at a multiple of 8, so their bits share one word: gather the
+    // group leaders' flags (lanes 0, 8, .., 56) and set them with one atomic per bitmap
+    const uint64_t ma = __ballot(mine && lane == 0 && fa != 0);
+    const uint64_t mb = __ballot(mine && lane == 0 && fb != 0);
+    if (lane64 == 0) {
+      uint32_t ba = 0, bb = 0;
+#pragma unroll
+      for (int g = 0; g < 64 / kG; ++g) {
+        ba |= (uint32_t)((ma >> (kG * g)) & 1u) << g;
+        bb |= (uint32_t)((mb >> (kG * g)) & 1u) << g;
+      }
+      const int64_t r0 = bid * kRowsPerBlock + wid * (64 / kG);
+      if (AFF == 2 && ba) atomicOr(o.aout + (r0 >> 5), ba << (r0 & 31));
+      if (bb) atomicOr(o.bout + (r0 >> 5), bb << (r0 & 31));
+    }
   }
 }
 
@@ -305,7 +352,12 @@ hipError_t run_shape(const Op& o, const DevQ& q, const DevAdj& L, int64_t n,
   const int64_t nlb = (n + kRowsPerBlock - 1) / kRowsPerBlock;
   const int64_t nmb = ((int64_t)h.nmed + kWaves - 1) / kWaves;
   const int64_t grid = (int64_t)h.nchunk + h.nheavy + nmb + nlb;
-  traverse_kernel<KIND, WT, AFF><<<(unsigned)grid, kB, 0, s>>>(o, q, L, n, nmb, h);
+  const int64_t lds = AFF == 0 ? 0 : o.nwords * 4 * (AFF == 2 ? 2 : 1);
+  if (AFF > 0 && lds <= kLdsBitmapBytes)
+    traverse_kernel<KIND, WT, AFF, true><<<(unsigned)grid, kB, (size_t)lds, s>>>(o, q, L, n, nmb,
+                                                                                  h);
+  else
+    traverse_kernel<KIND, WT, AFF, false><<<(unsigned)grid, kB, 0, s>>>(o, q, L, n, nmb, h);
   if (h.nhuge > 0)
     traverse_combine_kernel<KIND, WT, AFF><<<(unsigned)((h.nhuge + 63) / 64), 64, 0, s>>>(
         o, q, L, h);
@@ -349,7 +401,8 @@ hipError_t launch_patch(const AdjPtrs& t, const Patch& p, hipStream_t s) {
 
 hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const double* x,
                          double* y, double scale, hipStream_t s, const double* base,
-                         double post, const uint32_t* fin, uint32_t* fout) {
+                         double post, const uint32_t* fin, uint32_t* fout, int64_t nwords) {
+  if (fout && nwords < (n + 31) / 32) return hipErrorInvalidValue;
   Op o = blank();
   o.kind = 0;
   o.x = x;
@@ -360,6 +413,7 @@ hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const dou
   o.b0 = fin;
   o.b1 = fin;
   o.bout = fout;
+  o.nwords = nwords;
   return run(o, q, q.in, n, h, s);
 }
 
@@ -397,6 +451,8 @@ hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, doub
   o.sx = sx;
   o.sy = sy;
   if (aff) {
+    if (aff->nwords < (n + 31) / 32) return hipErrorInvalidValue;
+    o.nwords = aff->nwords;
     o.a0 = aff->a0;
     o.a1 = aff->a1 ? aff->a1 : aff->a0;
     o.aout = aff->aout;

@@ -32,12 +32,14 @@ struct IdList {
 
 // ---------------------------------------------------------------------------------------
 // Sparse traversals. Rows with more than kLight entries are listed by the host: "medium"
-// rows (at most kMedium entries) are handled by one wave each, "heavy" rows (at most kHuge)
-// by a workgroup, and "huge" rows are cut into chunks of kChunk entries, one workgroup per
-// chunk, whose partial sums a second small launch adds up in chunk order.
+// rows (at most kMedium entries) are handled by one wave each, "heavy" rows (up to a split
+// threshold, kSplitRows by default) by a workgroup, and "huge" rows are cut into chunks of
+// kChunk entries, one workgroup per chunk, whose partial sums a second small launch adds up
+// in chunk order. The second launch costs a few microseconds, so only rows whose single
+// workgroup would trail the rest of the launch by more than that are split.
 constexpr int kLight = 64;
 constexpr int kMedium = 2048;
-constexpr int kHuge = 16384;
+constexpr int kSplitRows = 65536;
 constexpr int kChunk = 8192;
 struct HeavyArgs {
   const int32_t* med;    // medium row ids (device), ascending
@@ -61,13 +63,15 @@ struct AffLevel {
   const uint32_t* b0;
   const uint32_t* b1;
   uint32_t* bout;
+  int64_t nwords;  // words per bitmap (covers every node id that can appear in the lists)
 };
 // y[a] = post * (base[a] + scale * (Q x)[a]) for a < n (base may be null). When fout is set,
-// bit a of fout is also set if some in-neighbour x of a has bit x of fin (old-graph F1).
+// bit a of fout is also set if some in-neighbour x of a has bit x of fin (old-graph F1);
+// nwords as in AffLevel.
 hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const double* x,
                          double* y, double scale, hipStream_t s, const double* base = nullptr,
                          double post = 1.0, const uint32_t* fin = nullptr,
-                         uint32_t* fout = nullptr);
+                         uint32_t* fout = nullptr, int64_t nwords = 0);
 // y[b] = scale * (Q^T x)[b] = scale * sum_{a in out(b)} Q[a][b] x[a] (h: heavy out-rows).
 // The input comes pre-divided by the row weight of Q, xd[a] = x[a] / d[a] (d = in-degree, or
 // the in-weight sum when weighted; 0 where d[a] = 0), so an entry costs one gather; the

@@ -50,7 +50,7 @@ class Context:
     S (fixed point of eq (03a) on the device unless ``S0`` is given). Config keys follow
     ``sr_config``: C, K, K_ps, s_prec ('fp64' | 'hilo' | 'fp32'), mode ('dense' | 'column'),
     gamma_form ('closed' | 'direct'), prune, node_cap, edge_cap, init_tol, init_max_iter,
-    batch_chunk, fused_batch.
+    batch_chunk, fused_batch, split_rows.
     """
 
     def __init__(self, n, src, dst, weight=None, S0=None, stream=None, **config):

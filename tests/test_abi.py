@@ -48,7 +48,7 @@ def test_default_config_and_strerror():
     cfg = _lib.sr_config()
     assert L.sr_default_config(ctypes.byref(cfg)) == 0
     assert cfg.C == 0.6 and cfg.K == 15 and cfg.K_ps == 30 and cfg.prune == 1
-    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 64
+    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 64 and cfg.split_rows == 65536
     assert L.sr_strerror(-3) == b"edge exists"
     assert L.sr_default_config(None) == _lib.SR_EINVAL
 
@@ -73,6 +73,7 @@ int main(void) {
   printf("sr_update_stats %zu\n", sizeof(sr_update_stats));
   printf("sr_batch_stats %zu\n", sizeof(sr_batch_stats));
   F(sr_config, node_cap) F(sr_config, init_tol) F(sr_config, fused_batch)
+  F(sr_config, split_rows)
   F(sr_update_stats, bound) F(sr_batch_stats, pairs) F(sr_batch_stats, fused_passes)
   return 0;
 }

@@ -1,11 +1,11 @@
 """Parity on graphs whose rows exceed the traversals' chunking threshold.
 
-A row of more than 16,384 entries is cut into chunks of 8,192 entries, one workgroup per
-chunk, and a second launch adds the chunks' partial sums; a row of 2,049 to 16,384 entries
-takes one whole workgroup. The graph here is a Chung-Lu graph (n = 26,000) with two hubs: H1
-with 24,575 in-neighbours (three chunks, one entry short of the chunk table's cover) and
-20,000 out-neighbours, and H2 with 16,384 in-neighbours (the last length of the
-whole-workgroup tier). The updates make H1's in-list outgrow its chunk table, move H2 into
+With split_rows = 16,384, a row of more than 16,384 entries is cut into chunks of 8,192
+entries, one workgroup per chunk, and a second launch adds the chunks' partial sums; a row of
+2,049 to 16,384 entries takes one whole workgroup. The graph here is a Chung-Lu graph
+(n = 26,000) with two hubs: H1 with 24,575 in-neighbours (three chunks, one entry short of
+the chunk table's cover) and 20,000 out-neighbours, and H2 with 16,384 in-neighbours (the
+last length of the whole-workgroup tier). The updates make H1's in-list outgrow its chunk table, move H2 into
 the chunked tier and back, and run the column method over H1's chunked out-list.
 """
 import numpy as np
@@ -23,6 +23,7 @@ C = 0.6
 N = 26_000
 H1, H2 = 5, 7
 IN1, OUT1, IN2, OUT2 = 3 * 8192 - 1, 20_000, 16_384, 100
+SPLIT = 16_384
 
 
 def _say(*a):
@@ -61,7 +62,7 @@ def _check_columns(ctx, Q, cols, bar):
 def test_huge_rows_stream_pruned():
     s, d = _graph()
     a, b, c = _non_in_neighbours(s, d, H1, 3, seed=7003)
-    ctx = _ctx(N, s, d, C=C, K=15, s_prec="hilo", prune=True)
+    ctx = _ctx(N, s, d, C=C, K=15, s_prec="hilo", prune=True, split_rows=SPLIT)
     tr = EdgeTracker(N, s, d)
     Q0 = tr.Q()
     e2 = int(s[d == H2][0])  # an existing in-edge of H2
@@ -99,7 +100,7 @@ def test_huge_rows_column_mode():
     (i,) = _non_in_neighbours(s, d, H1, 1, seed=7005)
     K, Kps = 10, 30
     block = W.column_sample(N, 61, seed=7006, extra=[H1, H2, i])
-    ctx = _ctx(N, s, d, C=C, K=K, K_ps=Kps, mode="column")
+    ctx = _ctx(N, s, d, C=C, K=K, K_ps=Kps, mode="column", split_rows=SPLIT)
     _say(f"huge rows, column mode: insert ({i}, {H1}), {len(block)} columns")
     ctx.apply_edge_update(i, H1, 1)
     got = ctx.query_columns(block).double().cpu().numpy().T
@@ -126,7 +127,8 @@ def test_huge_rows_fused_batch():
             bi.append(x)
             bj.append(y)
     bo = [1] * len(bi)
-    ctx = _ctx(N, s, d, C=C, K=25, s_prec="hilo", fused_batch=True, batch_chunk=8)
+    ctx = _ctx(N, s, d, C=C, K=25, s_prec="hilo", fused_batch=True, batch_chunk=8,
+               split_rows=SPLIT)
     st = ctx.apply_batch(bi, bj, bo, stats=True)
     _say(f"huge rows, fused batch of {len(bi)} edges: {st['blocks']} blocks, "
          f"{st['fused_passes']} passes")
