@@ -70,24 +70,45 @@ struct Shape {};
 // `step` lanes. Entries are taken U at a time: the U index loads, then the U dependent
 // gathers (and bitmap words), are issued together; positions past p1 read entry p0 and are
 // masked out. A lane thus waits for two memory latencies per U entries instead of two per
-// entry.
-template <int U, int KIND, bool WT, int AFF, bool LDSB>
+// entry. With PIPE (rows of several passes) the index loads of the next pass are issued
+// right after the gathers of the current one, so a pass costs about one latency.
+template <int U, int KIND, bool WT, int AFF, bool LDSB, bool PIPE = false>
 __device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const DevAdj& L,
                                            const uint32_t* lbits, int64_t st, int p0, int p1,
                                            int lane, int step, double& v0, double& v1,
                                            uint32_t& fa, uint32_t& fb) {
-  for (int base = p0 + lane; base < p1; base += U * step) {
-    int32_t x[U];
-    double w[U];
-    bool ok[U];
+  // entries base, base + step, ..: positions at or past p1 read entry p0 (p0 < p1 wherever
+  // this runs)
+  auto load_idx = [&](int base, int32_t (&xx)[U], double (&ww)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = base + u * step;
-      ok[u] = p < p1;
-      const int64_t pc = st + (ok[u] ? p : p0);
-      x[u] = L.idx[pc];
-      w[u] = WT ? L.w[pc] : 1.0;
+      const int64_t pc = st + (p < p1 ? p : p0);
+      xx[u] = L.idx[pc];
+      ww[u] = WT ? L.w[pc] : 1.0;
     }
+  };
+  int32_t xn[U];
+  double wn[U];
+  int base = p0 + lane;
+  if (PIPE && base < p1) load_idx(base, xn, wn);
+  for (; base < p1; base += U * step) {
+    int32_t x[U];
+    double w[U];
+    bool ok[U];
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        x[u] = xn[u];
+        w[u] = wn[u];
+      }
+    } else {
+      load_idx(base, x, w);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) ok[u] = base + u * step < p1;
+    // next pass's indices (clamped, so the loads are unconditional)
+    if constexpr (PIPE) load_idx(base + U * step, xn, wn);
     if constexpr (KIND == 1) {
       double2 v[U];
 #pragma unroll
@@ -248,8 +269,12 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
     // per pass
     const int64_t row = h.heavy[bid];
     const int len = L.len[row];
-    accumulate<8, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len, threadIdx.x, kB,
-                                       v0, v1, fa, fb);
+    if (len > 8 * kB)  // several passes: pipelined index loads
+      accumulate<8, KIND, WT, AFF, LDSB, true>(o, q, L, lbits, L.start[row], 0, len,
+                                               threadIdx.x, kB, v0, v1, fa, fb);
+    else
+      accumulate<8, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len, threadIdx.x,
+                                         kB, v0, v1, fa, fb);
     int fw = (fa ? 1 : 0) | (fb ? 2 : 0);
     block_reduce(v0, v1, fw, red0, red1, redf);
     if (threadIdx.x == 0) {
@@ -266,9 +291,14 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
     if (mi >= h.nmed) return;
     const int64_t row = h.med[mi];
     const int len = L.len[row];
-    // (8 at a time with bitmaps, which would otherwise spill registers)
-    accumulate<AFF == 2 ? 8 : 16, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len,
-                                                       lane64, 64, v0, v1, fa, fb);
+    // (8 at a time with both bitmaps or weights, which would otherwise spill registers)
+    constexpr int UM = (AFF == 2 || WT) ? 8 : 16;
+    if (len > UM * 64)  // several passes: pipelined index loads
+      accumulate<UM, KIND, WT, AFF, LDSB, true>(o, q, L, lbits, L.start[row], 0, len, lane64,
+                                                64, v0, v1, fa, fb);
+    else
+      accumulate<UM, KIND, WT, AFF, LDSB>(o, q, L, lbits, L.start[row], 0, len, lane64, 64,
+                                          v0, v1, fa, fb);
     v0 = wave_sum(v0, 64);
     v1 = wave_sum(v1, 64);
     if constexpr (AFF > 0) {
