@@ -78,6 +78,10 @@ struct sr_ctx {
 
   double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) x node_cap
   double* xd = nullptr;    // PartialSim: two vectors x_t / d (d: row weight of Q), node_cap each
+  double* corr = nullptr;  // fused batches: correction vectors, 2 kCorrSlots x p_rows
+  double* corr_w = nullptr;  // their weights, 2 kCorrSlots x 64
+  int32_t* corr_tab = nullptr;  // slot table of a batch (rstart | sink | rows)
+  int64_t corr_tab_cap = 0;
 
   HeavySet hin, hout;      // heavy in-rows (Q) and out-rows (Q^T)
 
@@ -395,11 +399,16 @@ AffArgs aff_args(const sr_ctx* c, int64_t n) {
 // deferred block, gstride doubles apart (block-major, so that the series traversal of a block
 // gathers from rows of pld doubles). A block writes its (xi_k, eta_k) pairs into panel
 // r_prev / pld, and S_t columns are corrected by the r_prev deferred columns before gamma.
+// With incremental corrections, cI / cJ are the block's correction vectors (added to the
+// gathered columns) and the deferred panel is not read.
 struct FusedTarget {
   double* P;
   int64_t gstride;
   int pld;
   int r_prev;
+  bool incremental = false;
+  const double* cI = nullptr;
+  const double* cJ = nullptr;
 };
 
 // One low-rank block (Table 2 rows C0 insert/delete, or C2): gamma from the old S and graph,
@@ -433,8 +442,8 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   // S[:, I] (with supports) and S[:, j] from the old S.
   const IdList src_rows = idlist(I, 0, case_id == 0 ? I.size() : 0);
   HC(launch_gather_rows(ctx->S, n_work, src_rows, 0, j, ctx->SI, ctx->Sj, ctx->suppI,
-                        ctx->suppJ, s));
-  if (ft && ft->r_prev > 0)
+                        ctx->suppJ, s, ft ? ft->cI : nullptr, ft ? ft->cJ : nullptr));
+  if (ft && !ft->incremental && ft->r_prev > 0)
     HC(launch_panel_correct(ft->P, ft->pld, ft->gstride, ft->r_prev, n_work, src_rows, j, ctx->wts,
                             ctx->SI, ctx->Sj, s));
   const AffArgs aa = aff_args(ctx, n_work);
@@ -547,8 +556,9 @@ sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_
   hipStream_t s = ctx->stream;
   const double C = ctx->cfg.C;
   const IdList il = idlist(I, 0, I.size());
-  HC(launch_gather_rows(ctx->S, n_work, il, 0, -1, ctx->SI, nullptr, ctx->suppI, nullptr, s));
-  if (ft && ft->r_prev > 0)
+  HC(launch_gather_rows(ctx->S, n_work, il, 0, -1, ctx->SI, nullptr, ctx->suppI, nullptr, s,
+                        ft ? ft->cI : nullptr, nullptr));
+  if (ft && !ft->incremental && ft->r_prev > 0)
     HC(launch_panel_correct(ft->P, ft->pld, ft->gstride, ft->r_prev, n_work, il, -1, ctx->wts, ctx->SI,
                             nullptr, s));
   HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n_work, ctx->SI, ctx->ytmp,
@@ -669,12 +679,14 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)hipFree(ctx->S_mem[0]);
   (void)hipFree(ctx->S_mem[1]);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp,
-                  ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd};
+                  ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd, ctx->corr,
+                  ctx->corr_w};
   for (double* p : dd) (void)hipFree(p);
   uint32_t* bb[] = {ctx->suppI, ctx->suppJ, ctx->Abits, ctx->Bbits, ctx->Ahat, ctx->Bhat};
   for (uint32_t* p : bb) (void)hipFree(p);
   (void)hipFree(ctx->rowlist);
   (void)hipFree(ctx->d_ids);
+  (void)hipFree(ctx->corr_tab);
   heavy_free(ctx->hin);
   heavy_free(ctx->hout);
   (void)hipFree(ctx->d_cnt);
@@ -1179,8 +1191,83 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     q = 0;
     return SR_OK;
   };
+
+  // Incremental corrections (fused form, panel width 32 or 64): the blocks of a chunk that
+  // read columns of S (low-rank and C1 blocks) take slots. When a deferred block has its
+  // panel segment, it adds its terms to the correction vectors of the chunk's later slots
+  // (launch_corr_update); a block then reads S[:, I] and S[:, j] as the stored columns plus
+  // its two vectors, instead of correcting them from the whole deferred panel. The chunk
+  // boundaries are the flushes: after `chunk` deferred blocks, or before a block that would
+  // take more than kCorrSlots slots.
+  const bool incremental = fused && (ctx->pld == 32 || ctx->pld == 64);
+  std::vector<int> slot_of(plan.size(), -1), chunk_of(plan.size(), 0);
+  std::vector<char> flush_before(plan.size(), 0);
+  std::vector<int> chunk_base{0};  // first slot of chunk c; chunk c ends at chunk_base[c + 1]
+  std::vector<int32_t> rstart{0}, sinks, rows;
+  if (incremental) {
+    int cid = 0, nsl = 0, qp = 0, total = 0;
+    for (size_t bi = 0; bi < plan.size(); ++bi) {
+      const Block& b = plan[bi];
+      const bool low = b.case_id == 0 || b.case_id == 2;
+      const bool reads = low || b.case_id == 1;
+      if (reads && nsl == kCorrSlots) {
+        flush_before[bi] = 1;
+        ++cid;
+        chunk_base.push_back(total);
+        nsl = qp = 0;
+      }
+      chunk_of[bi] = cid;
+      if (reads) {
+        slot_of[bi] = total++;
+        ++nsl;
+        if (b.case_id != 2) rows.insert(rows.end(), b.I.begin(), b.I.end());
+        rstart.push_back((int32_t)rows.size());
+        sinks.push_back(low ? b.j : -1);
+      }
+      if (low && ++qp == chunk) {
+        ++cid;
+        chunk_base.push_back(total);
+        nsl = qp = 0;
+      }
+    }
+    chunk_base.push_back(total);
+    const int64_t ldc = ctx->p_rows;
+    if (!ctx->corr) {
+      if (dalloc(&ctx->corr, 2 * (int64_t)kCorrSlots * ldc) != hipSuccess ||
+          dalloc(&ctx->corr_w, 2 * (int64_t)kCorrSlots * 64) != hipSuccess)
+        return SR_ENOMEM;
+    }
+    // slot table: rstart | sink | rows, uploaded once per batch (after the previous batch's
+    // kernels, which read the old table, have run)
+    std::vector<int32_t> tab(rstart);
+    tab.insert(tab.end(), sinks.begin(), sinks.end());
+    tab.insert(tab.end(), rows.begin(), rows.end());
+    HC(hipStreamSynchronize(ctx->stream));
+    if ((int64_t)tab.size() > ctx->corr_tab_cap) {
+      (void)hipFree(ctx->corr_tab);
+      ctx->corr_tab = nullptr;
+      ctx->corr_tab_cap = 0;
+      const int64_t c = std::max<int64_t>(1024, 2 * (int64_t)tab.size());
+      if (hipMalloc((void**)&ctx->corr_tab, (size_t)c * 4) != hipSuccess) return SR_ENOMEM;
+      ctx->corr_tab_cap = c;
+    }
+    HC(hipMemcpy(ctx->corr_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
+  }
+  const int nslots = (int)sinks.size();
+  CorrSlots cs{};
+  if (incremental) {
+    cs.rstart = ctx->corr_tab;
+    cs.sink = ctx->corr_tab + nslots + 1;
+    cs.rows = ctx->corr_tab + 2 * nslots + 1;
+    cs.corr = ctx->corr;
+    cs.ldc = ctx->p_rows;
+    cs.w = ctx->corr_w;
+  }
+
   ctx->last_plan.clear();
-  for (const Block& b : plan) {
+  int cur_chunk = -1;
+  for (size_t bi = 0; bi < plan.size(); ++bi) {
+    const Block& b = plan[bi];
     bc[b.case_id]++;
     ctx->last_plan.push_back(b.case_id);
     ctx->last_plan.push_back(b.op);
@@ -1188,13 +1275,36 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     ctx->last_plan.push_back((int32_t)b.dj);
     ctx->last_plan.push_back((int32_t)b.I.size());
     for (int32_t i : b.I) ctx->last_plan.push_back(i);
+    if (incremental && flush_before[bi]) {
+      r = flush();
+      if (r != SR_OK) return r;
+    }
+    if (incremental && chunk_of[bi] != cur_chunk) {
+      // a new chunk: its slots' vectors start at zero
+      cur_chunk = chunk_of[bi];
+      cs.base = chunk_base[cur_chunk];
+      const int64_t nv = 2 * (int64_t)(chunk_base[cur_chunk + 1] - cs.base);
+      if (nv > 0) HC(hipMemsetAsync(ctx->corr, 0, (size_t)(nv * cs.ldc * 8), ctx->stream));
+    }
     FusedTarget ft{ctx->Pb, ctx->p_rows * ctx->pld, ctx->pld, q * ctx->pld};
+    ft.incremental = incremental;
+    if (incremental && slot_of[bi] >= 0) {
+      ft.cI = ctx->corr + (int64_t)2 * (slot_of[bi] - cs.base) * cs.ldc;
+      ft.cJ = ft.cI + cs.ldc;
+    }
     switch (b.case_id) {
       case 0:
       case 2:
         r = lowrank_block(ctx, b.case_id, b.op, b.I, b.j, n_new, nullptr, fused ? &ft : nullptr);
         ++lowrank;
         pairs += n_new * n_new;
+        if (r == SR_OK && incremental) {
+          // this block's terms for the chunk's later slots
+          const int s0 = slot_of[bi] + 1, s1 = chunk_base[chunk_of[bi] + 1];
+          if (s1 > s0)
+            HC(launch_corr_update(ctx->Pb + (int64_t)q * ctx->p_rows * ctx->pld, ctx->pld, n_new,
+                                  cs, s0, s1, ctx->stream));
+        }
         if (r == SR_OK && fused && ++q == chunk) r = flush();
         break;
       case 1:

@@ -31,7 +31,9 @@ __global__ __launch_bounds__(kB) void gather_rows_kernel(SView S, int64_t n, IdL
                                                          int32_t j, double* __restrict__ SI,
                                                          double* __restrict__ Sj,
                                                          uint32_t* __restrict__ suppI,
-                                                         uint32_t* __restrict__ suppJ) {
+                                                         uint32_t* __restrict__ suppJ,
+                                                         const double* __restrict__ cI,
+                                                         const double* __restrict__ cJ) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
   const bool in = a < n;
   double s = (in && acc) ? SI[a] : 0.0;
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(kB) void gather_rows_kernel(SView S, int64_t n, IdL
       s += v;
       sup |= (v != 0.0);
     }
-    SI[a] = s;
+    SI[a] = cI ? s + cI[a] : s;
   }
   const uint64_t bI = __ballot(sup);
   const int lane = threadIdx.x & 63;
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kB) void gather_rows_kernel(SView S, int64_t n, IdL
     bool supj = false;
     if (in) {
       const double v = s_get(S, (int64_t)j * S.ld + a);
-      Sj[a] = v;
+      Sj[a] = cJ ? v + cJ[a] : v;
       supj = v != 0.0;
     }
     const uint64_t bJ = __ballot(supj);
@@ -339,8 +341,8 @@ hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStrea
 
 hipError_t launch_gather_rows(SView S, int64_t n, const IdList& I, int acc, int32_t j,
                               double* SI, double* Sj, uint32_t* suppI, uint32_t* suppJ,
-                              hipStream_t s) {
-  gather_rows_kernel<<<g1(n), kB, 0, s>>>(S, n, I, acc, j, SI, Sj, suppI, suppJ);
+                              hipStream_t s, const double* cI, const double* cJ) {
+  gather_rows_kernel<<<g1(n), kB, 0, s>>>(S, n, I, acc, j, SI, Sj, suppI, suppJ, cI, cJ);
   return hipGetLastError();
 }
 

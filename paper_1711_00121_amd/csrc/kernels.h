@@ -92,9 +92,11 @@ hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, doub
 // Dense S helpers.
 // SI[a] = sum_{i in I} S[i][a] (accumulate when acc != 0), suppI |= (S[i][a] != 0);
 // when j >= 0 also Sj[a] = S[j][a], suppJ bit = (S[j][a] != 0).
+// cI / cJ (optional): corrections added to SI / Sj after the supports are taken.
 hipError_t launch_gather_rows(SView S, int64_t n, const IdList& I, int acc, int32_t j,
                               double* SI, double* Sj, uint32_t* suppI, uint32_t* suppJ,
-                              hipStream_t s);
+                              hipStream_t s, const double* cI = nullptr,
+                              const double* cJ = nullptr);
 // out[a] = sum_{x in in_old(j)} S[x][a] (rows of S for the in-neighbours of j).
 hipError_t launch_gather_inrows(SView S, int64_t n, const DevQ& q, int32_t j, double* out,
                                 hipStream_t s);
@@ -209,6 +211,28 @@ struct LowRankArgs {
                       // batch panel); column c of row a is at (c / pld) gstride + a pld + c % pld
 };
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
+// Fused batches, incremental form. The blocks of a chunk that read columns of S take slots;
+// slot s reads the sum of the columns I_s and the column j_s (j_s < 0: none), and keeps two
+// correction vectors of the chunk's deferred terms, corr[2 (s - base)] and
+// corr[2 (s - base) + 1], ldc doubles each. After a deferred block has written its panel
+// segment Pseg (n rows of pld doubles; columns at or past 2(K+1) zero), slots s0 .. s1 - 1
+// receive its part of those columns (eq (71) per column):
+//   corr[2 (s - base)][a]     += sum_c Pseg[a][c] sum_{i in I_s} Pseg[i][c ^ 1]
+//   corr[2 (s - base) + 1][a] += sum_c Pseg[a][c] Pseg[j_s][c ^ 1]
+// pld must be 32 or 64 (other widths: hipErrorInvalidValue; the caller then corrects from
+// the whole panel with launch_panel_correct).
+constexpr int kCorrSlots = 192;  // slots per chunk at most (a chunk is cut before more)
+struct CorrSlots {
+  const int32_t* rstart;  // rows of slot s: rows[rstart[s] .. rstart[s + 1])
+  const int32_t* rows;
+  const int32_t* sink;    // j_s or -1
+  double* corr;
+  int64_t ldc;
+  int32_t base;           // first slot of the chunk
+  double* w;              // scratch: 2 (s1 - s0) pld doubles
+};
+hipError_t launch_corr_update(const double* Pseg, int pld, int64_t n, const CorrSlots& c,
+                              int s0, int s1, hipStream_t s);
 // Fused batches: the columns S_t[:, c] of the current S are the stored S plus the deferred
 // blocks' terms sum_{col < r} P[:, col] P[c, col ^ 1]. wts[col] = sum_{i in I} P[i][col ^ 1]
 // and wts[r + col] = P[j][col ^ 1] (j < 0: no second vector), then

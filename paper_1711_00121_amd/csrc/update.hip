@@ -455,6 +455,64 @@ __global__ __launch_bounds__(256) void panel_gemv_kernel(const double* __restric
   }
 }
 
+// Incremental corrections of a fused chunk (the declaration states the sums). Weights first:
+// one thread per (vector, panel column).
+__global__ __launch_bounds__(256) void corr_weights_kernel(const double* __restrict__ Pseg,
+                                                          int pld, CorrSlots c, int s0, int s1) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int nv = 2 * (s1 - s0);
+  if (t >= nv * pld) return;
+  const int v = t / pld, col = t % pld;
+  const int slot = s0 + v / 2;
+  const int cs = col ^ 1;
+  double w = 0.0;
+  if ((v & 1) == 0) {
+    for (int p = c.rstart[slot]; p < c.rstart[slot + 1]; ++p)
+      w += Pseg[(int64_t)c.rows[p] * pld + cs];
+  } else {
+    const int j = c.sink[slot];
+    if (j >= 0) w = Pseg[(int64_t)j * pld + cs];
+  }
+  c.w[t] = w;
+}
+
+// One thread per row a: the row's PW panel entries stay in registers, the weights of up to
+// kCorrVB vectors at a time are staged in LDS (every lane reads the same word), and each
+// vector's entry a is read, increased and written back (coalesced over a).
+constexpr int kCorrVB = 64;
+template <int PW>
+__global__ __launch_bounds__(256) void corr_update_kernel(const double* __restrict__ Pseg,
+                                                         int64_t n, CorrSlots c, int s0,
+                                                         int s1) {
+  __shared__ double lw[kCorrVB * PW];
+  const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool in = a < n;
+  double p[PW];
+  const double2* row = reinterpret_cast<const double2*>(Pseg + (in ? a : 0) * PW);
+#pragma unroll
+  for (int q = 0; q < PW / 2; ++q) {
+    const double2 v = row[q];
+    p[2 * q] = v.x;
+    p[2 * q + 1] = v.y;
+  }
+  const int nv = 2 * (s1 - s0);
+  double* out = c.corr + (int64_t)2 * (s0 - c.base) * c.ldc + a;
+  for (int v0 = 0; v0 < nv; v0 += kCorrVB) {
+    const int vb = min(kCorrVB, nv - v0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < vb * PW; e += 256) lw[e] = c.w[(int64_t)v0 * PW + e];
+    __syncthreads();
+    if (in) {
+      for (int v = 0; v < vb; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < PW; ++q) acc += p[q] * lw[v * PW + q];
+        out[(int64_t)(v0 + v) * c.ldc] += acc;
+      }
+    }
+  }
+}
+
 // Column output for one block (r <= RC panel columns, float32):
 //     out[p][b] = sum_{c < r} P[rows[p]][c] P[b][c ^ 1]   (Delta S[b][rows[p]], eq (71))
 // for list positions p < nrows and nodes b < ncols. The tiling is the streaming kernel's
@@ -561,6 +619,22 @@ hipError_t launch_panel_correct(const double* P, int pld, int64_t gstride, int r
   panel_gemv_kernel<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(P, pld, gstride, r, n, wts,
                                                             I.count ? SI : nullptr,
                                                             j >= 0 ? Sj : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_update(const double* Pseg, int pld, int64_t n, const CorrSlots& c,
+                              int s0, int s1, hipStream_t s) {
+  if (pld != 32 && pld != 64) return hipErrorInvalidValue;
+  if (s1 <= s0 || n <= 0) return hipSuccess;
+  const int nt = 2 * (s1 - s0) * pld;
+  corr_weights_kernel<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(Pseg, pld, c, s0, s1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (pld == 32)
+    corr_update_kernel<32><<<grid, 256, 0, s>>>(Pseg, n, c, s0, s1);
+  else
+    corr_update_kernel<64><<<grid, 256, 0, s>>>(Pseg, n, c, s0, s1);
   return hipGetLastError();
 }
 
