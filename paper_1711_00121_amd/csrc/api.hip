@@ -78,8 +78,9 @@ struct sr_ctx {
 
   double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) x node_cap
   double* xd = nullptr;    // PartialSim: two vectors x_t / d (d: row weight of Q), node_cap each
-  double* corr = nullptr;  // fused batches: correction vectors, 2 kCorrSlots x p_rows
-  double* corr_w = nullptr;  // their weights, 2 kCorrSlots x 64
+  int corr_slots = 0;      // fused batches: slots per chunk at most (2 batch_chunk + 32)
+  double* corr = nullptr;  // correction vectors, 2 corr_slots x p_rows
+  double* corr_w = nullptr;  // their weights, 2 corr_slots x 64
   int32_t* corr_tab = nullptr;  // slot table of a batch (rstart | sink | rows)
   int64_t corr_tab_cap = 0;
 
@@ -1198,8 +1199,14 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   // (launch_corr_update); a block then reads S[:, I] and S[:, j] as the stored columns plus
   // its two vectors, instead of correcting them from the whole deferred panel. The chunk
   // boundaries are the flushes: after `chunk` deferred blocks, or before a block that would
-  // take more than kCorrSlots slots.
+  // take more than corr_slots slots (C1 blocks between the deferred ones also take slots).
   const bool incremental = fused && (ctx->pld == 32 || ctx->pld == 64);
+  if (incremental && !ctx->corr) {
+    ctx->corr_slots = 2 * chunk + 32;
+    if (dalloc(&ctx->corr, 2 * (int64_t)ctx->corr_slots * ctx->p_rows) != hipSuccess ||
+        dalloc(&ctx->corr_w, 2 * (int64_t)ctx->corr_slots * 64) != hipSuccess)
+      return SR_ENOMEM;
+  }
   std::vector<int> slot_of(plan.size(), -1), chunk_of(plan.size(), 0);
   std::vector<char> flush_before(plan.size(), 0);
   std::vector<int> chunk_base{0};  // first slot of chunk c; chunk c ends at chunk_base[c + 1]
@@ -1210,7 +1217,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
       const Block& b = plan[bi];
       const bool low = b.case_id == 0 || b.case_id == 2;
       const bool reads = low || b.case_id == 1;
-      if (reads && nsl == kCorrSlots) {
+      if (reads && nsl == ctx->corr_slots) {
         flush_before[bi] = 1;
         ++cid;
         chunk_base.push_back(total);
@@ -1231,12 +1238,6 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
       }
     }
     chunk_base.push_back(total);
-    const int64_t ldc = ctx->p_rows;
-    if (!ctx->corr) {
-      if (dalloc(&ctx->corr, 2 * (int64_t)kCorrSlots * ldc) != hipSuccess ||
-          dalloc(&ctx->corr_w, 2 * (int64_t)kCorrSlots * 64) != hipSuccess)
-        return SR_ENOMEM;
-    }
     // slot table: rstart | sink | rows, uploaded once per batch (after the previous batch's
     // kernels, which read the old table, have run)
     std::vector<int32_t> tab(rstart);

@@ -220,8 +220,7 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
 //   corr[2 (s - base)][a]     += sum_c Pseg[a][c] sum_{i in I_s} Pseg[i][c ^ 1]
 //   corr[2 (s - base) + 1][a] += sum_c Pseg[a][c] Pseg[j_s][c ^ 1]
 // pld must be 32 or 64 (other widths: hipErrorInvalidValue; the caller then corrects from
-// the whole panel with launch_panel_correct).
-constexpr int kCorrSlots = 192;  // slots per chunk at most (a chunk is cut before more)
+// the whole panel with launch_panel_correct). The caller caps the slots of a chunk.
 struct CorrSlots {
   const int32_t* rstart;  // rows of slot s: rows[rstart[s] .. rstart[s + 1])
   const int32_t* rows;
