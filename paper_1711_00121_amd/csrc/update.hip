@@ -42,6 +42,9 @@ struct Raw {
   float h;
 };
 
+// NT: non-temporal store (S entries that one launch writes exactly once).
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+
 template <int PREC>
 __device__ __forceinline__ void sload(const SView& S, int64_t off, Raw<PREC>& x) {
   if constexpr (PREC == PREC_FP64) {
@@ -60,15 +63,23 @@ __device__ __forceinline__ double sval(const Raw<PREC>& x) {
   else return (double)x.h;
 }
 
-template <int PREC>
+template <int PREC, bool NT = false>
 __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
   if constexpr (PREC == PREC_FP64) {
-    S.d[off] = t;
+    if constexpr (NT) __builtin_nontemporal_store(t, S.d + off);
+    else S.d[off] = t;
   } else if constexpr (PREC == PREC_HILO) {
     const float h = (float)t;
-    S.hl[off] = make_float2(h, (float)(t - (double)h));
+    const float l = (float)(t - (double)h);
+    if constexpr (NT) {
+      const nt_float2 v = {h, l};
+      __builtin_nontemporal_store(v, reinterpret_cast<nt_float2*>(S.hl + off));
+    } else {
+      S.hl[off] = make_float2(h, l);
+    }
   } else {
-    S.hi[off] = (float)t;
+    if constexpr (NT) __builtin_nontemporal_store((float)t, S.hi + off);
+    else S.hi[off] = (float)t;
   }
 }
 
@@ -86,6 +97,9 @@ __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
 // afterwards: a load under a branch is followed by a full wait and serialises the tile.
 constexpr int SC = 64;
 constexpr int ST = SC / 16;
+// The updated entries are stored non-temporally (measured: 8% faster at n = 20k and 50k);
+// non-temporal loads of the same entries were 30-50% slower.
+constexpr bool kStripNTStore = true;
 
 template <int PREC, bool MASK, bool HASROWS>
 __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
@@ -218,7 +232,7 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
       for (int t = 0; t < ST; ++t) {
         if (!((on >> t) & 1)) continue;
         const int64_t b = c0 + t * 16 + l16;
-        sput<PREC>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
+        sput<PREC, kStripNTStore>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
       }
     }
 #pragma unroll
