@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--max-batch", type=int, default=4096)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--split-rows", type=int, default=0,
+                    help="graph rows above this many entries are traversed in chunks "
+                         "(0: the library default)")
     ap.add_argument("--plain-edges", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -102,6 +105,7 @@ def run_batch(args):
     batches, counts = W.batch_stream(n, s, d, nb, args.max_batch, seed=2003)
     t0 = time.perf_counter()
     ctx = Context(n, s, d, C=C, K=K, s_prec="hilo", node_cap=counts[-1] + 64,
+                  split_rows=args.split_rows,
                   edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
                   fused_batch=not args.no_fused, batch_chunk=args.chunk)
     torch.cuda.synchronize()
@@ -269,7 +273,7 @@ def run_columns(args):
     cols = W.column_sample(n, cfg["columns"], seed=3004)[:cfg["columns"]]
     blocks = [cols[b:b + cfg["block"]] for b in range(0, len(cols), cfg["block"])]
     ctx = Context(n, s, d, C=C, K=K, K_ps=Kps, mode="column",
-                  edge_cap=m + args.warmup + steps + 1024)
+                  edge_cap=m + args.warmup + steps + 1024, split_rows=args.split_rows)
     out_buf = torch.empty((cfg["block"], n), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
 
