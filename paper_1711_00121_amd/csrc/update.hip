@@ -517,11 +517,20 @@ __global__ __launch_bounds__(256) void corr_update_kernel(const double* __restri
     for (int e = threadIdx.x; e < vb * PW; e += 256) lw[e] = c.w[(int64_t)v0 * PW + e];
     __syncthreads();
     if (in) {
-      for (int v = 0; v < vb; ++v) {
-        double acc = 0.0;
+      // 8 vectors at a time: their 8 loads are issued together (positions past vb reload the
+      // last vector and are not stored)
+      for (int v = 0; v < vb; v += 8) {
+        double cur[8];
 #pragma unroll
-        for (int q = 0; q < PW; ++q) acc += p[q] * lw[v * PW + q];
-        out[(int64_t)(v0 + v) * c.ldc] += acc;
+        for (int u = 0; u < 8; ++u) cur[u] = out[(int64_t)(v0 + min(v + u, vb - 1)) * c.ldc];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int vv = min(v + u, vb - 1);
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < PW; ++q) acc += p[q] * lw[vv * PW + q];
+          if (v + u < vb) out[(int64_t)(v0 + v + u) * c.ldc] = cur[u] + acc;
+        }
       }
     }
   }
