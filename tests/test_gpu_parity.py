@@ -324,6 +324,37 @@ def test_errors_leave_state_unchanged():
     assert np.array_equal(ctx.S().cpu().numpy(), S0)
 
 
+def test_fused_batch_slot_cap_flushes_early():
+    """A chunk holds at most 2 chunk + 32 blocks that read columns of S; one more forces an
+    early fused pass. One C0 insertion (deferred) followed by 40 insertions into 40 new sinks
+    (C1 blocks, which read the deferred block's corrections) with batch_chunk = 3 (cap 38):
+    the 38th reading block flushes the chunk with its one deferred block (the batch's only
+    fused pass), and the last C1 blocks start a new chunk whose corrections are zero. S must
+    match the oracle's Inc-bSR at the same K."""
+    n = 300
+    K = 15
+    s, d = W.chung_lu(n, 1500, seed=65)
+    es = set(zip(s.tolist(), d.tolist()))
+    g = W.rng(66)
+    while True:
+        i, j = (int(v) for v in g.integers(n, size=2))
+        if i != j and (i, j) not in es:
+            break
+    srcs = g.choice(n, size=40, replace=True)
+    bi = [i] + [int(x) for x in srcs]
+    bj = [j] + list(range(n, n + 40))
+    bo = [1] * len(bi)
+    ctx = ctx_for(n, s, d, s_prec="fp64", node_cap=n + 40, fused_batch=True, batch_chunk=3,
+                  K=K)
+    st = ctx.apply_batch(bi, bj, bo, stats=True)
+    assert st["blocks_case"][0] == 1 and st["blocks_case"][1] == 40
+    assert st["fused_passes"] == 1 and st["lowrank_blocks"] == 1
+    S_or, _ = OI.inc_bsr(n, s.astype(np.int64), d.astype(np.int64),
+                         O.fixed_point(Gr.transition_matrix(n, s, d), C), bi, bj, bo, C, K)
+    assert maxabs(ctx.S().cpu().numpy(), S_or) < 1e-12
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "hilo"])
 @pytest.mark.parametrize("chunk", [1, 3, 64])
 def test_fused_batches_match_oracle(prec, chunk):
