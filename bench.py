@@ -53,6 +53,8 @@ def main():
                     help="graph rows above this many entries are traversed in chunks "
                          "(0: the library default)")
     ap.add_argument("--plain-edges", type=int, default=24)
+    ap.add_argument("--case-edges", type=int, default=4,
+                    help="single edges timed per case C0-C3 on the plain path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -162,6 +164,40 @@ def run_batch(args):
     plain_ms, plain_launches = ctx.profile_read(reset=True)
     ctx.profile(False)
 
+    from paper_1711_00121_amd._lib import SR_EEXIST, SimRankError
+    # Per case (Table 2 rows C0-C3), single edges on the plain path: an edge between existing
+    # nodes, into a new sink, from a new source, and between two new nodes (ids dense).
+    per_case = {}
+    rng = np.random.default_rng(4203)
+    es_cur = set()
+    for case in ("C0", "C1", "C2", "C3"):
+        times = []
+        for _ in range(args.case_edges):
+            n_cur = ctx.sizes()[0]
+            if case == "C0":
+                while True:
+                    a, b = (int(v) for v in rng.integers(n_cur, size=2))
+                    if a != b and (a, b) not in es_cur:
+                        break
+                es_cur.add((a, b))
+            elif case == "C1":
+                a, b = int(rng.integers(n_cur)), n_cur
+            elif case == "C2":
+                a, b = n_cur, int(rng.integers(n_cur))
+            else:
+                a, b = n_cur, n_cur + 1
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            try:
+                ctx.apply_edge_update(a, b, 1)
+            except SimRankError as e:  # an existing edge drawn for C0: skip it
+                if e.status != SR_EEXIST:
+                    raise
+                continue
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t2) * 1e3)
+        per_case[case] = round(float(np.mean(times)), 3) if times else None
+
     edge_rate = edges / dt
     plain_edge_rate = len(sample) / dt_plain if sample else None
     nf = float(np.mean(n_nodes))
@@ -197,6 +233,7 @@ def run_batch(args):
                             "fused": not args.no_fused})
     out.update({
         "edge_updates_per_s": edge_rate, "edges": edges, "lowrank_blocks": lowrank,
+        "plain_ms_per_edge_by_case": per_case,
         "fused_passes": passes,
         "plain_gpu": {"edges": len(sample), "edge_updates_per_s": plain_edge_rate,
                       "pair_updates_per_s": plain_pairs / dt_plain if sample else None,

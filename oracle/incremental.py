@@ -21,6 +21,7 @@ Readings taken where the paper is silent or garbled (each one listed in the desi
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 
 from .graph import in_degrees, out_neighbours, transition_matrix
 
@@ -71,6 +72,9 @@ def rank_one_block(Q, d, I, j, op):
     n = Q.shape[0]
     delta = len(I)
     eI = indicator(n, I)
+    Qj = Q[j, :]
+    if sp.issparse(Qj):
+        Qj = np.asarray(Qj.todense()).ravel()
     u = np.zeros(n)
     if op > 0:
         if d[j] == 0:
@@ -78,14 +82,14 @@ def rank_one_block(Q, d, I, j, op):
             v = eI / delta
         else:
             u[j] = delta / (d[j] + delta)
-            v = eI / delta - Q[j, :]
+            v = eI / delta - Qj
     else:
         if d[j] == delta:
             u[j] = 1.0
             v = -eI / delta
         else:
             u[j] = delta / (d[j] - delta)
-            v = Q[j, :] - eI / delta
+            v = Qj - eI / delta
     return u, v
 
 
@@ -582,6 +586,54 @@ def delta_columns_c0(n, src, dst, i, j, cols, C, K, K_ps):
         m += np.outer(xi, eta[cols])
         nn += np.outer(eta, xi[cols])
     return m + nn
+
+
+def delta_columns_batch(n, src, dst, bi, bj, bop, cols, C, K, K_ps):
+    """Columns ``Delta S[:, x]`` (x in ``cols``) of a batch of edge insertions and deletions
+    between existing nodes, block by block in linear memory: the plan of Algorithm 6
+    (net update, deletions first, sink-grouped blocks) with the column method of Algorithm 7
+    inside each block. For block (I, j, op) on the graph as the earlier blocks left it,
+    PartialSim (depth ``K_ps``) gives ``S[:, I] = sum_{i in I} S[:, i]`` and ``S[:, j]``;
+    Table 2 row (C0) gives u, v and gamma; the series of eq (16a) gives xi_k, eta_k; and
+    eq (71) adds ``sum_k (eta_k[x] xi_k + xi_k[x] eta_k)`` to column x. Then the block's
+    edges are applied. A batch that creates nodes raises ValueError.
+
+    Returns an ``n x len(cols)`` array.
+    """
+    from .simrank import partial_sim
+    plan, n_new = plan_batch(n, src, dst, bi, bj, bop)
+    if n_new != n or any(b["case"] != 0 for b in plan):
+        raise ValueError("every edge of the batch must join existing nodes")
+    cols = np.asarray(cols, dtype=np.int64)
+    es = set(zip(np.asarray(src).tolist(), np.asarray(dst).tolist()))
+    out = np.zeros((n, len(cols)))
+    for blk in plan:
+        s_arr = np.asarray([a for a, _ in es], dtype=np.int64)
+        d_arr = np.asarray([b for _, b in es], dtype=np.int64)
+        Q = transition_matrix(n, s_arr, d_arr)
+        d = in_degrees(n, s_arr, d_arr)
+        I, j, op = list(blk["I"]), blk["j"], blk["op"]
+        SI = np.zeros(n)
+        for i in I:
+            SI += partial_sim(Q, i, K_ps, C)
+        Sj = partial_sim(Q, j, K_ps, C)
+        gamma = gamma_closed_parts(Q @ SI, Sj, float(SI[I].sum()), float(Sj[j]), int(d[j]),
+                                   len(I), j, C, op)
+        u, v = rank_one_block(Q, d, I, j, op)
+        xi = np.zeros(n)
+        xi[j] = C
+        eta = gamma
+        for k in range(K + 1):
+            out += np.outer(xi, eta[cols]) + np.outer(eta, xi[cols])
+            if k < K:
+                xi, eta = (C * (Q @ xi) + C * float(v @ xi) * u,
+                           Q @ eta + float(v @ eta) * u)
+        for i in I:
+            if op > 0:
+                es.add((i, j))
+            else:
+                es.remove((i, j))
+    return out
 
 
 def inc_sr_all_p_column(n, src, dst, S_col_x, x, edges, C, K):

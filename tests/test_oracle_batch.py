@@ -5,6 +5,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 import workloads as W
 from oracle import graph as Gr
@@ -125,3 +126,72 @@ def test_algorithm7_column_all_cases():
                                     [1] * len(edges))
         S2 = O.fixed_point(Gr.transition_matrix(n2, s2, d2), C)
         assert np.abs(col - S2[:, x]).max() < 1e-13
+
+
+def _mixed_existing_batch(n, s, d, seed, n_ins=10, n_del=6, shared=3):
+    """Insertions of non-edges (some sharing a sink) and deletions of existing edges,
+    all between existing nodes."""
+    g = W.rng(seed)
+    es = set(zip(s.tolist(), d.tolist()))
+    bi, bj, bo = [], [], []
+    sink = int(g.integers(n))
+    while len(bi) < n_ins:
+        a = int(g.integers(n))
+        b = sink if len(bi) < shared else int(g.integers(n))
+        if a != b and (a, b) not in es and (a, b) not in zip(bi, bj):
+            bi.append(a)
+            bj.append(b)
+            bo.append(1)
+    for e in g.choice(len(s), size=n_del, replace=False).tolist():
+        bi.append(int(s[e]))
+        bj.append(int(d[e]))
+        bo.append(-1)
+    return bi, bj, bo
+
+
+def test_column_batch_matches_recompute():
+    """Algorithm 6's blocks with the column method inside (deep K and PartialSim depth):
+    the summed Delta S columns equal the difference of the converged S of the two graphs."""
+    n = 60
+    s, d = W.chung_lu(n, 240, seed=73)
+    bi, bj, bo = _mixed_existing_batch(n, s, d, seed=74)
+    cols = [0, 3, bj[0], bi[0], 59]
+    got = I.delta_columns_batch(n, s.astype(np.int64), d.astype(np.int64), bi, bj, bo, cols,
+                                C, 70, 70)
+    n2, s2, d2 = Gr.apply_edges(n, s, d, bi, bj, bo)
+    S_new = O.fixed_point(Gr.transition_matrix(n2, s2, d2), C)
+    S_old = O.fixed_point(Gr.transition_matrix(n, s, d), C)
+    assert np.abs(got - (S_new - S_old)[:, cols]).max() < 1e-13
+
+
+def test_column_batch_single_edge_is_the_unit_column_method():
+    n = 60
+    s, d = W.chung_lu(n, 240, seed=75)
+    ii, jj = W.insertion_stream(n, s, d, 1, seed=76)
+    i, j = int(ii[0]), int(jj[0])
+    cols = [1, 2, i, j]
+    a = I.delta_columns_batch(n, s.astype(np.int64), d.astype(np.int64), [i], [j], [1], cols,
+                              C, 10, 30)
+    b = I.delta_columns_c0(n, s.astype(np.int64), d.astype(np.int64), i, j, cols, C, 10, 30)
+    assert np.abs(a - b).max() < 1e-15
+
+
+def test_column_batch_equals_dense_inc_bsr_at_depth():
+    """At deep K the column form of the batch and the dense Inc-bSR give the same Delta S
+    columns (the dense form starts from the converged S)."""
+    n = 60
+    s, d = W.chung_lu(n, 240, seed=77)
+    bi, bj, bo = _mixed_existing_batch(n, s, d, seed=78)
+    cols = list(range(0, n, 7))
+    S_old = O.fixed_point(Gr.transition_matrix(n, s, d), C)
+    S_new, _ = I.inc_bsr(n, s.astype(np.int64), d.astype(np.int64), S_old, bi, bj, bo, C, 70)
+    got = I.delta_columns_batch(n, s.astype(np.int64), d.astype(np.int64), bi, bj, bo, cols,
+                                C, 70, 70)
+    assert np.abs(got - (S_new - S_old)[:, cols]).max() < 1e-12
+
+
+def test_column_batch_rejects_new_nodes():
+    n = 20
+    s, d = W.chung_lu(n, 60, seed=79)
+    with pytest.raises(ValueError):
+        I.delta_columns_batch(n, s, d, [1], [n], [1], [0], C, 5, 5)
