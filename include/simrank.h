@@ -149,6 +149,23 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
 sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* src, const int32_t* dst,
                       const int8_t* op, sr_batch_stats* stats);
 
+/* Column mode: applies a batch of edge insertions and deletions between existing nodes and
+ * returns the columns of its Delta S, memory-efficiently: Algorithm 6's plan (as
+ * apply_batch) with the column method of Algorithm 7 inside every block (PartialSim of
+ * S[:, I] and S[:, j] on the graph as the earlier blocks left it, Table 2 row C0, the K-step
+ * series of eq (16a)), and eq (71) summed over the blocks:
+ *   out_dev[t * ld_out + a] = Delta S[a][cols[t]]   (float64, t < ncols, a < n).
+ * cols: host array of node ids (< n); out_dev: device, ncols x ld_out float64, ld_out >= n,
+ * overwritten (entries past n of a row are set to zero). Memory: batch_chunk deferred
+ * panels of n x 2(K+1) doubles (rounded up to 32), then one FP64 matrix-core pass over them
+ * per chunk. SR_EMODE outside column mode, for a weighted graph, or when an edge would create
+ * a node; SR_ERANGE for a column id out of range; otherwise as apply_batch (validation errors
+ * change nothing). stats: NULL, or filled after synchronising. */
+sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* src,
+                              const int32_t* dst, const int8_t* op, const int32_t* cols,
+                              int32_t ncols, double* out_dev, int64_t ld_out,
+                              sr_batch_stats* stats);
+
 /* Writes column x as n float64 values to out_dev (device). what = SR_COL_S: the current
  * S[:, x] (dense mode). what = SR_COL_DELTA: Delta S[:, x] of the last apply_edge_update
  * (both modes; eq (71): M_K[:, x] + M_K[x, :]^T). */

@@ -605,11 +605,10 @@ def delta_columns_batch(n, src, dst, bi, bj, bop, cols, C, K, K_ps):
     if n_new != n or any(b["case"] != 0 for b in plan):
         raise ValueError("every edge of the batch must join existing nodes")
     cols = np.asarray(cols, dtype=np.int64)
-    es = set(zip(np.asarray(src).tolist(), np.asarray(dst).tolist()))
+    s_arr = np.asarray(src, dtype=np.int64)
+    d_arr = np.asarray(dst, dtype=np.int64)
     out = np.zeros((n, len(cols)))
     for blk in plan:
-        s_arr = np.asarray([a for a, _ in es], dtype=np.int64)
-        d_arr = np.asarray([b for _, b in es], dtype=np.int64)
         Q = transition_matrix(n, s_arr, d_arr)
         d = in_degrees(n, s_arr, d_arr)
         I, j, op = list(blk["I"]), blk["j"], blk["op"]
@@ -628,11 +627,13 @@ def delta_columns_batch(n, src, dst, bi, bj, bop, cols, C, K, K_ps):
             if k < K:
                 xi, eta = (C * (Q @ xi) + C * float(v @ xi) * u,
                            Q @ eta + float(v @ eta) * u)
-        for i in I:
-            if op > 0:
-                es.add((i, j))
-            else:
-                es.remove((i, j))
+        # the block's edges i -> j, i in I
+        if op > 0:
+            s_arr = np.concatenate([s_arr, np.asarray(I, dtype=np.int64)])
+            d_arr = np.concatenate([d_arr, np.full(len(I), j, dtype=np.int64)])
+        else:
+            drop = (d_arr == j) & np.isin(s_arr, np.asarray(I, dtype=np.int64))
+            s_arr, d_arr = s_arr[~drop], d_arr[~drop]
     return out
 
 

@@ -80,6 +80,8 @@ SIGNATURES = {
     "apply_edge_update": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(sr_update_stats)]),
     "apply_batch": (C.c_int, [P, C.c_int64, I32P, I32P, I8P, C.POINTER(sr_batch_stats)]),
+    "apply_batch_columns": (C.c_int, [P, C.c_int64, I32P, I32P, I8P, I32P, C.c_int32, P,
+                                      C.c_int64, C.POINTER(sr_batch_stats)]),
     "query_column": (C.c_int, [P, C.c_int32, C.c_int32, P]),
     "query_columns": (C.c_int, [P, I32P, C.c_int32, P, C.c_int64]),
     "sr_gather_pairs": (C.c_int, [P, C.c_int64, P, P, P]),

@@ -601,7 +601,9 @@ sr_status c3_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j) {
 // PartialSim (section 7): column q of the K_ps-term SimRank into out (n values).
 // x_0 = e_q, x_t = Q^T x_{t-1} (t = 1..K); y = x_K, y <- x_{K-t} + C Q y (t = 1..K); (1 - C) y.
 // The Q^T products read x_{t-1} divided by the row weights of Q (two alternating buffers).
-sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
+// With several ids the start is their indicator, and by linearity the result is the sum of
+// their columns (S[:, I] of Table 2).
+sr_status partial_sim(sr_ctx* ctx, const IdList& ids, double* out) {
   const int64_t n = ctx->g.n;
   const int Kp = ctx->cfg.K_ps > 0 ? ctx->cfg.K_ps : ctx->cfg.K;
   const double C = ctx->cfg.C;
@@ -610,7 +612,7 @@ sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
   const DevAdj out_l = devout(ctx);
   auto x = [&](int t) { return ctx->xs + (int64_t)t * ctx->node_cap; };
   auto xd = [&](int t) { return ctx->xd + (int64_t)(t & 1) * ctx->node_cap; };
-  HC(launch_unit_vector(x(0), n, q, s, &dq, xd(0)));
+  HC(launch_indicator(x(0), n, ids, s, &dq, xd(0)));
   const HeavyArgs hin = heavy_args(ctx->hin), hout = heavy_args(ctx->hout);
   for (int t = 1; t <= Kp; ++t)
     HC(launch_spmv_qt(dq, out_l, hout, n, xd(t - 1), x(t), t < Kp ? xd(t) : nullptr, 1.0, s));
@@ -622,6 +624,13 @@ sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
   }
   if (Kp == 0) HC(hipMemcpyAsync(out, x(0), (size_t)n * 8, hipMemcpyDeviceToDevice, s));
   return SR_OK;
+}
+
+sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
+  IdList l;
+  l.count = 1;
+  l.id[0] = q;
+  return partial_sim(ctx, l, out);
 }
 
 bool valid_ctx(sr_ctx* c) { return c != nullptr; }
@@ -1332,6 +1341,128 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     stats->lowrank_blocks = lowrank;
     stats->n_after = n_new;
     stats->pairs = pairs;
+    stats->fused_passes = passes;
+  }
+  return SR_OK;
+}
+
+sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t* bj,
+                              const int8_t* bo, const int32_t* cols, int32_t ncols,
+                              double* out_dev, int64_t ld_out, sr_batch_stats* stats) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (cnt < 0 || (cnt > 0 && (!bi || !bj || !bo)) || ncols < 0 ||
+      (ncols > 0 && (!cols || !out_dev)))
+    return SR_EINVAL;
+  if (ctx->cfg.mode != SR_COLUMN || ctx->weighted) return SR_EMODE;
+  const int64_t n = ctx->g.n;
+  if (ld_out < n) return SR_EINVAL;
+  for (int32_t t = 0; t < ncols; ++t)
+    if (cols[t] < 0 || cols[t] >= n) return SR_ERANGE;
+  std::vector<Block> plan;
+  int64_t n_new = 0, net_edges = 0;
+  sr_status r = plan_batch(ctx, cnt, bi, bj, bo, plan, n_new, net_edges);
+  if (r != SR_OK) return r;
+  if (n_new != n) return SR_EMODE;
+  for (const Block& b : plan)
+    if (b.case_id != 0) return SR_EMODE;
+
+  hipStream_t s = ctx->stream;
+  const double C = ctx->cfg.C;
+  const int K = ctx->cfg.K;
+  const int pld = ctx->pld;
+  const int chunk = ctx->cfg.batch_chunk > 0 ? ctx->cfg.batch_chunk : 1;
+  const int64_t gstride = ctx->p_rows * pld;
+  // deferred panels (block-major); columns past 2(K+1) and rows past n stay zero
+  if (!ctx->Pb) {
+    if (dalloc(&ctx->Pb, gstride * chunk) != hipSuccess) return SR_ENOMEM;
+    HC(hipMemsetAsync(ctx->Pb, 0, (size_t)gstride * chunk * 8, s));
+  }
+  if (ncols > 0) {
+    if (ctx->ids_cap < ncols) {
+      HC(hipStreamSynchronize(s));
+      (void)hipFree(ctx->d_ids);
+      ctx->d_ids = nullptr;
+      ctx->ids_cap = 0;
+      if (dalloc(&ctx->d_ids, ncols) != hipSuccess) return SR_ENOMEM;
+      ctx->ids_cap = ncols;
+    }
+    HC(hipStreamSynchronize(s));
+    HC(hipMemcpy(ctx->d_ids, cols, (size_t)ncols * 4, hipMemcpyHostToDevice));
+    HC(hipMemsetAsync(out_dev, 0, (size_t)ncols * ld_out * 8, s));
+  }
+  int q = 0, passes = 0;
+  auto flush = [&]() -> sr_status {
+    if (q == 0 || ncols == 0) {
+      q = 0;
+      return SR_OK;
+    }
+    LowRankArgs la{};
+    la.P = ctx->Pb;
+    la.pld = pld;
+    la.gstride = gstride;
+    la.p_rows = ctx->p_rows;
+    la.r = q * pld;
+    la.rows = ctx->d_ids;
+    la.nrows = ncols;
+    la.ncols = n;
+    la.acc_out = out_dev;
+    la.ld_out = ld_out;
+    HC(profiled(ctx, [&]() { return launch_lowrank_acc(la, s); }));
+    ++passes;
+    q = 0;
+    return SR_OK;
+  };
+  ctx->last_plan.clear();
+  for (const Block& b : plan) {
+    ctx->last_plan.push_back(b.case_id);
+    ctx->last_plan.push_back(b.op);
+    ctx->last_plan.push_back(b.j);
+    ctx->last_plan.push_back((int32_t)b.dj);
+    ctx->last_plan.push_back((int32_t)b.I.size());
+    for (int32_t i : b.I) ctx->last_plan.push_back(i);
+    double* P = ctx->Pb + (int64_t)q * gstride;
+    // S[:, I] and S[:, j] on the current graph (PartialSim), Q S[:, I], then Table 2 (C0)
+    const IdList il = idlist(b.I, 0, b.I.size());
+    r = partial_sim(ctx, il, ctx->SI);
+    if (r == SR_OK) r = partial_sim(ctx, b.j, ctx->Sj);
+    if (r != SR_OK) return r;
+    HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->QSI, 1.0, s));
+    GammaArgs ga{};
+    ga.kind = 0;
+    ga.op = b.op;
+    ga.j = b.j;
+    ga.delta = (int32_t)b.I.size();
+    ga.dj = ctx->g.in.len[b.j];
+    ga.C = C;
+    ga.xi0 = C;
+    ga.I = il;
+    HC(launch_gamma(ga, n, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, P, pld, nullptr, s));
+    std::vector<std::pair<int32_t, int32_t>> e;
+    for (int32_t i : b.I) e.push_back({i, b.j});
+    r = edit_graph(ctx, e, b.op);
+    if (r != SR_OK) return r;
+    for (int k = 0; k < K; ++k)
+      HC(launch_series_step(devq(ctx), heavy_args(ctx->hin), n, P, pld, k, C, 1.0, nullptr, s,
+                            ctx->pairs, ctx->node_cap));
+    if (++q == chunk) {
+      r = flush();
+      if (r != SR_OK) return r;
+    }
+  }
+  r = flush();
+  if (r != SR_OK) return r;
+  ctx->last_r = 0;  // the single-update series state no longer describes the graph
+  if (stats) {
+    HC(hipStreamSynchronize(s));
+    memset(stats, 0, sizeof(*stats));
+    stats->edges_in = cnt;
+    stats->edges_net = net_edges;
+    stats->blocks = (int64_t)plan.size();
+    stats->blocks_case[0] = (int64_t)plan.size();
+    stats->lowrank_blocks = (int64_t)plan.size();
+    stats->n_after = n;
+    stats->pairs = (int64_t)plan.size() * n * ncols;
     stats->fused_passes = passes;
   }
   return SR_OK;

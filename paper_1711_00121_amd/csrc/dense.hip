@@ -289,18 +289,21 @@ __global__ __launch_bounds__(kB) void rows_to_f32_kernel(SView S, int64_t n,
   if (a < n) out[t * ld_out + a] = (float)s_get(S, (int64_t)rows[t] * S.ld + a);
 }
 
-__global__ __launch_bounds__(kB) void unit_vector_kernel(double* x, int64_t n, int32_t q,
-                                                         DevQ dq, double* xd) {
+// x = indicator of the ids (sum of e_i); with xd, also xd[a] = x[a] / d[a] (0 where d[a] = 0)
+__global__ __launch_bounds__(kB) void indicator_kernel(double* x, int64_t n, IdList ids, DevQ dq,
+                                                       double* xd) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (a >= n) return;
-  x[a] = (a == q) ? 1.0 : 0.0;
+  double v = 0.0;
+  for (int t = 0; t < ids.count; ++t) v = (ids.id[t] == a) ? 1.0 : v;
+  x[a] = v;
   if (xd) {
-    double v = 0.0;
-    if (a == q) {
+    double r = 0.0;
+    if (v != 0.0) {
       const double d = dq.W ? dq.W[a] : (double)dq.in.len[a];
-      v = d > 0.0 ? 1.0 / d : 0.0;
+      r = d > 0.0 ? v / d : 0.0;
     }
-    xd[a] = v;
+    xd[a] = r;
   }
 }
 
@@ -320,10 +323,10 @@ inline unsigned g1(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
 }  // namespace
 
-hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s, const DevQ* dq,
-                              double* xd) {
+hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t s,
+                            const DevQ* dq, double* xd) {
   if (n <= 0) return hipSuccess;
-  unit_vector_kernel<<<g1(n), kB, 0, s>>>(x, n, q, dq ? *dq : DevQ{}, dq ? xd : nullptr);
+  indicator_kernel<<<g1(n), kB, 0, s>>>(x, n, ids, dq ? *dq : DevQ{}, dq ? xd : nullptr);
   return hipGetLastError();
 }
 

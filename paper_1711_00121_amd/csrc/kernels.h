@@ -209,8 +209,14 @@ struct LowRankArgs {
   int64_t p_rows;     // rows allocated in P (rows past the written ones are zero)
   int64_t gstride;    // doubles between consecutive groups of pld columns (block-major
                       // batch panel); column c of row a is at (c / pld) gstride + a pld + c % pld
+  double* acc_out;    // launch_lowrank_acc: float64 output, ld_out doubles per row
 };
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
+// Column mode, batches: acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1] for list
+// positions p < nrows and nodes a < ncols (the deferred blocks' Delta S[a][rows[p]], eq (71)),
+// on FP64 matrix cores. P is block-major (gstride); r and pld multiples of 16; P holds at least
+// ncols rounded up to 128 rows.
+hipError_t launch_lowrank_acc(const LowRankArgs& a, hipStream_t s);
 // Fused batches, incremental form. The blocks of a chunk that read columns of S take slots;
 // slot s reads the sum of the columns I_s and the column j_s (j_s < 0: none), and keeps two
 // correction vectors of the chunk's deferred terms, corr[2 (s - base)] and
@@ -261,9 +267,10 @@ hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const d
                             double C, const int32_t* slot_edge, double* dq, double* dw,
                             hipStream_t s);
 // Small helpers.
-// x = e_q; with dq, also xd = e_q / d[q] (d as for launch_spmv_qt; 0 when d[q] = 0).
-hipError_t launch_unit_vector(double* x, int64_t n, int32_t q, hipStream_t s,
-                              const DevQ* dq = nullptr, double* xd = nullptr);
+// x = sum of e_i over the ids (distinct); with dq, also xd[a] = x[a] / d[a], d the in-degree
+// (or the in-weight sum when weighted), 0 where d[a] = 0.
+hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t s,
+                            const DevQ* dq = nullptr, double* xd = nullptr);
 hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
 hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);

@@ -286,16 +286,26 @@ __device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64
   J = i + (t - (i * T - i * (i - 1) / 2));
 }
 
-template <int PREC>
+// RECT (column mode, batches): a rectangular product accumulated into a float64 output,
+//     acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1]   (p < nrows, a < ncols),
+// over T row tiles (list positions) x TJ column tiles (nodes), without the symmetry; A rows
+// are gathered through the list (positions past it read its last entry, not stored).
+template <int PREC, bool RECT = false>
 __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
-                                                          int64_t per) {
+                                                          int64_t per, int64_t TJ = 0) {
   __shared__ double As[2][GT * GP];
   __shared__ double Bs[2][GT * GP];
   const int64_t w = blockIdx.x;
   const int64_t t = (w % NXCD) * per + w / NXCD;
-  if (t >= T * (T + 1) / 2) return;
   int64_t I, J;
-  tri_tile(t, T, I, J);
+  if constexpr (RECT) {
+    if (t >= T * TJ) return;
+    I = t / TJ;
+    J = t % TJ;
+  } else {
+    if (t >= T * (T + 1) / 2) return;
+    tri_tile(t, T, I, J);
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -310,13 +320,25 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
   const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
   const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
   const int64_t ustep = GR * (int64_t)g.pld;
+  // RECT: the A rows of this thread, gathered through the list
+  int64_t arow[RECT ? GL : 1];
+  if constexpr (RECT) {
+#pragma unroll
+    for (int u = 0; u < GL; ++u) {
+      const int64_t p = r0 + lrow + GR * u;
+      arow[u] = (int64_t)g.rows[p < g.nrows ? p : g.nrows - 1] * g.pld + lcol;
+    }
+  }
   double2 ra[GL], rb[GL];
   auto load = [&](int ch) {
     // chunk ch: columns [ch GC, ch GC + GC) lie in column group (ch GC) / pld
     const int64_t cb = (int64_t)((ch * GC) / g.pld) * g.gstride + (ch * GC) % g.pld;
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
+      if constexpr (RECT)
+        ra[u] = *reinterpret_cast<const double2*>(g.P + arow[u] + cb);
+      else
+        ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
       rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
     }
   };
@@ -362,6 +384,34 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
     __builtin_amdgcn_sched_barrier(0);
     store(buf ^ 1);
     __syncthreads();
+  }
+
+  if constexpr (RECT) {
+    // acc_out[p][a] += acc, one row sub-tile at a time (loads first, then the stores)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double x[4][4];
+      int on[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t p = r0 + wr * 64 + s * 16 + v * 4 + lk;
+          const int64_t b = c0 + wc * 64 + q * 16 + l16;
+          on[q][v] = p < g.nrows && b < g.ncols;
+          x[q][v] = g.acc_out[on[q][v] ? p * g.ld_out + b : 0];
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (!on[q][v]) continue;
+          const int64_t p = r0 + wr * 64 + s * 16 + v * 4 + lk;
+          const int64_t b = c0 + wc * 64 + q * 16 + l16;
+          g.acc_out[p * g.ld_out + b] = x[q][v] + acc[s][q][v];
+        }
+    }
+    return;
   }
 
   // S[a][b] += acc and S[b][a] += acc, one row sub-tile at a time: the direct and the
@@ -754,6 +804,20 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   } else {
     lowrank_gemm_kernel<PREC_FP32><<<grid, NT, 0, s>>>(a, T, per);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_lowrank_acc(const LowRankArgs& a, hipStream_t s) {
+  if (a.nrows <= 0 || a.ncols <= 0 || a.r <= 0) return hipSuccess;
+  if (a.rows == nullptr || a.acc_out == nullptr || a.r % GC != 0 || a.pld % GC != 0 ||
+      a.ld_out < a.ncols)
+    return hipErrorInvalidValue;
+  const int64_t T = (a.nrows + GT - 1) / GT;
+  const int64_t TJ = (a.ncols + GT - 1) / GT;
+  if (a.p_rows < TJ * GT) return hipErrorInvalidValue;
+  const int64_t tiles = T * TJ;
+  const int64_t per = (tiles + NXCD - 1) / NXCD;
+  lowrank_gemm_kernel<PREC_FP64, true><<<(unsigned)(per * NXCD), NT, 0, s>>>(a, T, per, TJ);
   return hipGetLastError();
 }
 

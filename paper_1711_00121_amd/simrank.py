@@ -99,6 +99,28 @@ class Context:
         out["blocks_case"] = list(s.blocks_case)
         return out
 
+    def apply_batch_columns(self, src, dst, op, cols, out=None, stats=False):
+        """Column mode: applies a batch between existing nodes and returns the float64 Delta S
+        columns of the whole batch as rows, ``out[t, :] = Delta S[:, cols[t]]``."""
+        n, _ = self.sizes()
+        src = _i32(src)
+        dst = _i32(dst)
+        cols = _i32(cols)
+        op = np.ascontiguousarray(np.asarray(op, dtype=np.int8))
+        if out is None:
+            out = torch.empty((len(cols), n), dtype=torch.float64, device="cuda")
+        s = L.sr_batch_stats() if stats else None
+        st = self.lib.apply_batch_columns(self.h, int(len(src)), _ptr(src, C.c_int32),
+                                          _ptr(dst, C.c_int32), _ptr(op, C.c_int8),
+                                          _ptr(cols, C.c_int32), int(len(cols)), _dev(out),
+                                          out.stride(0), C.byref(s) if s is not None else None)
+        L.check(st, "apply_batch_columns")
+        if s is None:
+            return out
+        info = {f: getattr(s, f) for f, _ in L.sr_batch_stats._fields_}
+        info["blocks_case"] = list(s.blocks_case)
+        return out, info
+
     # ------------------------------------------------------------------ queries
     def sizes(self):
         n = C.c_int64()

@@ -140,6 +140,37 @@ def test_fullsize_columns_n1m():
 
 
 @pytest.mark.gpu
+def test_fullsize_column_batch_n1m():
+    """Column mode at n = 1M: a batch of 12 insertions (6 into one sink) and 4 deletions
+    between existing nodes, one 8,192-column block, against the oracle's same block-by-block
+    column method on sampled columns."""
+    cfg = W.WORKLOADS[4]
+    n, m, K, Kps = cfg["n"], cfg["m"], cfg["K"], cfg["K_ps"]
+    _say(f"column batch n={n} m={m} K={K} K_ps={Kps}: generating")
+    s, d = W.chung_lu(n, m, seed=1004)
+    bi, bj, bo = W.existing_batch(n, s, d, n_ins=12, n_del=4, shared=6, seed=2104)
+    block = W.column_sample(n, cfg["block"] - 2, seed=3004,
+                            extra=[int(bi[0]), int(bj[0])])[:cfg["block"]]
+    ctx = _ctx(n, s, d, C=C, K=K, K_ps=Kps, mode="column")
+    out, st = ctx.apply_batch_columns(bi, bj, bo, block, stats=True)
+    torch.cuda.synchronize()
+    _say(f"batch of {len(bi)} edges: {st['blocks']} blocks, {st['fused_passes']} passes")
+    pick = np.unique(np.concatenate([[0, len(block) - 1],
+                                     W.rng(6104).choice(len(block), 6, replace=False),
+                                     np.nonzero((block == bi[0]) | (block == bj[0]))[0]]))
+    got = out[torch.as_tensor(pick, device="cuda")].cpu().numpy().T
+    del out
+    ref = OI.delta_columns_batch(n, s.astype(np.int64), d.astype(np.int64), bi, bj, bo,
+                                 block[pick], C, K, Kps)
+    err = maxabs(got, ref)
+    scale = float(np.abs(ref).max())
+    _say(f"{len(block)}-column block: max |dS_gpu - dS_oracle| over {len(pick)} columns = "
+         f"{err:.3e}; max |dS| = {scale:.3e}")
+    assert scale > 0.0 and err < 1e-12 * scale + 1e-15
+    ctx.close()
+
+
+@pytest.mark.gpu
 def test_fullsize_adjoint_n20k():
     cfg = W.WORKLOADS[5]
     n, m = cfg["n"], cfg["m"]

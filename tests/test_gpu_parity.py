@@ -258,6 +258,70 @@ def test_column_mode_delta_columns():
         cur_s, cur_d = s2.astype(np.int64), d2.astype(np.int64)
 
 
+def _existing_batch(n, s, d, seed, n_ins, n_del, shared):
+    """Insertions of non-edges (the first `shared` into one sink) and deletions of existing
+    edges, all between existing nodes."""
+    g = W.rng(seed)
+    es = set(zip(s.tolist(), d.tolist()))
+    bi, bj, bo = [], [], []
+    sink = int(g.integers(n))
+    while len(bi) < n_ins:
+        a = int(g.integers(n))
+        b = sink if len(bi) < shared else int(g.integers(n))
+        if a != b and (a, b) not in es and (a, b) not in set(zip(bi, bj)):
+            bi.append(a)
+            bj.append(b)
+            bo.append(1)
+    for e in g.choice(len(s), size=n_del, replace=False).tolist():
+        bi.append(int(s[e]))
+        bj.append(int(d[e]))
+        bo.append(-1)
+    return bi, bj, bo
+
+
+@pytest.mark.parametrize("chunk", [1, 64])
+def test_column_batch_matches_oracle(chunk):
+    """Column mode, a batch between existing nodes: Algorithm 6's blocks with the column
+    method inside, summed over the blocks on FP64 matrix cores, against the oracle's same
+    computation (same K and PartialSim depth) on a ragged shape (n = 1500 nodes, 70 columns);
+    chunk 1 runs one pass per block, chunk 64 one pass for the batch."""
+    n, K, Kps = 1500, 10, 30
+    s, d = W.chung_lu(n, 9000, seed=91)
+    bi, bj, bo = _existing_batch(n, s, d, seed=92, n_ins=14, n_del=6, shared=4)
+    cols = W.column_sample(n, 66, seed=93, extra=[bj[0], bi[0], 0, n - 1])[:70]
+    ctx = ctx_for(n, s, d, mode="column", K=K, K_ps=Kps, batch_chunk=chunk)
+    out, st = ctx.apply_batch_columns(bi, bj, bo, cols, stats=True)
+    got = out.cpu().numpy().T
+    ref = OI.delta_columns_batch(n, s.astype(np.int64), d.astype(np.int64), bi, bj, bo, cols, C,
+                                 K, Kps)
+    scale = np.abs(ref).max()
+    assert scale > 0 and maxabs(got, ref) < 1e-12 * scale + 1e-15
+    assert st["fused_passes"] == -(-st["lowrank_blocks"] // chunk)
+    assert ctx.sizes() == (n, len(s) + 14 - 6)
+    ctx.close()
+
+
+def test_column_batch_rejections_leave_state():
+    n = 300
+    s, d = W.chung_lu(n, 1200, seed=94)
+    ctx = ctx_for(n, s, d, mode="column", K=5, K_ps=10, node_cap=n + 8)
+    from paper_1711_00121_amd._lib import SR_EMODE, SR_ERANGE, SimRankError
+    with pytest.raises(SimRankError) as e:
+        ctx.apply_batch_columns([1, 2], [n, 3], [1, 1], [0, 1])   # creates node n
+    assert e.value.status == SR_EMODE
+    with pytest.raises(SimRankError) as e:
+        ctx.apply_batch_columns([1], [2] if (1, 2) not in set(zip(s.tolist(), d.tolist()))
+                                else [3], [1], [0, n])
+    assert e.value.status == SR_ERANGE
+    assert ctx.sizes() == (n, len(s))
+    dense = ctx_for(n, s, d, s_prec="fp64")
+    with pytest.raises(SimRankError) as e:
+        dense.apply_batch_columns([1], [2], [1], [0])
+    assert e.value.status == SR_EMODE
+    ctx.close()
+    dense.close()
+
+
 @pytest.mark.parametrize("K,n", [(0, 700), (3, 701), (4, 700), (6, 702), (8, 700), (10, 703),
                                  (12, 700), (15, 701)])
 def test_column_kernel_every_depth(K, n):

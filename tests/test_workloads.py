@@ -63,3 +63,19 @@ def test_with_hubs_exact_degrees():
     assert np.array_equal(s2, s3) and np.array_equal(d2, d3)
     with pytest.raises(ValueError):
         W.with_hubs(n, s2, d2, [(3, 10, 10)], seed=93)
+
+
+def test_existing_batch_valid():
+    n = 500
+    s, d = W.chung_lu(n, 2500, seed=95)
+    bi, bj, bo = W.existing_batch(n, s, d, n_ins=12, n_del=5, shared=4, seed=96)
+    es = set(zip(s.tolist(), d.tolist()))
+    ins = [(a, b) for a, b, o in zip(bi.tolist(), bj.tolist(), bo.tolist()) if o > 0]
+    dels = [(a, b) for a, b, o in zip(bi.tolist(), bj.tolist(), bo.tolist()) if o < 0]
+    assert len(ins) == 12 and len(dels) == 5
+    assert len(set(ins)) == 12 and not (set(ins) & es) and all(a != b for a, b in ins)
+    assert len(set(dels)) == 5 and set(dels) <= es
+    assert len({b for _, b in ins[:4]}) == 1
+    assert np.all(bi < n) and np.all(bj < n)
+    b2 = W.existing_batch(n, s, d, n_ins=12, n_del=5, shared=4, seed=96)
+    assert all(np.array_equal(x, y) for x, y in zip((bi, bj, bo), b2))

@@ -33,6 +33,7 @@ __all__ = [
     "loss_pairs",
     "column_sample",
     "with_hubs",
+    "existing_batch",
     "rng",
 ]
 
@@ -344,3 +345,27 @@ def with_hubs(n, src, dst, hubs, seed):
                 add_d.extend(pick.tolist())
     return (np.concatenate([src, np.asarray(add_s, dtype=np.int64)]).astype(np.int32),
             np.concatenate([dst, np.asarray(add_d, dtype=np.int64)]).astype(np.int32))
+
+
+def existing_batch(n, src, dst, n_ins, n_del, shared, seed):
+    """A batch between existing nodes: ``n_ins`` insertions of distinct non-edges (the first
+    ``shared`` into one uniformly drawn sink, the rest uniform), then ``n_del`` deletions of
+    distinct existing edges. Returns int32 arrays ``(src, dst)`` and int8 ops."""
+    g = rng(seed)
+    es = set(zip(np.asarray(src).tolist(), np.asarray(dst).tolist()))
+    bi, bj = [], []
+    new = set()
+    sink = int(g.integers(n))
+    while len(bi) < n_ins:
+        a = int(g.integers(n))
+        b = sink if len(bi) < shared else int(g.integers(n))
+        if a != b and (a, b) not in es and (a, b) not in new:
+            new.add((a, b))
+            bi.append(a)
+            bj.append(b)
+    for e in g.choice(len(src), size=n_del, replace=False).tolist():
+        bi.append(int(src[e]))
+        bj.append(int(dst[e]))
+    ops = [1] * n_ins + [-1] * n_del
+    return (np.asarray(bi, dtype=np.int32), np.asarray(bj, dtype=np.int32),
+            np.asarray(ops, dtype=np.int8))
