@@ -16,6 +16,9 @@ The other workloads of the method are measured the same way with --workload:
   stream   n = 20k, m = 200k, 1,000 single-edge updates (70% insert), pruned, K = 15
   columns  n = 1M, m = 10M, column-by-column mode (no stored S), K = 10, PartialSim depth
            30; per insertion 65,536 Delta S columns in blocks of 8,192, float32 output
+  columns_batch  the columns graph; per step one batch between existing nodes (48
+           insertions, 16 of them into one sink, and 16 deletions) applied block by block,
+           returning the batch's float64 Delta S columns for 8,192 columns
   adjoint  n = 20k, m = 200k weighted (lognormal(0, 0.5)), dL/dw of a loss over 4,096 pairs
 """
 import argparse
@@ -43,7 +46,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "stream", "columns", "adjoint"])
+                    choices=["batch", "stream", "columns", "columns_batch", "adjoint"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--max-batch", type=int, default=4096)
@@ -55,6 +58,8 @@ def main():
     ap.add_argument("--plain-edges", type=int, default=24)
     ap.add_argument("--case-edges", type=int, default=4,
                     help="single edges timed per case C0-C3 on the plain path")
+    ap.add_argument("--cb-edges", default="48,16,16",
+                    help="columns_batch: insertions, deletions, insertions sharing one sink")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -69,7 +74,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"batch": run_batch, "stream": run_stream, "columns": run_columns,
-           "adjoint": run_adjoint}[args.workload]
+           "columns_batch": run_columns_batch, "adjoint": run_adjoint}[args.workload]
     print(json.dumps(run(args)), flush=True)
 
 
@@ -357,6 +362,72 @@ def run_columns(args):
     return out
 
 
+# ------------------------------------------------------------------------------ columns_batch
+def run_columns_batch(args):
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context
+
+    cfg = W.WORKLOADS[4]
+    n, m, K, Kps = args.n or cfg["n"], args.m or cfg["m"], cfg["K"], cfg["K_ps"]
+    n_ins, n_del, shared = (int(x) for x in args.cb_edges.split(","))
+    steps = args.steps
+    log(f"bench: generating Chung-Lu n={n} m={m}")
+    s, d = W.chung_lu(n, m, seed=1004)
+    batches = W.existing_batches(n, s, d, args.warmup + steps, n_ins, n_del, shared, seed=2204)
+    cols = W.column_sample(n, cfg["block"], seed=3004)[:cfg["block"]]
+    ctx = Context(n, s, d, C=C, K=K, K_ps=Kps, mode="column",
+                  edge_cap=m + (args.warmup + steps) * n_ins + 1024,
+                  split_rows=args.split_rows)
+    out_buf = torch.empty((len(cols), n), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for t in range(args.warmup):
+        ctx.apply_batch_columns(*batches[t], cols, out=out_buf)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    blocks = passes = 0
+    t0 = time.perf_counter()
+    for t in range(args.warmup, args.warmup + steps):
+        _, st = ctx.apply_batch_columns(*batches[t], cols, out=out_buf, stats=True)
+        blocks += st["blocks"]
+        passes += st["fused_passes"]
+        log(f"bench: batch {t - args.warmup + 1}/{steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    values = float(n) * len(cols) * steps
+    edges = (n_ins + n_del) * steps
+    out = common(args, cfg, values / dt, "pair-values/s", dt, steps,
+                 extra_cfg={"workload": "column_batch_n1m", "K_ps": Kps,
+                            "columns": len(cols), "batch": {"insert": n_ins, "delete": n_del,
+                                                            "shared_sink": shared},
+                            "output": "float64"})
+    out["metric"] = "batch Delta S column values/s, column-by-column mode (no stored S)"
+    out["edges_per_s"] = edges / dt
+    out["blocks_per_batch"] = blocks / steps
+    # the accumulate adds P[cols] P^T for the whole batch: 2 (K + 1) panel columns per block,
+    # 2 flop per panel column and output value
+    flops = 2.0 * len(cols) * n * 2 * (K + 1) * blocks
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                       "traffic": traffic("lowrank_gemm_kernel_rect"),
+                       "kernel": "lowrank_gemm_kernel (rectangular accumulate)",
+                       "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
+                       "share_of_step": round(kern_ms / (1e3 * dt), 3),
+                       "algorithmic": "2 (K + 1) panel columns per block; 2 flop per panel "
+                                      "column and output value"}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_columns_batch(n, s, d, batches[0], cols[:64], K, Kps,
+                                                         args.cpu_seconds)
+    return out
+
+
 # ------------------------------------------------------------------------------ adjoint
 def run_adjoint(args):
     import torch
@@ -541,6 +612,35 @@ def cpu_baseline_delta_columns(n, s, d, i, j, cols, K, Kps, seconds):
     return {"value": float(n) * done / dt, "unit": "pair-values/s", "cores": 1,
             "kind": "oracle", "sample": f"{done} Delta S columns of one insertion "
                                         f"(8 per oracle call), {dt:.1f} s on one host thread"}
+
+
+def cpu_baseline_columns_batch(n, s, d, batch, cols, K, Kps, seconds):
+    """The oracle's block-by-block Delta S columns of one batch, run on consecutive 4-edge
+    slices of the batch (each on the graph the earlier slices left) until the time budget is
+    used; the whole batch's time is extrapolated linearly in edges."""
+    import numpy as np
+
+    from oracle import incremental as OI
+    bi, bj, bo = batch
+    cur_s, cur_d = s.astype(np.int64), d.astype(np.int64)
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < seconds and done < len(bi):
+        sl = slice(done, min(done + 4, len(bi)))
+        OI.delta_columns_batch(n, cur_s, cur_d, bi[sl], bj[sl], bo[sl], cols, C, K, Kps)
+        ins, dels = bo[sl] > 0, bo[sl] < 0
+        drop = np.isin(cur_s * n + cur_d,
+                       bi[sl][dels].astype(np.int64) * n + bj[sl][dels].astype(np.int64))
+        cur_s = np.concatenate([cur_s[~drop], bi[sl][ins].astype(np.int64)])
+        cur_d = np.concatenate([cur_d[~drop], bj[sl][ins].astype(np.int64)])
+        done = sl.stop
+    dt = time.perf_counter() - t0
+    per_batch = dt * len(bi) / done
+    return {"value": float(n) * len(cols) / per_batch, "unit": "pair-values/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} of {len(bi)} edges of one batch in 4-edge slices, "
+                      f"{len(cols)} columns, {dt:.1f} s on one host thread; batch time "
+                      f"extrapolated linearly in edges"}
 
 
 def cpu_baseline_gradient(n, s, d, w, a, b, seconds):

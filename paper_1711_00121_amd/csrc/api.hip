@@ -76,8 +76,8 @@ struct sr_ctx {
   bool last_aff = false;   // AFF bitmaps hold the last update
   std::vector<int32_t> last_plan;
 
-  double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) x node_cap
-  double* xd = nullptr;    // PartialSim: two vectors x_t / d (d: row weight of Q), node_cap each
+  double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) pairs x node_cap
+  double* xd = nullptr;    // PartialSim: two pair vectors x_t / d (d: row weight of Q)
   int corr_slots = 0;      // fused batches: slots per chunk at most (2 batch_chunk + 32)
   double* corr = nullptr;  // correction vectors, 2 corr_slots x p_rows
   double* corr_w = nullptr;  // their weights, 2 corr_slots x 64
@@ -626,11 +626,36 @@ sr_status partial_sim(sr_ctx* ctx, const IdList& ids, double* out) {
   return SR_OK;
 }
 
-sr_status partial_sim(sr_ctx* ctx, int32_t q, double* out) {
-  IdList l;
-  l.count = 1;
-  l.id[0] = q;
-  return partial_sim(ctx, l, out);
+// Two PartialSim columns at once, S[:, a] into outa and S[:, b] into outb, as pairs of vectors
+// (the recurrences are the same linear maps, so each product reads both in one gather). The
+// Horner pass writes y_t over x_{K-t}, the base it adds, row by row.
+sr_status partial_sim2(sr_ctx* ctx, const IdList& a, const IdList& b, double* outa,
+                       double* outb) {
+  const int64_t n = ctx->g.n;
+  const int Kp = ctx->cfg.K_ps > 0 ? ctx->cfg.K_ps : ctx->cfg.K;
+  if (Kp == 0) {
+    sr_status r = partial_sim(ctx, a, outa);
+    return r == SR_OK ? partial_sim(ctx, b, outb) : r;
+  }
+  const double C = ctx->cfg.C;
+  hipStream_t s = ctx->stream;
+  const DevQ dq = devq(ctx);
+  const DevAdj out_l = devout(ctx);
+  auto x2 = [&](int t) { return ctx->xs + (int64_t)t * 2 * ctx->node_cap; };
+  auto xd2 = [&](int t) { return ctx->xd + (int64_t)(t & 1) * 2 * ctx->node_cap; };
+  HC(launch_indicator2(x2(0), n, a, b, s, dq, xd2(0)));
+  const HeavyArgs hin = heavy_args(ctx->hin), hout = heavy_args(ctx->hout);
+  for (int t = 1; t <= Kp; ++t)
+    HC(launch_spmv_qt2(dq, out_l, hout, n, xd2(t - 1), x2(t), t < Kp ? xd2(t) : nullptr, 1.0,
+                       s));
+  for (int t = 1; t <= Kp; ++t) {
+    double* base = x2(Kp - t);
+    if (t == Kp)
+      HC(launch_spmv_q2(dq, hin, n, x2(Kp - t + 1), nullptr, C, s, base, 1.0 - C, outa, outb));
+    else
+      HC(launch_spmv_q2(dq, hin, n, x2(Kp - t + 1), base, C, s, base, 1.0));
+  }
+  return SR_OK;
 }
 
 bool valid_ctx(sr_ctx* c) { return c != nullptr; }
@@ -843,8 +868,8 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
 
   if (cfg.mode == SR_COLUMN) {
     const int Kp = cfg.K_ps > 0 ? cfg.K_ps : cfg.K;
-    IC(dalloc(&ctx->xs, (int64_t)(Kp + 1) * node_cap));
-    IC(dalloc(&ctx->xd, 2 * node_cap));
+    IC(dalloc(&ctx->xs, (int64_t)(Kp + 1) * 2 * node_cap));
+    IC(dalloc(&ctx->xd, 4 * node_cap));
     *out = ctx;
     return SR_OK;
   }
@@ -961,9 +986,11 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
   if (ctx->cfg.mode == SR_COLUMN) {
     if (case_id != 0 || op < 0) return SR_EMODE;
     // Algorithm 7, case C0: old columns by PartialSim, gamma, series on the new graph.
-    sr_status r = partial_sim(ctx, i, ctx->SI);
-    if (r != SR_OK) return r;
-    r = partial_sim(ctx, j, ctx->Sj);
+    IdList li, lj;
+    li.count = lj.count = 1;
+    li.id[0] = i;
+    lj.id[0] = j;
+    sr_status r = partial_sim2(ctx, li, lj, ctx->SI, ctx->Sj);
     if (r != SR_OK) return r;
     hipStream_t s = ctx->stream;
     const double C = ctx->cfg.C;
@@ -1424,8 +1451,10 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
     double* P = ctx->Pb + (int64_t)q * gstride;
     // S[:, I] and S[:, j] on the current graph (PartialSim), Q S[:, I], then Table 2 (C0)
     const IdList il = idlist(b.I, 0, b.I.size());
-    r = partial_sim(ctx, il, ctx->SI);
-    if (r == SR_OK) r = partial_sim(ctx, b.j, ctx->Sj);
+    IdList lj;
+    lj.count = 1;
+    lj.id[0] = b.j;
+    r = partial_sim2(ctx, il, lj, ctx->SI, ctx->Sj);
     if (r != SR_OK) return r;
     HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->QSI, 1.0, s));
     GammaArgs ga{};

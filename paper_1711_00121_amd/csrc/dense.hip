@@ -307,6 +307,19 @@ __global__ __launch_bounds__(kB) void indicator_kernel(double* x, int64_t n, IdL
   }
 }
 
+__global__ __launch_bounds__(kB) void indicator2_kernel(double* x2, int64_t n, IdList ia,
+                                                        IdList ib, DevQ dq, double* xd2) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a >= n) return;
+  double u = 0.0, v = 0.0;
+  for (int t = 0; t < ia.count; ++t) u = (ia.id[t] == a) ? 1.0 : u;
+  for (int t = 0; t < ib.count; ++t) v = (ib.id[t] == a) ? 1.0 : v;
+  *reinterpret_cast<double2*>(x2 + 2 * a) = make_double2(u, v);
+  const double d = dq.W ? dq.W[a] : (double)dq.in.len[a];
+  const double r = d > 0.0 ? 1.0 / d : 0.0;
+  *reinterpret_cast<double2*>(xd2 + 2 * a) = make_double2(u * r, v * r);
+}
+
 __global__ __launch_bounds__(kB) void fill_diag_kernel(double* A, int64_t n, int64_t ld,
                                                        double v) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -327,6 +340,13 @@ hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t
                             const DevQ* dq, double* xd) {
   if (n <= 0) return hipSuccess;
   indicator_kernel<<<g1(n), kB, 0, s>>>(x, n, ids, dq ? *dq : DevQ{}, dq ? xd : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_indicator2(double* x2, int64_t n, const IdList& a, const IdList& b,
+                             hipStream_t s, const DevQ& dq, double* xd2) {
+  if (n <= 0) return hipSuccess;
+  indicator2_kernel<<<g1(n), kB, 0, s>>>(x2, n, a, b, dq, xd2);
   return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ __global__ __launch_bounds__(64) void patch_kernel(AdjPtrs t, Patch p) {
 
 // What one traversal computes. Values per entry: NV = 1 (x) or 2 (xi, eta pair).
 struct Op {
-  int kind;             // 0: y = post*(base + scale*Q x); 1: series step; 2: y = scale*Q^T x
+  int kind;             // 0: y = post*(base + scale*Q x); 1: series step; 2: y = scale*Q^T x;
+                        // 3, 4: kinds 0 and 2 on two vectors at once (pairs of double)
   const double* x;      // kind 0/2 input vector (kind 2: divided by the row weight of Q)
   double* y;            // kind 0/2 output vector
   double* yd;           // kind 2: optional output divided by the row weight of Q
@@ -45,6 +46,10 @@ struct Op {
   int sld;
   double* cdst;         // kind 1: optional compact copy of the new pair (row a at 2 a)
   double sx, sy;
+  // kinds 3 and 4: the input pairs are read through src / sld (sld = 2); y, yd and base hold
+  // pairs (row a at 2 a); kind 3 writes the two halves to ya and yb instead when ya is set
+  double* ya;
+  double* yb;
   // optional bitmaps (pull form of Theorem 4): out bit b = OR_{x in row b} (in0 | in1)(x)
   const uint32_t* a0;
   const uint32_t* a1;
@@ -60,7 +65,7 @@ struct Op {
 constexpr int64_t kLdsBitmapBytes = 48 * 1024;
 
 // Compile-time shape of one traversal: KIND (0: y = post (base + scale Q x); 1: series step;
-// 2: y = scale Q^T x), WT (weighted graph), AFF (0: no bitmaps; 1: bout only, from b0 | b1;
+// 2: y = scale Q^T x; 3, 4: kinds 0 and 2 on pairs), WT (weighted graph), AFF (0: no bitmaps; 1: bout only, from b0 | b1;
 // 2: aout and bout), LDSB (bitmaps staged in LDS). Every instantiation is straight-line: no load sits under a branch, so
 // no load waits for another that it does not depend on.
 template <int KIND, bool WT, int AFF>
@@ -109,7 +114,8 @@ __device__ __forceinline__ void accumulate(const Op& o, const DevQ& q, const Dev
     for (int u = 0; u < U; ++u) ok[u] = base + u * step < p1;
     // next pass's indices (clamped, so the loads are unconditional)
     if constexpr (PIPE) load_idx(base + U * step, xn, wn);
-    if constexpr (KIND == 1) {
+    if constexpr (KIND == 1 || KIND >= 3) {
+      // a pair per node: both vectors of a gather share one cache line
       double2 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -179,12 +185,42 @@ __device__ __forceinline__ void finish(const Op& o, const DevQ& q, int64_t row, 
     v *= o.scale;
     if (o.base) v += o.base[row];
     o.y[row] = o.post * v;
-  } else {
+  } else if constexpr (KIND == 2) {
     const double v = o.scale * v0;
     o.y[row] = v;
     if (o.yd) {
       const double d = WT ? q.W[row] : (double)q.in.len[row];
       o.yd[row] = d > 0.0 ? v / d : 0.0;
+    }
+  } else if constexpr (KIND == 3) {
+    double2 v = make_double2(0.0, 0.0);
+    if (len > 0) {
+      const double inv = WT ? 1.0 / q.W[row] : 1.0 / (double)len;
+      v.x = v0 * inv;
+      v.y = v1 * inv;
+    }
+    v.x *= o.scale;
+    v.y *= o.scale;
+    if (o.base) {
+      const double2 b = *reinterpret_cast<const double2*>(o.base + 2 * row);
+      v.x += b.x;
+      v.y += b.y;
+    }
+    v.x *= o.post;
+    v.y *= o.post;
+    if (o.ya) {
+      o.ya[row] = v.x;
+      o.yb[row] = v.y;
+    } else {
+      *reinterpret_cast<double2*>(o.y + 2 * row) = v;
+    }
+  } else {
+    const double2 v = make_double2(o.scale * v0, o.scale * v1);
+    *reinterpret_cast<double2*>(o.y + 2 * row) = v;
+    if (o.yd) {
+      const double d = WT ? q.W[row] : (double)q.in.len[row];
+      const double r = d > 0.0 ? 1.0 / d : 0.0;
+      *reinterpret_cast<double2*>(o.yd + 2 * row) = make_double2(v.x * r, v.y * r);
     }
   }
 }
@@ -409,6 +445,10 @@ hipError_t run(const Op& o, const DevQ& q, const DevAdj& L, int64_t n, const Hea
       return wt ? run_shape<1, true, 2>(o, q, L, n, h, s) : run_shape<1, false, 2>(o, q, L, n, h, s);
     return wt ? run_shape<1, true, 0>(o, q, L, n, h, s) : run_shape<1, false, 0>(o, q, L, n, h, s);
   }
+  if (o.kind == 3)
+    return wt ? run_shape<3, true, 0>(o, q, L, n, h, s) : run_shape<3, false, 0>(o, q, L, n, h, s);
+  if (o.kind == 4)
+    return wt ? run_shape<4, true, 0>(o, q, L, n, h, s) : run_shape<4, false, 0>(o, q, L, n, h, s);
   return wt ? run_shape<2, true, 0>(o, q, L, n, h, s) : run_shape<2, false, 0>(o, q, L, n, h, s);
 }
 
@@ -455,6 +495,37 @@ hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, 
   o.x = xd;
   o.y = y;
   o.yd = yd;
+  o.scale = scale;
+  return run(o, q, out, n, h, s);
+}
+
+hipError_t launch_spmv_q2(const DevQ& q, const HeavyArgs& h, int64_t n, const double* x2,
+                          double* y2, double scale, hipStream_t s, const double* base2,
+                          double post, double* ya, double* yb) {
+  if ((ya == nullptr) != (yb == nullptr) || (ya == nullptr && y2 == nullptr))
+    return hipErrorInvalidValue;
+  Op o = blank();
+  o.kind = 3;
+  o.src = x2;
+  o.sld = 2;
+  o.y = y2;
+  o.ya = ya;
+  o.yb = yb;
+  o.scale = scale;
+  o.base = base2;
+  o.post = post;
+  return run(o, q, q.in, n, h, s);
+}
+
+hipError_t launch_spmv_qt2(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
+                           const double* xd2, double* y2, double* yd2, double scale,
+                           hipStream_t s) {
+  Op o = blank();
+  o.kind = 4;
+  o.src = xd2;
+  o.sld = 2;
+  o.y = y2;
+  o.yd = yd2;
   o.scale = scale;
   return run(o, q, out, n, h, s);
 }

@@ -79,6 +79,15 @@ hipError_t launch_spmv_q(const DevQ& q, const HeavyArgs& h, int64_t n, const dou
 hipError_t launch_spmv_qt(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
                           const double* xd, double* y, double* yd, double scale,
                           hipStream_t s);
+// The same two products on two vectors at once, stored as pairs (node a at 2 a): the gathers of
+// both vectors share one cache line. launch_spmv_q2 writes y2, or, with ya and yb set, the two
+// halves to ya and yb (base2 may alias y2: each row reads its base before writing).
+hipError_t launch_spmv_q2(const DevQ& q, const HeavyArgs& h, int64_t n, const double* x2,
+                          double* y2, double scale, hipStream_t s, const double* base2 = nullptr,
+                          double post = 1.0, double* ya = nullptr, double* yb = nullptr);
+hipError_t launch_spmv_qt2(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
+                           const double* xd2, double* y2, double* yd2, double scale,
+                           hipStream_t s);
 // One step of eq (16a) on the panel P (row a holds (xi_k, eta_k) pairs for k = 0..K, pld
 // doubles per row): xi_{k+1} = sx * Q xi_k, eta_{k+1} = sy * Q eta_k; optionally one
 // affected-area level in the same pass.
@@ -271,6 +280,9 @@ hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const d
 // (or the in-weight sum when weighted), 0 where d[a] = 0.
 hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t s,
                             const DevQ* dq = nullptr, double* xd = nullptr);
+// Pairs (indicator of a, indicator of b) at x2[2 v], x2[2 v + 1], and x2 / d at xd2.
+hipError_t launch_indicator2(double* x2, int64_t n, const IdList& a, const IdList& b,
+                             hipStream_t s, const DevQ& dq, double* xd2);
 hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
 hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);

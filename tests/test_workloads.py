@@ -79,3 +79,22 @@ def test_existing_batch_valid():
     assert np.all(bi < n) and np.all(bj < n)
     b2 = W.existing_batch(n, s, d, n_ins=12, n_del=5, shared=4, seed=96)
     assert all(np.array_equal(x, y) for x, y in zip((bi, bj, bo), b2))
+
+
+def test_existing_batches_apply_in_sequence():
+    n = 400
+    s, d = W.chung_lu(n, 2000, seed=97)
+    batches = W.existing_batches(n, s, d, 3, n_ins=10, n_del=4, shared=3, seed=98)
+    assert len(batches) == 3
+    cur = set(zip(s.tolist(), d.tolist()))
+    for bi, bj, bo in batches:
+        assert len(bi) == 14 and bo.tolist() == [1] * 10 + [-1] * 4
+        ins = list(zip(bi[:10].tolist(), bj[:10].tolist()))
+        dels = list(zip(bi[10:].tolist(), bj[10:].tolist()))
+        assert len({b for _, b in ins[:3]}) == 1
+        assert not (set(ins) & cur) and set(dels) <= cur
+        cur |= set(ins)
+        cur -= set(dels)
+    one = W.existing_batches(n, s, d, 1, n_ins=10, n_del=4, shared=3, seed=98)[0]
+    assert all(np.array_equal(x, y)
+               for x, y in zip(one, W.existing_batch(n, s, d, 10, 4, 3, seed=98)))

@@ -351,21 +351,36 @@ def existing_batch(n, src, dst, n_ins, n_del, shared, seed):
     """A batch between existing nodes: ``n_ins`` insertions of distinct non-edges (the first
     ``shared`` into one uniformly drawn sink, the rest uniform), then ``n_del`` deletions of
     distinct existing edges. Returns int32 arrays ``(src, dst)`` and int8 ops."""
+    return existing_batches(n, src, dst, 1, n_ins, n_del, shared, seed)[0]
+
+
+def existing_batches(n, src, dst, count, n_ins, n_del, shared, seed):
+    """``count`` batches shaped as in ``existing_batch`` (each with its own shared sink) that
+    can be applied one after another: no edge appears in two of them, insertions are non-edges
+    of the original graph and deletions are distinct original edges. Returns a list of
+    ``(src, dst, ops)`` triples."""
     g = rng(seed)
     es = set(zip(np.asarray(src).tolist(), np.asarray(dst).tolist()))
-    bi, bj = [], []
     new = set()
-    sink = int(g.integers(n))
-    while len(bi) < n_ins:
-        a = int(g.integers(n))
-        b = sink if len(bi) < shared else int(g.integers(n))
-        if a != b and (a, b) not in es and (a, b) not in new:
-            new.add((a, b))
-            bi.append(a)
-            bj.append(b)
-    for e in g.choice(len(src), size=n_del, replace=False).tolist():
-        bi.append(int(src[e]))
-        bj.append(int(dst[e]))
-    ops = [1] * n_ins + [-1] * n_del
-    return (np.asarray(bi, dtype=np.int32), np.asarray(bj, dtype=np.int32),
-            np.asarray(ops, dtype=np.int8))
+    ins = []
+    for _ in range(count):
+        bi, bj = [], []
+        sink = int(g.integers(n))
+        while len(bi) < n_ins:
+            a = int(g.integers(n))
+            b = sink if len(bi) < shared else int(g.integers(n))
+            if a != b and (a, b) not in es and (a, b) not in new:
+                new.add((a, b))
+                bi.append(a)
+                bj.append(b)
+        ins.append((bi, bj))
+    dels = g.choice(len(src), size=n_del * count, replace=False).tolist()
+    out = []
+    for t, (bi, bj) in enumerate(ins):
+        for e in dels[t * n_del:(t + 1) * n_del]:
+            bi.append(int(src[e]))
+            bj.append(int(dst[e]))
+        ops = [1] * n_ins + [-1] * n_del
+        out.append((np.asarray(bi, dtype=np.int32), np.asarray(bj, dtype=np.int32),
+                    np.asarray(ops, dtype=np.int8)))
+    return out
