@@ -17,6 +17,9 @@ What is here, by module:
                    (Inc-uSR), Theorem 4 (affected areas), Theorems 5-8 and Algorithms 3-5
                    (node insertions C1-C3), Table 2 and Algorithm 6 (batches), Algorithm 7
                    (column-by-column updates).
+* ``tree``         all-pairs SimRank seeded from a breadth-first spanning forest (Example
+                   1.2): the forest, its S by the example's closed form, and the other edges
+                   applied as one Inc-bSR batch.
 * ``adjoint``      gradient of a pairwise squared loss on S with respect to edge weights,
                    by the transposed Sylvester iteration, and its finite-difference check.
                    The paper has no gradient; this follows from eq (03a) by the chain rule.
