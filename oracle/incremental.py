@@ -411,11 +411,17 @@ def sink_blocks(edges):
     return blocks
 
 
-def plan_batch(n, src, dst, bi, bj, bop):
+MAX_SOURCES = 60
+
+
+def plan_batch(n, src, dst, bi, bj, bop, max_sources=MAX_SOURCES):
     """Algorithm 6 planning with the readings: deletion blocks first (sinks ascending),
     then insertion blocks (sinks ascending); each insertion block is split at the time it
     is processed into sources already in V (processed first) and sources not yet in V;
-    a node joins V when a processed block creates it.
+    a node joins V when a processed block creates it. A block of more than ``max_sources``
+    sources is taken as consecutive blocks of at most that many (sources ascending) with the
+    same sink: consecutive Table 2 updates of one sink compose to the update of their union,
+    so the split changes nothing but the series truncation of each part.
 
     New node ids must be exactly ``n .. n + N - 1``. Returns a list of dicts with keys
     ``case`` (0..3), ``op``, ``I`` (sorted sources), ``j``, ``dj`` (in-degree of j when the
@@ -444,22 +450,26 @@ def plan_batch(n, src, dst, bi, bj, bop):
         deg[b] = deg.get(b, 0) + 1
     V = set(range(n))
     plan = []
+    step = max_sources if max_sources else None
     for (I, j) in sink_blocks(minus):
-        plan.append(dict(case=0, op=-1, I=sorted(I), j=j, dj=deg.get(j, 0)))
-        deg[j] = deg.get(j, 0) - len(I)
+        I = sorted(I)
+        for lo in range(0, len(I), step or len(I)):
+            part = I[lo:lo + step] if step else I
+            plan.append(dict(case=0, op=-1, I=part, j=j, dj=deg.get(j, 0)))
+            deg[j] = deg.get(j, 0) - len(part)
     for (I, j) in sink_blocks(plus):
         old = sorted(x for x in I if x in V)
         new = sorted(x for x in I if x not in V)
-        for part, in_v in ((old, True), (new, False)):
-            if not part:
-                continue
-            j_in = j in V
-            case = {(True, True): 0, (True, False): 1, (False, True): 2, (False, False): 3}[
-                (in_v, j_in)]
-            plan.append(dict(case=case, op=1, I=part, j=j, dj=deg.get(j, 0)))
-            deg[j] = deg.get(j, 0) + len(part)
-            V.update(part)
-            V.add(j)
+        for whole, in_v in ((old, True), (new, False)):
+            for lo in range(0, len(whole), step or max(len(whole), 1)):
+                part = whole[lo:lo + step] if step else whole
+                j_in = j in V
+                case = {(True, True): 0, (True, False): 1, (False, True): 2,
+                        (False, False): 3}[(in_v, j_in)]
+                plan.append(dict(case=case, op=1, I=part, j=j, dj=deg.get(j, 0)))
+                deg[j] = deg.get(j, 0) + len(part)
+                V.update(part)
+                V.add(j)
     return plan, n_new
 
 

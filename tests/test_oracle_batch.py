@@ -195,3 +195,40 @@ def test_column_batch_rejects_new_nodes():
     s, d = W.chung_lu(n, 60, seed=79)
     with pytest.raises(ValueError):
         I.delta_columns_batch(n, s, d, [1], [n], [1], [0], C, 5, 5)
+
+
+def test_long_blocks_split_into_consecutive_blocks_of_one_sink():
+    """A sink with more than 60 sources is taken as consecutive blocks of at most 60 (sources
+    ascending); a new sink's later parts find it existing (case C1 then C0)."""
+    n = 200
+    src, dst = [1], [2]
+    bi = list(range(3, 133))                      # 130 existing sources into sink 0
+    bj = [0] * 130
+    bi += list(range(10, 80))                     # 70 existing sources into the new sink 200
+    bj += [200] * 70
+    plan, n_new = I.plan_batch(n, src, dst, bi, bj, [1] * len(bi))
+    assert n_new == 201
+    sizes = [(b["case"], b["j"], len(b["I"]), b["dj"]) for b in plan]
+    assert sizes == [(0, 0, 60, 0), (0, 0, 60, 60), (0, 0, 10, 120),
+                     (1, 200, 60, 0), (0, 200, 10, 60)]
+    assert plan[0]["I"] == list(range(3, 63)) and plan[2]["I"] == list(range(123, 133))
+    whole, _ = I.plan_batch(n, src, dst, bi, bj, [1] * len(bi), max_sources=None)
+    assert [len(b["I"]) for b in whole] == [130, 70]
+
+
+def test_split_blocks_compose_to_recompute():
+    """Inc-bSR with the 60-source split and without it both reach the recompute of the
+    updated graph at a deep series (the split only changes each part's truncation)."""
+    n = 90
+    s, d = W.chung_lu(n, 300, seed=741)
+    es = set(zip(s.tolist(), d.tolist()))
+    add = [(a, 5) for a in range(n) if a != 5 and (a, 5) not in es][:70]
+    bi = [a for a, _ in add]
+    bj = [b for _, b in add]
+    S0 = O.fixed_point(Gr.transition_matrix(n, s, d), C)
+    S1, plan = I.inc_bsr(n, s, d, S0, bi, bj, [1] * len(bi), C, 60)
+    assert [len(b["I"]) for b in plan] == [60, 10]
+    s2 = np.concatenate([s, bi])
+    d2 = np.concatenate([d, bj])
+    exact = O.fixed_point(Gr.transition_matrix(n, s2, d2), C)
+    assert np.abs(S1 - exact).max() < 1e-11
