@@ -19,6 +19,9 @@ The other workloads of the method are measured the same way with --workload:
   columns_batch  the columns graph; per step one batch between existing nodes (48
            insertions, 16 of them into one sink, and 16 deletions) applied block by block,
            returning the batch's float64 Delta S columns for 8,192 columns
+  forest   the stream's graph (n = 20k, m = 200k); one step computes all-pairs S by seeding
+           it from a breadth-first spanning forest (closed form) and applying the other
+           edges as one batch, beside the fixed-point initialisation of the same graph
   adjoint  n = 20k, m = 200k weighted (lognormal(0, 0.5)), dL/dw of a loss over 4,096 pairs
 """
 import argparse
@@ -46,7 +49,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "stream", "columns", "columns_batch", "adjoint"])
+                    choices=["batch", "stream", "columns", "columns_batch", "forest", "adjoint"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--max-batch", type=int, default=4096)
@@ -74,7 +77,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"batch": run_batch, "stream": run_stream, "columns": run_columns,
-           "columns_batch": run_columns_batch, "adjoint": run_adjoint}[args.workload]
+           "columns_batch": run_columns_batch, "forest": run_forest,
+           "adjoint": run_adjoint}[args.workload]
     print(json.dumps(run(args)), flush=True)
 
 
@@ -428,6 +432,82 @@ def run_columns_batch(args):
     return out
 
 
+# ------------------------------------------------------------------------------ forest
+def run_forest(args):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context
+
+    cfg = W.WORKLOADS[2]
+    n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
+    log(f"bench: generating Chung-Lu n={n} m={m}")
+    s, d = W.chung_lu(n, m, seed=1002)
+    common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk,
+                      split_rows=args.split_rows)
+
+    def seeded(profile=False):
+        return Context(n, s, d, init="forest", profile=profile, **common_cfg)
+
+    for w in range(args.warmup):
+        seeded().close()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {w} done")
+    times, kern_ms, launches = [], 0.0, 0
+    ctx = None
+    for k in range(args.steps):
+        if ctx is not None:
+            ctx.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = seeded(profile=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ms, cnt = ctx.profile_read(reset=True)
+        kern_ms += ms
+        launches += cnt
+        log(f"bench: step {k}: {times[-1]:.2f} s, {ctx.init_stats['blocks']} blocks, "
+            f"{ctx.init_stats['fused_passes']} fused passes")
+    st = ctx.init_stats
+    dt = float(np.sum(times))
+    # the fixed-point initialisation of the same graph, and how far the two S are apart
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ref = Context(n, s, d, **common_cfg)
+    torch.cuda.synchronize()
+    t_fixed = time.perf_counter() - t1
+    diff = float((ctx.S() - ref.S()).abs().max())
+    ref.close()
+    out = common(args, cfg, float(n) * n * args.steps / dt, "S entries/s", dt, args.steps,
+                 extra_cfg={"workload": "forest_seeded_n20k", "s_store": "f32 value + f32 "
+                            "compensation", "batch_chunk": args.chunk})
+    out["metric"] = "all-pairs SimRank seeded from a spanning forest (Example 1.2), S entries/s"
+    out["seconds_per_all_pairs"] = dt / args.steps
+    out["forest"] = {"tree_edges": m - st["edges_in"], "batch_edges": st["edges_in"],
+                     "blocks": st["blocks"], "lowrank_blocks": st["lowrank_blocks"],
+                     "fused_passes": st["fused_passes"]}
+    out["fixed_point_init_s"] = t_fixed
+    out["max_abs_vs_fixed_point"] = diff
+    pld = 2 * (K + 1)
+    flops = float(n) * (n + 1.0) * pld * st["lowrank_blocks"] * args.steps
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                       "traffic": traffic("lowrank_gemm_kernel"),
+                       "kernel": "lowrank_gemm_kernel (fused batch pass)",
+                       "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
+                       "share_of_step": round(kern_ms / (1e3 * dt), 3),
+                       "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per "
+                                      "low-rank block"}
+    ctx.close()
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_forest(K)
+    return out
+
+
 # ------------------------------------------------------------------------------ adjoint
 def run_adjoint(args):
     import torch
@@ -641,6 +721,24 @@ def cpu_baseline_columns_batch(n, s, d, batch, cols, K, Kps, seconds):
             "sample": f"{done} of {len(bi)} edges of one batch in 4-edge slices, "
                       f"{len(cols)} columns, {dt:.1f} s on one host thread; batch time "
                       f"extrapolated linearly in edges"}
+
+
+def cpu_baseline_forest(K, n=900, m=9000):
+    """The oracle's whole forest-seeded pipeline (forest, closed form, Inc-bSR of the other
+    edges) on a smaller graph of the same generator and density, scaled to S entries/s; its
+    dense products are held to one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import tree as OT
+    s, d = W.chung_lu(n, m, seed=1002)
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        OT.tree_seeded(n, s.astype("int64"), d.astype("int64"), C, K)
+    dt = time.perf_counter() - t0
+    return {"value": float(n) * n / dt, "unit": "S entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole pipeline at n = {n}, m = {m} (same generator and density), "
+                      f"{dt:.1f} s on one host thread"}
 
 
 def cpu_baseline_gradient(n, s, d, w, a, b, seconds):

@@ -84,6 +84,9 @@ typedef struct sr_config {
                             chunks of 8192 entries, one workgroup each, whose partial sums a
                             second small launch adds; rows of 2049 .. split_rows entries take
                             one workgroup. 0 means 65536; otherwise at least 2048            */
+  int32_t profile;       /* 1: time the S-update launches from creation on (as sr_profile(1)),
+                            so that those inside init_simrank_tree are counted too          */
+  int32_t reserved;      /* set to 0                                                        */
 } sr_config;
 
 /* Per-update statistics (filled when a non-null pointer is passed; the call then
@@ -130,6 +133,21 @@ sr_status sr_default_config(sr_config* cfg);
 sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
                        const int32_t* dst, const double* weight, const sr_config* cfg,
                        const void* S0, void* hip_stream);
+
+/* All-pairs SimRank seeded from a spanning forest (Example 1.2): builds the breadth-first
+ * spanning forest of the digraph (nodes without in-edges are roots first, then any node not
+ * reached yet, both in ascending id; out-neighbours are scanned in ascending id), creates a
+ * dense-mode context on the forest's edges with S set by the example's closed form (for a, b
+ * at one depth H whose lowest common ancestor is lambda edges up,
+ * S[a][b] = C^lambda (1 - C^(H - lambda + 1)); 0 across depths and across trees), then
+ * applies every other edge, in the caller's order, as one apply_batch of insertions. The
+ * result is S of the whole graph up to the K-term truncation of each block's series.
+ * src, dst: host arrays of m edges (no self-loops, no duplicates); cfg: as init_simrank, mode
+ * must be SR_DENSE (SR_EMODE otherwise), edge_cap 0 means 2 m + 1024. Unweighted only.
+ * stats: NULL, or the batch's statistics. On any error nothing is returned (*out = NULL). */
+sr_status init_simrank_tree(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                            const int32_t* dst, const sr_config* cfg, void* hip_stream,
+                            sr_batch_stats* stats);
 
 /* Applies one edge update, op = +1 insert or -1 delete (Algorithms 1 and 2, Theorem 9;
  * node insertions: Algorithms 3, 4, 5 with the new ids i == n (C2), j == n (C1), or

@@ -36,6 +36,8 @@ class sr_config(C.Structure):
         ("batch_chunk", C.c_int32),
         ("fused_batch", C.c_int32),
         ("split_rows", C.c_int32),
+        ("profile", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -77,6 +79,8 @@ SIGNATURES = {
     "sr_default_config": (C.c_int, [C.POINTER(sr_config)]),
     "init_simrank": (C.c_int, [C.POINTER(P), C.c_int64, C.c_int64, I32P, I32P, F64P,
                                C.POINTER(sr_config), P, P]),
+    "init_simrank_tree": (C.c_int, [C.POINTER(P), C.c_int64, C.c_int64, I32P, I32P,
+                                    C.POINTER(sr_config), P, C.POINTER(sr_batch_stats)]),
     "apply_edge_update": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(sr_update_stats)]),
     "apply_batch": (C.c_int, [P, C.c_int64, I32P, I32P, I8P, C.POINTER(sr_batch_stats)]),

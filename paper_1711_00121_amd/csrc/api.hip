@@ -732,9 +732,12 @@ sr_status sr_destroy(sr_ctx* ctx) {
   return SR_OK;
 }
 
-sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
-                       const int32_t* dst, const double* weight, const sr_config* cfg_in,
-                       const void* S0, void* hip_stream) {
+// Context set-up shared by init_simrank and init_simrank_tree. With tree_parent, the graph is
+// a spanning forest (tree_parent / tree_depth per node) and S is its closed form.
+static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                           const int32_t* dst, const double* weight, const sr_config* cfg_in,
+                           const void* S0, void* hip_stream, const int32_t* tree_parent,
+                           const int32_t* tree_depth) {
   if (!out || n <= 0 || m < 0 || (m > 0 && (!src || !dst))) return SR_EINVAL;
   *out = nullptr;
   sr_config cfg;
@@ -764,6 +767,7 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   if (!ctx) return SR_ENOMEM;
   ctx->cfg = cfg;
   ctx->hin.split = ctx->hout.split = cfg.split_rows;
+  ctx->profiling = cfg.profile != 0;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->node_cap = node_cap;
   ctx->edge_cap = edge_cap;
@@ -893,6 +897,26 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
     IC(hipMemset(ctx->S_mem[0], 0, cells * 4));
   }
 
+  if (tree_parent) {
+    // S of the forest by Example 1.2's closed form, written straight into the store
+    int32_t *dp = nullptr, *dd = nullptr;
+    hipError_t e = hipMalloc(&dp, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc(&dd, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMemcpy(dp, tree_parent, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dd, tree_depth, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_tree_init(ctx->S, n, dp, dd, cfg.C, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(dp);
+    (void)hipFree(dd);
+    if (e != hipSuccess) {
+      sr_destroy(ctx);
+      return SR_EHIP;
+    }
+    ctx->updated = false;
+    *out = ctx;
+    return SR_OK;
+  }
+
   // Initial S: copy S0, or iterate S <- C Q S Q^T + (1 - C) I in float64 (eq (03a)):
   //   T = Q S (row gather), U = T^T, S' = C Q U + (1 - C) I; S symmetric so U = S Q^T.
   const int64_t ldi = (n + 63) / 64 * 64;
@@ -950,6 +974,95 @@ sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
   *out = ctx;
   return SR_OK;
 #undef IC
+}
+
+sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                       const int32_t* dst, const double* weight, const sr_config* cfg_in,
+                       const void* S0, void* hip_stream) {
+  return init_impl(out, n, m, src, dst, weight, cfg_in, S0, hip_stream, nullptr, nullptr);
+}
+
+sr_status init_simrank_tree(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                            const int32_t* dst, const sr_config* cfg_in, void* hip_stream,
+                            sr_batch_stats* stats) {
+  if (!out || n <= 0 || m < 0 || (m > 0 && (!src || !dst))) return SR_EINVAL;
+  *out = nullptr;
+  sr_config cfg;
+  if (cfg_in) {
+    cfg = *cfg_in;
+  } else {
+    sr_default_config(&cfg);
+  }
+  if (cfg.mode != SR_DENSE) return SR_EMODE;
+  for (int64_t e = 0; e < m; ++e) {
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return SR_ERANGE;
+    if (src[e] == dst[e]) return SR_ESELF;
+  }
+  if (cfg.edge_cap <= 0) cfg.edge_cap = 2 * m + 1024;
+  // Breadth-first spanning forest (Example 1.2): nodes without in-edges are roots first, then
+  // any node not reached yet, both in ascending id; out-neighbours scanned in ascending id.
+  std::vector<int64_t> ostart(n + 1, 0);
+  std::vector<int32_t> indeg(n, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    ++ostart[src[e] + 1];
+    ++indeg[dst[e]];
+  }
+  for (int64_t v = 0; v < n; ++v) ostart[v + 1] += ostart[v];
+  std::vector<int32_t> onb(m);
+  {
+    std::vector<int64_t> fill(ostart.begin(), ostart.end() - 1);
+    for (int64_t e = 0; e < m; ++e) onb[fill[src[e]]++] = dst[e];
+    for (int64_t v = 0; v < n; ++v) std::sort(onb.begin() + ostart[v], onb.begin() + ostart[v + 1]);
+  }
+  std::vector<int32_t> parent(n, -1), depth(n, 0), queue;
+  std::vector<char> seen(n, 0);
+  queue.reserve(n);
+  auto grow = [&](int32_t r) {
+    if (seen[r]) return;
+    seen[r] = 1;
+    size_t head = queue.size();
+    queue.push_back(r);
+    while (head < queue.size()) {
+      const int32_t u = queue[head++];
+      for (int64_t p = ostart[u]; p < ostart[u + 1]; ++p) {
+        const int32_t v = onb[p];
+        if (!seen[v]) {
+          seen[v] = 1;
+          parent[v] = u;
+          depth[v] = depth[u] + 1;
+          queue.push_back(v);
+        }
+      }
+    }
+  };
+  for (int32_t v = 0; v < n; ++v)
+    if (indeg[v] == 0) grow(v);
+  for (int32_t v = 0; v < n; ++v) grow(v);
+  // forest edges parent[v] -> v (by v); the other edges keep the caller's order
+  std::vector<int32_t> ts, td, rs, rd;
+  for (int32_t v = 0; v < n; ++v)
+    if (parent[v] >= 0) {
+      ts.push_back(parent[v]);
+      td.push_back(v);
+    }
+  for (int64_t e = 0; e < m; ++e)
+    if (parent[dst[e]] != src[e]) {
+      rs.push_back(src[e]);
+      rd.push_back(dst[e]);
+    }
+  if ((int64_t)(ts.size() + rs.size()) != m) return SR_EEXIST;  // a forest edge given twice
+  sr_ctx* ctx = nullptr;
+  sr_status st = init_impl(&ctx, n, (int64_t)ts.size(), ts.data(), td.data(), nullptr, &cfg,
+                           nullptr, hip_stream, parent.data(), depth.data());
+  if (st != SR_OK) return st;
+  std::vector<int8_t> ops(rs.size(), 1);
+  st = apply_batch(ctx, (int64_t)rs.size(), rs.data(), rd.data(), ops.data(), stats);
+  if (st != SR_OK) {
+    sr_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return SR_OK;
 }
 
 sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,

@@ -320,6 +320,49 @@ __global__ __launch_bounds__(kB) void indicator2_kernel(double* x2, int64_t n, I
   *reinterpret_cast<double2*>(xd2 + 2 * a) = make_double2(u * r, v * r);
 }
 
+// S of a spanning forest (Example 1.2): row a of the tile, columns c0 + t, t < kTreeCols.
+// Nodes at different depths score 0; at one depth H they climb to their lowest common
+// ancestor (lambda steps) and score C^lambda (1 - C^(H - lambda + 1)), or 0 if they reach
+// different roots. Every entry of the n x n block is written.
+constexpr int kTreeT = 256;
+constexpr int kTreeCols = 1024;
+
+__global__ __launch_bounds__(kTreeT) void tree_init_kernel(SView S, int64_t n, int64_t ncb,
+                                                           const int32_t* parent,
+                                                           const int32_t* depth, double C) {
+  const int64_t a = (int64_t)blockIdx.x / ncb;
+  const int64_t c0 = ((int64_t)blockIdx.x % ncb) * kTreeCols;
+  const int ha = depth[a];
+  for (int t = threadIdx.x; t < kTreeCols; t += kTreeT) {
+    const int64_t b = c0 + t;
+    if (b >= n) break;
+    double v = 0.0;
+    if (depth[b] == ha) {
+      // a and b are at one depth, so they reach their roots together: at most ha steps
+      int32_t x = (int32_t)a, y = (int32_t)b;
+      int lam = 0;
+      bool meet = true;
+      while (x != y) {
+        const int32_t px = parent[x], py = parent[y];
+        if (px < 0 || py < 0) {
+          meet = false;
+          break;
+        }
+        x = px;
+        y = py;
+        ++lam;
+      }
+      if (meet) {
+        double cl = 1.0, ch = 1.0;
+        for (int k = 0; k < lam; ++k) cl *= C;
+        for (int k = 0; k < ha - lam + 1; ++k) ch *= C;
+        v = cl * (1.0 - ch);
+      }
+    }
+    s_put(S, a * S.ld + b, v);
+  }
+}
+
 __global__ __launch_bounds__(kB) void fill_diag_kernel(double* A, int64_t n, int64_t ld,
                                                        double v) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -347,6 +390,16 @@ hipError_t launch_indicator2(double* x2, int64_t n, const IdList& a, const IdLis
                              hipStream_t s, const DevQ& dq, double* xd2) {
   if (n <= 0) return hipSuccess;
   indicator2_kernel<<<g1(n), kB, 0, s>>>(x2, n, a, b, dq, xd2);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int32_t* depth,
+                            double C, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t ncb = (n + kTreeCols - 1) / kTreeCols;
+  const int64_t grid = n * ncb;
+  if (grid >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  tree_init_kernel<<<(unsigned)grid, kTreeT, 0, s>>>(S, n, ncb, parent, depth, C);
   return hipGetLastError();
 }
 

@@ -283,6 +283,10 @@ hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t
 // Pairs (indicator of a, indicator of b) at x2[2 v], x2[2 v + 1], and x2 / d at xd2.
 hipError_t launch_indicator2(double* x2, int64_t n, const IdList& a, const IdList& b,
                              hipStream_t s, const DevQ& dq, double* xd2);
+// Writes S of a spanning forest (parent[v] = -1 for a root; depth[v] its level) into the
+// n x n block of the store by Example 1.2's closed form.
+hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int32_t* depth,
+                            double C, hipStream_t s);
 hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
 hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);

@@ -37,7 +37,7 @@ def default_config(**kw):
             v = _MODE[v] if isinstance(v, str) else v
         elif k == "gamma_form":
             v = _GAMMA[v] if isinstance(v, str) else v
-        elif k in ("prune", "fused_batch"):
+        elif k in ("prune", "fused_batch", "profile"):
             v = int(bool(v))
         setattr(cfg, k, v)
     return cfg
@@ -50,10 +50,14 @@ class Context:
     S (fixed point of eq (03a) on the device unless ``S0`` is given). Config keys follow
     ``sr_config``: C, K, K_ps, s_prec ('fp64' | 'hilo' | 'fp32'), mode ('dense' | 'column'),
     gamma_form ('closed' | 'direct'), prune, node_cap, edge_cap, init_tol, init_max_iter,
-    batch_chunk, fused_batch, split_rows.
+    batch_chunk, fused_batch, split_rows, profile.
     """
 
-    def __init__(self, n, src, dst, weight=None, S0=None, stream=None, **config):
+    def __init__(self, n, src, dst, weight=None, S0=None, stream=None, init="fixed_point",
+                 **config):
+        """``init="forest"`` seeds S from a breadth-first spanning forest and applies the
+        other edges as one batch (Example 1.2); the batch's statistics are kept in
+        ``self.init_stats``."""
         self.lib = L.load()
         self.cfg = default_config(**config)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -66,6 +70,23 @@ class Context:
         if S0 is not None:
             s0 = S0.to(device="cuda", dtype=torch.float64).contiguous()
         handle = C.c_void_p()
+        self.init_stats = None
+        if init == "forest":
+            if w is not None or s0 is not None:
+                raise ValueError("a forest-seeded context is unweighted and computes its own S")
+            s = L.sr_batch_stats()
+            st = self.lib.init_simrank_tree(
+                C.byref(handle), int(n), int(len(src)), _ptr(src, C.c_int32),
+                _ptr(dst, C.c_int32), C.byref(self.cfg), C.c_void_p(self.stream.cuda_stream),
+                C.byref(s))
+            L.check(st, "init_simrank_tree")
+            self.init_stats = {f: getattr(s, f) for f, _ in L.sr_batch_stats._fields_}
+            self.init_stats["blocks_case"] = list(s.blocks_case)
+            self.h = handle
+            self.m0 = len(src)
+            return
+        if init != "fixed_point":
+            raise ValueError(f"unknown init {init!r}")
         st = self.lib.init_simrank(
             C.byref(handle), int(n), int(len(src)), _ptr(src, C.c_int32), _ptr(dst, C.c_int32),
             _ptr(w, C.c_double) if w is not None else None, C.byref(self.cfg),

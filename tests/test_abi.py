@@ -49,6 +49,7 @@ def test_default_config_and_strerror():
     assert L.sr_default_config(ctypes.byref(cfg)) == 0
     assert cfg.C == 0.6 and cfg.K == 15 and cfg.K_ps == 30 and cfg.prune == 1
     assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 64 and cfg.split_rows == 65536
+    assert cfg.profile == 0 and cfg.reserved == 0
     assert L.sr_strerror(-3) == b"edge exists"
     assert L.sr_default_config(None) == _lib.SR_EINVAL
 
@@ -59,6 +60,7 @@ def test_null_context_arguments_are_rejected_without_gpu():
     assert L.apply_edge_update(None, 0, 1, 1, None) == _lib.SR_EINVAL
     assert L.sr_destroy(None) == _lib.SR_OK
     assert L.init_simrank(None, 10, 0, None, None, None, None, None, None) == _lib.SR_EINVAL
+    assert L.init_simrank_tree(None, 10, 0, None, None, None, None, None) == _lib.SR_EINVAL
 
 
 def test_struct_layout_matches_header():
@@ -73,7 +75,7 @@ int main(void) {
   printf("sr_update_stats %zu\n", sizeof(sr_update_stats));
   printf("sr_batch_stats %zu\n", sizeof(sr_batch_stats));
   F(sr_config, node_cap) F(sr_config, init_tol) F(sr_config, fused_batch)
-  F(sr_config, split_rows)
+  F(sr_config, split_rows) F(sr_config, profile)
   F(sr_update_stats, bound) F(sr_batch_stats, pairs) F(sr_batch_stats, fused_passes)
   return 0;
 }
