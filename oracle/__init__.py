@@ -20,6 +20,7 @@ What is here, by module:
 * ``tree``         all-pairs SimRank seeded from a breadth-first spanning forest (Example
                    1.2): the forest, its S by the example's closed form, and the other edges
                    applied as one Inc-bSR batch.
+* ``serving``      top-k single-source selection on a column of S and precision@k.
 * ``adjoint``      gradient of a pairwise squared loss on S with respect to edge weights,
                    by the transposed Sylvester iteration, and its finite-difference check.
                    The paper has no gradient; this follows from eq (03a) by the chain rule.
