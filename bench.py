@@ -22,6 +22,8 @@ The other workloads of the method are measured the same way with --workload:
   forest   the stream's graph (n = 20k, m = 200k); one step computes all-pairs S by seeding
            it from a breadth-first spanning forest (closed form) and applying the other
            edges as one batch, beside the fixed-point initialisation of the same graph
+  topk     the batch graph (n = 50k, m = 1M) after one batch of updates; one step serves
+           4,096 top-100 single-source queries from the stored S
   adjoint  n = 20k, m = 200k weighted (lognormal(0, 0.5)), dL/dw of a loss over 4,096 pairs
 """
 import argparse
@@ -49,7 +51,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "stream", "columns", "columns_batch", "forest", "adjoint"])
+                    choices=["batch", "stream", "columns", "columns_batch", "forest", "topk",
+                             "adjoint"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--max-batch", type=int, default=4096)
@@ -77,7 +80,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"batch": run_batch, "stream": run_stream, "columns": run_columns,
-           "columns_batch": run_columns_batch, "forest": run_forest,
+           "columns_batch": run_columns_batch, "forest": run_forest, "topk": run_topk,
            "adjoint": run_adjoint}[args.workload]
     print(json.dumps(run(args)), flush=True)
 
@@ -508,6 +511,58 @@ def run_forest(args):
     return out
 
 
+# ------------------------------------------------------------------------------ topk
+def run_topk(args, nq=4096, k=100):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context
+
+    cfg = W.WORKLOADS[3]
+    n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
+    log(f"bench: generating Chung-Lu n={n} m={m}")
+    s, d = W.chung_lu(n, m, seed=1003)
+    batches, counts = W.batch_stream(n, s, d, 1, args.max_batch, seed=2003)
+    ctx = Context(n, s, d, C=C, K=K, s_prec="hilo", node_cap=counts[-1] + 64,
+                  edge_cap=m + len(batches[0][0]) + 1024, batch_chunk=args.chunk,
+                  split_rows=args.split_rows)
+    ctx.apply_batch(*batches[0])
+    n_now = ctx.sizes()[0]
+    torch.cuda.synchronize()
+    log(f"bench: S ready after one batch, n = {n_now}")
+    steps = args.steps + args.warmup
+    qs = [W.rng(5003 + t).choice(n_now, nq, replace=False).astype(np.int32) for t in range(steps)]
+    out_buf = (torch.empty((nq, k), dtype=torch.int32, device="cuda"),
+               torch.empty((nq, k), dtype=torch.float64, device="cuda"))
+    for t in range(args.warmup):
+        ctx.query_topk(qs[t], k, out=out_buf)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for t in range(args.warmup, steps):
+        ctx.query_topk(qs[t], k, out=out_buf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    res = common(args, cfg, nq * args.steps / dt, "queries/s", dt, args.steps,
+                 extra_cfg={"workload": "topk_serving_n50k", "queries": nq, "k": k,
+                            "s_store": "f32 value + f32 compensation",
+                            "after": f"one batch of {len(batches[0][0])} edge updates"})
+    res["metric"] = "top-k single-source queries/s from the stored S after updates"
+    # each query reads its row of the store once: n entries of 8 B (value + compensation)
+    res["roofline"] = hbm_roof(8.0 * n_now * nq * args.steps, kern_ms, "topk_kernel",
+                               launches, "one row of the store per query (8 B per entry)")
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        rows = np.stack([ctx.query_column(int(x)).cpu().numpy() for x in qs[0][:256]])
+        res["cpu_baseline"] = cpu_baseline_topk(rows, qs[0][:256], k, args.cpu_seconds)
+    ctx.close()
+    return res
+
+
 # ------------------------------------------------------------------------------ adjoint
 def run_adjoint(args):
     import torch
@@ -738,6 +793,22 @@ def cpu_baseline_forest(K, n=900, m=9000):
     dt = time.perf_counter() - t0
     return {"value": float(n) * n / dt, "unit": "S entries/s", "cores": 1, "kind": "oracle",
             "sample": f"the whole pipeline at n = {n}, m = {m} (same generator and density), "
+                      f"{dt:.1f} s on one host thread"}
+
+
+def cpu_baseline_topk(rows, queries, k, seconds):
+    """The oracle's top-k selection on the same stored rows (copied to the host), cycling
+    through them until the time budget is used."""
+    from oracle import serving as Sv
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < seconds:
+        r = done % len(queries)
+        Sv.topk(rows[r], int(queries[r]), k)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} selections over {len(queries)} stored rows of the same S, "
                       f"{dt:.1f} s on one host thread"}
 
 

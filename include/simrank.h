@@ -195,6 +195,16 @@ sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev);
 sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* out_dev,
                         int64_t ld_out);
 
+/* Top-k single-source search after any updates: for each query x = q[t] (host array of nq
+ * ids < n), the k nodes b with the largest S[x][b], best first, ties to the smaller id, x
+ * itself left out when exclude_self is nonzero: idx_dev[t * k + r] (int32, device) and
+ * val_dev[t * k + r] (float64, device), r < k. Dense mode reads the stored row of x (S is
+ * symmetric) once per query; column mode computes S[:, x] by PartialSim (section 7, depth
+ * K_ps) two queries at a time first. 1 <= k <= 3072 and k <= n - (exclude_self ? 1 : 0),
+ * else SR_EINVAL; SR_ERANGE for a query id out of range. */
+sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
+                     int32_t exclude_self, int32_t* idx_dev, double* val_dev);
+
 /* Gathers S[a[p], b[p]] for npairs pairs into out_dev (float64); a_dev, b_dev device int32.
  * Dense mode. */
 sr_status sr_gather_pairs(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev,

@@ -1674,6 +1674,54 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
   return SR_OK;
 }
 
+sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
+                     int32_t exclude_self, int32_t* idx_dev, double* val_dev) {
+  if (!valid_ctx(ctx) || nq < 0 || (nq > 0 && (!q || !idx_dev || !val_dev))) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  const int64_t n = ctx->g.n;
+  if (k < 1 || k > kTopkMax || k > n - (exclude_self ? 1 : 0)) return SR_EINVAL;
+  for (int32_t t = 0; t < nq; ++t)
+    if (q[t] < 0 || q[t] >= n) return SR_ERANGE;
+  if (nq == 0) return SR_OK;
+  if (ctx->ids_cap < nq) {
+    HC(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_ids);
+    ctx->d_ids = nullptr;
+    ctx->ids_cap = 0;
+    if (dalloc(&ctx->d_ids, nq) != hipSuccess) return SR_ENOMEM;
+    ctx->ids_cap = nq;
+  }
+  HC(hipStreamSynchronize(ctx->stream));  // d_ids may be read by earlier work
+  HC(hipMemcpy(ctx->d_ids, q, (size_t)nq * 4, hipMemcpyHostToDevice));
+  hipStream_t s = ctx->stream;
+  const int ex = exclude_self ? 1 : 0;
+  if (ctx->cfg.mode == SR_DENSE) {
+    HC(profiled(ctx, [&]() {
+      return launch_topk(ctx->S, nullptr, 0, ctx->d_ids, nq, n, k, ex, idx_dev, val_dev, s);
+    }));
+    return SR_OK;
+  }
+  // column mode: the PartialSim columns of two queries at a time, then their selections
+  for (int32_t t = 0; t < nq; t += 2) {
+    IdList a, b;
+    a.count = b.count = 1;
+    a.id[0] = q[t];
+    b.id[0] = q[t + 1 < nq ? t + 1 : t];
+    sr_status r = partial_sim2(ctx, a, b, ctx->SI, ctx->Sj);
+    if (r != SR_OK) return r;
+    HC(profiled(ctx, [&]() {
+      return launch_topk(ctx->S, ctx->SI, 0, ctx->d_ids + t, 1, n, k, ex,
+                         idx_dev + (int64_t)t * k, val_dev + (int64_t)t * k, s);
+    }));
+    if (t + 1 < nq)
+      HC(profiled(ctx, [&]() {
+        return launch_topk(ctx->S, ctx->Sj, 0, ctx->d_ids + t + 1, 1, n, k, ex,
+                           idx_dev + (int64_t)(t + 1) * k, val_dev + (int64_t)(t + 1) * k, s);
+      }));
+  }
+  return SR_OK;
+}
+
 sr_status sr_gather_pairs(sr_ctx* ctx, int64_t np, const int32_t* a, const int32_t* b,
                           double* out) {
   if (!valid_ctx(ctx) || np < 0 || (np > 0 && (!a || !b || !out))) return SR_EINVAL;

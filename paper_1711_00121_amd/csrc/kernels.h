@@ -283,6 +283,12 @@ hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t
 // Pairs (indicator of a, indicator of b) at x2[2 v], x2[2 v + 1], and x2 / d at xd2.
 hipError_t launch_indicator2(double* x2, int64_t n, const IdList& a, const IdList& b,
                              hipStream_t s, const DevQ& dq, double* xd2);
+// Top-k of S row q[t] (or of vecs + t * ldv when vecs is set), ties to the smaller id, x
+// itself left out with exclude_self: out_idx / out_val[t * k + r], r < k, best first.
+constexpr int kTopkMax = 3072;
+hipError_t launch_topk(const SView& S, const double* vecs, int64_t ldv, const int32_t* q,
+                       int nq, int64_t n, int k, int exclude_self, int32_t* out_idx,
+                       double* out_val, hipStream_t s);
 // Writes S of a spanning forest (parent[v] = -1 for a root; depth[v] its level) into the
 // n x n block of the store by Example 1.2's closed form.
 hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int32_t* depth,

@@ -166,6 +166,19 @@ class Context:
                                        out.stride(0)), "query_columns")
         return out
 
+    def query_topk(self, q, k, exclude_self=True, out=None):
+        """Top-k most similar nodes of each query, best first (ties to the smaller id):
+        returns ``(idx, val)``, int32 and float64 tensors of shape ``(len(q), k)``."""
+        q = _i32(q)
+        if out is None:
+            out = (torch.empty((len(q), k), dtype=torch.int32, device="cuda"),
+                   torch.empty((len(q), k), dtype=torch.float64, device="cuda"))
+        idx, val = out
+        L.check(self.lib.query_topk(self.h, _ptr(q, C.c_int32), len(q), int(k),
+                                    int(bool(exclude_self)), _dev(idx), _dev(val)),
+                "query_topk")
+        return idx, val
+
     def gather_pairs(self, a, b):
         a = torch.as_tensor(a, dtype=torch.int32, device="cuda").contiguous()
         b = torch.as_tensor(b, dtype=torch.int32, device="cuda").contiguous()
