@@ -20,6 +20,9 @@ What is here, by module:
 * ``tree``         all-pairs SimRank seeded from a breadth-first spanning forest (Example
                    1.2): the forest, its S by the example's closed form, and the other edges
                    applied as one Inc-bSR batch.
+* ``partition``    all-pairs SimRank over a partitioned graph (Example 1.1): a breadth-first
+                   partitioner, S of the blocks computed block by block, and the cross-block
+                   edges applied as one Inc-bSR batch.
 * ``serving``      top-k single-source selection on a column of S and precision@k.
 * ``adjoint``      gradient of a pairwise squared loss on S with respect to edge weights,
                    by the transposed Sylvester iteration, and its finite-difference check.

@@ -98,3 +98,13 @@ def test_existing_batches_apply_in_sequence():
     one = W.existing_batches(n, s, d, 1, n_ins=10, n_del=4, shared=3, seed=98)[0]
     assert all(np.array_equal(x, y)
                for x, y in zip(one, W.existing_batch(n, s, d, 10, 4, 3, seed=98)))
+
+
+def test_communities_planted_groups():
+    n, m, parts = 1000, 6000, 5
+    s, d, g = W.communities(n, m, parts, 0.03, seed=99)
+    assert len(s) == m and len(set(zip(s.tolist(), d.tolist()))) == m and np.all(s != d)
+    assert np.bincount(g).tolist() == [200] * 5
+    assert (g[s] != g[d]).sum() == 180
+    s2, d2, g2 = W.communities(n, m, parts, 0.03, seed=99)
+    assert np.array_equal(s, s2) and np.array_equal(d, d2) and np.array_equal(g, g2)

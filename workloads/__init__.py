@@ -34,6 +34,8 @@ __all__ = [
     "column_sample",
     "with_hubs",
     "existing_batch",
+    "existing_batches",
+    "communities",
     "rng",
 ]
 
@@ -384,3 +386,41 @@ def existing_batches(n, src, dst, count, n_ins, n_del, shared, seed):
         out.append((np.asarray(bi, dtype=np.int32), np.asarray(bj, dtype=np.int32),
                     np.asarray(ops, dtype=np.int8)))
     return out
+
+
+def communities(n, m, parts, p_cross, seed):
+    """A digraph with planted communities: nodes are dealt into ``parts`` groups of near-equal
+    size under a seeded permutation (so a group's ids are scattered), each group holds a
+    Chung-Lu graph on its own nodes, and a fraction ``p_cross`` of the m edges joins uniformly
+    drawn nodes of different groups. Returns int32 ``(src, dst)`` and the int32 group of every
+    node (the planted labels, for reference)."""
+    g = rng(seed)
+    perm = g.permutation(n)
+    group = np.empty(n, dtype=np.int32)
+    sizes = [n // parts + (1 if p < n % parts else 0) for p in range(parts)]
+    members, start = [], 0
+    for p, sz in enumerate(sizes):
+        members.append(perm[start:start + sz])
+        group[perm[start:start + sz]] = p
+        start += sz
+    n_cross = int(round(m * p_cross))
+    src, dst = [], []
+    left = m - n_cross
+    for p, mem in enumerate(members):
+        mp = left // (parts - p)
+        left -= mp
+        s, d = chung_lu(len(mem), mp, seed=int(g.integers(1 << 31)))
+        src.append(mem[s])
+        dst.append(mem[d])
+    es = set(zip(np.concatenate(src).tolist(), np.concatenate(dst).tolist()))
+    cs, cd = [], []
+    while len(cs) < n_cross:
+        a, b = (int(v) for v in g.integers(n, size=2))
+        if group[a] != group[b] and (a, b) not in es:
+            es.add((a, b))
+            cs.append(a)
+            cd.append(b)
+    src = np.concatenate(src + [np.asarray(cs, dtype=np.int64)]).astype(np.int32)
+    dst = np.concatenate(dst + [np.asarray(cd, dtype=np.int64)]).astype(np.int32)
+    order = g.permutation(len(src))
+    return src[order], dst[order], group
