@@ -22,6 +22,9 @@ The other workloads of the method are measured the same way with --workload:
   forest   the stream's graph (n = 20k, m = 200k); one step computes all-pairs S by seeding
            it from a breadth-first spanning forest (closed form) and applying the other
            edges as one batch, beside the fixed-point initialisation of the same graph
+  partitioned  n = 20k, m = 200k with 16 planted communities (1% of edges across them);
+           one step partitions the graph (16 blocks), computes S of the blocks block by
+           block and applies the cross-block edges as one batch
   topk     the batch graph (n = 50k, m = 1M) after one batch of updates; one step serves
            4,096 top-100 single-source queries from the stored S
   adjoint  n = 20k, m = 200k weighted (lognormal(0, 0.5)), dL/dw of a loss over 4,096 pairs
@@ -51,8 +54,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "stream", "columns", "columns_batch", "forest", "topk",
-                             "adjoint"])
+                    choices=["batch", "stream", "columns", "columns_batch", "forest",
+                             "partitioned", "topk", "adjoint"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--max-batch", type=int, default=4096)
@@ -80,7 +83,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     run = {"batch": run_batch, "stream": run_stream, "columns": run_columns,
-           "columns_batch": run_columns_batch, "forest": run_forest, "topk": run_topk,
+           "columns_batch": run_columns_batch, "forest": run_forest,
+           "partitioned": run_partitioned, "topk": run_topk,
            "adjoint": run_adjoint}[args.workload]
     print(json.dumps(run(args)), flush=True)
 
@@ -511,6 +515,83 @@ def run_forest(args):
     return out
 
 
+# ------------------------------------------------------------------------------ partitioned
+def run_partitioned(args, parts=16, p_cross=0.01):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1711_00121_amd import Context, partition
+
+    cfg = W.WORKLOADS[2]
+    n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
+    log(f"bench: generating {parts} planted communities n={n} m={m}")
+    s, d, _ = W.communities(n, m, parts, p_cross, seed=1102)
+    common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk,
+                      split_rows=args.split_rows)
+
+    def build(profile=False):
+        lab = partition(n, s, d, parts)
+        return Context(n, s, d, init="partitioned", part=lab, profile=profile, **common_cfg)
+
+    for w in range(args.warmup):
+        build().close()
+        torch.cuda.synchronize()
+    times, kern_ms, launches = [], 0.0, 0
+    ctx = None
+    for k in range(args.steps):
+        if ctx is not None:
+            ctx.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = build(profile=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ms, cnt = ctx.profile_read(reset=True)
+        kern_ms += ms
+        launches += cnt
+        log(f"bench: step {k}: {times[-1]:.2f} s, {ctx.init_stats['edges_in']} cross edges, "
+            f"{ctx.init_stats['blocks']} blocks")
+    st = ctx.init_stats
+    dt = float(np.sum(times))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ref = Context(n, s, d, **common_cfg)
+    torch.cuda.synchronize()
+    t_fixed = time.perf_counter() - t1
+    diff = float((ctx.S() - ref.S()).abs().max())
+    ref.close()
+    out = common(args, cfg, float(n) * n * args.steps / dt, "S entries/s", dt, args.steps,
+                 extra_cfg={"workload": "partitioned_n20k", "parts": parts,
+                            "planted_cross_fraction": p_cross,
+                            "s_store": "f32 value + f32 compensation",
+                            "batch_chunk": args.chunk})
+    out["metric"] = ("all-pairs SimRank over a partitioned graph (Example 1.1), S entries/s")
+    out["seconds_per_all_pairs"] = dt / args.steps
+    out["partition"] = {"cross_edges": st["edges_in"], "blocks": st["blocks"],
+                        "lowrank_blocks": st["lowrank_blocks"],
+                        "fused_passes": st["fused_passes"]}
+    out["fixed_point_init_s"] = t_fixed
+    out["max_abs_vs_fixed_point"] = diff
+    pld = 2 * (K + 1)
+    flops = float(n) * (n + 1.0) * pld * st["lowrank_blocks"] * args.steps
+    achieved = flops / (kern_ms / 1e3) / 1e12 if kern_ms > 0 else 0.0
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                       "traffic": traffic("lowrank_gemm_kernel"),
+                       "kernel": "lowrank_gemm_kernel (fused batch pass)",
+                       "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
+                       "share_of_step": round(kern_ms / (1e3 * dt), 3),
+                       "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per "
+                                      "low-rank block"}
+    ctx.close()
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_partitioned(K, parts, p_cross)
+    return out
+
+
 # ------------------------------------------------------------------------------ topk
 def run_topk(args, nq=4096, k=100):
     import numpy as np
@@ -810,6 +891,25 @@ def cpu_baseline_topk(rows, queries, k, seconds):
     return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} selections over {len(queries)} stored rows of the same S, "
                       f"{dt:.1f} s on one host thread"}
+
+
+def cpu_baseline_partitioned(K, parts, p_cross, n=1200, m=12000):
+    """The oracle's whole partitioned pipeline (partition, block fixed points, Inc-bSR of the
+    cross edges) on a smaller graph of the same generator and density, scaled to S
+    entries/s; its dense products are held to one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import partition as OP
+    s, d, _ = W.communities(n, m, parts, p_cross, seed=1102)
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        lab = OP.bfs_partition(n, s, d, parts)
+        OP.partitioned(n, s, d, lab, C, K)
+    dt = time.perf_counter() - t0
+    return {"value": float(n) * n / dt, "unit": "S entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole pipeline at n = {n}, m = {m} ({parts} planted communities, "
+                      f"same density), {dt:.1f} s on one host thread"}
 
 
 def cpu_baseline_gradient(n, s, d, w, a, b, seconds):

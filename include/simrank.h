@@ -149,6 +149,27 @@ sr_status init_simrank_tree(sr_ctx** out, int64_t n, int64_t m, const int32_t* s
                             const int32_t* dst, const sr_config* cfg, void* hip_stream,
                             sr_batch_stats* stats);
 
+/* Graph partitioner for init_simrank_partitioned (host only, no GPU work): blocks of at most
+ * ceil(n / parts) nodes grown breadth first over the undirected graph. A block starts at the
+ * smallest unassigned id and scans neighbours in ascending id; a full block stops at once, and
+ * one whose search runs dry continues from the smallest unassigned id. part_out: host array
+ * of n block labels 0, 1, ... SR_EINVAL for parts < 1, SR_ERANGE for an edge out of range. */
+sr_status sr_partition(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                       int32_t parts, int32_t* part_out);
+
+/* All-pairs SimRank over a partitioned graph (Example 1.1): with part[v] the block of node v
+ * (host array, any labels in [0, n), e.g. from sr_partition), S of the edges inside blocks is
+ * block diagonal; each block's S is computed on its own nodes (the fixed point of eq (03a),
+ * float64) and placed on the diagonal of the store, then the edges across blocks are applied,
+ * in the caller's order, as one apply_batch of insertions. The result is S of the whole graph
+ * up to the K-term truncation of each block of the batch. cfg: as init_simrank, mode must be
+ * SR_DENSE (SR_EMODE otherwise), edge_cap 0 means 2 m + 1024. Unweighted only. stats: NULL,
+ * or the batch's statistics. On any error nothing is returned (*out = NULL). */
+sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                                   const int32_t* dst, const int32_t* part,
+                                   const sr_config* cfg, void* hip_stream,
+                                   sr_batch_stats* stats);
+
 /* Applies one edge update, op = +1 insert or -1 delete (Algorithms 1 and 2, Theorem 9;
  * node insertions: Algorithms 3, 4, 5 with the new ids i == n (C2), j == n (C1), or
  * i == n, j == n + 1 (C3)). Dense mode updates S; column mode keeps the series vectors of

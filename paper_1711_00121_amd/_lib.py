@@ -81,6 +81,9 @@ SIGNATURES = {
                                C.POINTER(sr_config), P, P]),
     "init_simrank_tree": (C.c_int, [C.POINTER(P), C.c_int64, C.c_int64, I32P, I32P,
                                     C.POINTER(sr_config), P, C.POINTER(sr_batch_stats)]),
+    "sr_partition": (C.c_int, [C.c_int64, C.c_int64, I32P, I32P, C.c_int32, I32P]),
+    "init_simrank_partitioned": (C.c_int, [C.POINTER(P), C.c_int64, C.c_int64, I32P, I32P, I32P,
+                                           C.POINTER(sr_config), P, C.POINTER(sr_batch_stats)]),
     "apply_edge_update": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(sr_update_stats)]),
     "apply_batch": (C.c_int, [P, C.c_int64, I32P, I32P, I8P, C.POINTER(sr_batch_stats)]),

@@ -732,12 +732,14 @@ sr_status sr_destroy(sr_ctx* ctx) {
   return SR_OK;
 }
 
-// Context set-up shared by init_simrank and init_simrank_tree. With tree_parent, the graph is
-// a spanning forest (tree_parent / tree_depth per node) and S is its closed form.
+// Context set-up shared by init_simrank, init_simrank_tree and init_simrank_partitioned. With
+// tree_parent, the graph is a spanning forest (tree_parent / tree_depth per node) and S is its
+// closed form; with block_part, every edge lies inside a block (block_part per node) and S is
+// computed block by block.
 static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
                            const int32_t* dst, const double* weight, const sr_config* cfg_in,
                            const void* S0, void* hip_stream, const int32_t* tree_parent,
-                           const int32_t* tree_depth) {
+                           const int32_t* tree_depth, const int32_t* block_part) {
   if (!out || n <= 0 || m < 0 || (m > 0 && (!src || !dst))) return SR_EINVAL;
   *out = nullptr;
   sr_config cfg;
@@ -897,6 +899,53 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
     IC(hipMemset(ctx->S_mem[0], 0, cells * 4));
   }
 
+  if (block_part) {
+    // S of the blocks' own edges, block by block (Example 1.1): each block's fixed point on a
+    // context of its own nodes (float64), placed on the diagonal of the store
+    int32_t np = 0;
+    for (int64_t v = 0; v < n; ++v) np = std::max(np, block_part[v] + 1);
+    std::vector<std::vector<int32_t>> mem(np), bs(np), bd(np);
+    std::vector<int32_t> loc(n);
+    for (int32_t v = 0; v < n; ++v) {
+      loc[v] = (int32_t)mem[block_part[v]].size();
+      mem[block_part[v]].push_back(v);
+    }
+    for (int64_t e = 0; e < m; ++e) {
+      const int32_t p = block_part[dst[e]];
+      bs[p].push_back(loc[src[e]]);
+      bd[p].push_back(loc[dst[e]]);
+    }
+    sr_config bc = cfg;
+    bc.mode = SR_DENSE;
+    bc.s_prec = SR_S_FP64;
+    bc.node_cap = 0;
+    bc.edge_cap = 0;
+    bc.profile = 0;
+    int32_t* dg = nullptr;
+    hipError_t e = hipMalloc(&dg, (size_t)n * 4);
+    sr_status bst = SR_OK;
+    for (int32_t p = 0; p < np && e == hipSuccess && bst == SR_OK; ++p) {
+      const int64_t nb = (int64_t)mem[p].size();
+      if (nb == 0) continue;
+      sr_ctx* b = nullptr;
+      bst = init_impl(&b, nb, (int64_t)bs[p].size(), bs[p].data(), bd[p].data(), nullptr, &bc,
+                      nullptr, hip_stream, nullptr, nullptr, nullptr);
+      if (bst != SR_OK) break;
+      e = hipMemcpy(dg, mem[p].data(), (size_t)nb * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = launch_place_block(ctx->S, dg, nb, b->S.d, b->S.ld, ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      sr_destroy(b);
+    }
+    (void)hipFree(dg);
+    if (bst != SR_OK || e != hipSuccess) {
+      sr_destroy(ctx);
+      return bst != SR_OK ? bst : SR_EHIP;
+    }
+    ctx->updated = false;
+    *out = ctx;
+    return SR_OK;
+  }
+
   if (tree_parent) {
     // S of the forest by Example 1.2's closed form, written straight into the store
     int32_t *dp = nullptr, *dd = nullptr;
@@ -979,7 +1028,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
 sr_status init_simrank(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
                        const int32_t* dst, const double* weight, const sr_config* cfg_in,
                        const void* S0, void* hip_stream) {
-  return init_impl(out, n, m, src, dst, weight, cfg_in, S0, hip_stream, nullptr, nullptr);
+  return init_impl(out, n, m, src, dst, weight, cfg_in, S0, hip_stream, nullptr, nullptr,
+                   nullptr);
 }
 
 sr_status init_simrank_tree(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
@@ -1053,10 +1103,119 @@ sr_status init_simrank_tree(sr_ctx** out, int64_t n, int64_t m, const int32_t* s
   if ((int64_t)(ts.size() + rs.size()) != m) return SR_EEXIST;  // a forest edge given twice
   sr_ctx* ctx = nullptr;
   sr_status st = init_impl(&ctx, n, (int64_t)ts.size(), ts.data(), td.data(), nullptr, &cfg,
-                           nullptr, hip_stream, parent.data(), depth.data());
+                           nullptr, hip_stream, parent.data(), depth.data(), nullptr);
   if (st != SR_OK) return st;
   std::vector<int8_t> ops(rs.size(), 1);
   st = apply_batch(ctx, (int64_t)rs.size(), rs.data(), rd.data(), ops.data(), stats);
+  if (st != SR_OK) {
+    sr_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return SR_OK;
+}
+
+sr_status sr_partition(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                       int32_t parts, int32_t* part_out) {
+  if (n <= 0 || m < 0 || parts < 1 || !part_out || (m > 0 && (!src || !dst))) return SR_EINVAL;
+  for (int64_t e = 0; e < m; ++e)
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return SR_ERANGE;
+  // undirected neighbour lists, ascending and without repeats
+  std::vector<int64_t> start(n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    ++start[src[e] + 1];
+    ++start[dst[e] + 1];
+  }
+  for (int64_t v = 0; v < n; ++v) start[v + 1] += start[v];
+  std::vector<int32_t> nb(2 * m);
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t e = 0; e < m; ++e) {
+      nb[fill[src[e]]++] = dst[e];
+      nb[fill[dst[e]]++] = src[e];
+    }
+  }
+  std::vector<int64_t> len(n);
+  for (int64_t v = 0; v < n; ++v) {
+    auto b = nb.begin() + start[v], e = nb.begin() + start[v + 1];
+    std::sort(b, e);
+    len[v] = std::unique(b, e) - b;
+  }
+  // blocks of at most ceil(n / parts) nodes, grown breadth first from the smallest
+  // unassigned id; a full block stops at once, a dry search continues from the next seed
+  const int64_t cap = (n + parts - 1) / parts;
+  for (int64_t v = 0; v < n; ++v) part_out[v] = -1;
+  std::vector<int32_t> queue;
+  queue.reserve(n);
+  int32_t p = 0;
+  int64_t size = 0, next = 0;
+  while (true) {
+    while (next < n && part_out[next] >= 0) ++next;
+    if (next == n) break;
+    part_out[next] = p;
+    ++size;
+    queue.clear();
+    queue.push_back((int32_t)next);
+    bool full = size == cap;
+    for (size_t h = 0; h < queue.size() && !full; ++h) {
+      const int32_t u = queue[h];
+      for (int64_t q = start[u]; q < start[u] + len[u]; ++q) {
+        const int32_t v = nb[q];
+        if (part_out[v] < 0) {
+          part_out[v] = p;
+          ++size;
+          queue.push_back(v);
+          if (size == cap) {
+            full = true;
+            break;
+          }
+        }
+      }
+    }
+    if (full) {
+      ++p;
+      size = 0;
+    }
+  }
+  return SR_OK;
+}
+
+sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                                   const int32_t* dst, const int32_t* part,
+                                   const sr_config* cfg_in, void* hip_stream,
+                                   sr_batch_stats* stats) {
+  if (!out || n <= 0 || m < 0 || !part || (m > 0 && (!src || !dst))) return SR_EINVAL;
+  *out = nullptr;
+  sr_config cfg;
+  if (cfg_in) {
+    cfg = *cfg_in;
+  } else {
+    sr_default_config(&cfg);
+  }
+  if (cfg.mode != SR_DENSE) return SR_EMODE;
+  for (int64_t v = 0; v < n; ++v)
+    if (part[v] < 0 || part[v] >= n) return SR_ERANGE;
+  for (int64_t e = 0; e < m; ++e) {
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return SR_ERANGE;
+    if (src[e] == dst[e]) return SR_ESELF;
+  }
+  if (cfg.edge_cap <= 0) cfg.edge_cap = 2 * m + 1024;
+  std::vector<int32_t> is, id, cs, cd;
+  for (int64_t e = 0; e < m; ++e) {
+    if (part[src[e]] == part[dst[e]]) {
+      is.push_back(src[e]);
+      id.push_back(dst[e]);
+    } else {
+      cs.push_back(src[e]);
+      cd.push_back(dst[e]);
+    }
+  }
+  sr_ctx* ctx = nullptr;
+  sr_status st = init_impl(&ctx, n, (int64_t)is.size(), is.data(), id.data(), nullptr, &cfg,
+                           nullptr, hip_stream, nullptr, nullptr, part);
+  if (st != SR_OK) return st;
+  std::vector<int8_t> ops(cs.size(), 1);
+  st = apply_batch(ctx, (int64_t)cs.size(), cs.data(), cd.data(), ops.data(), stats);
   if (st != SR_OK) {
     sr_destroy(ctx);
     return st;

@@ -1,6 +1,8 @@
 // Dense-S kernels: row gathers and the gamma vector of the rank-one Sylvester equation
 // (Theorems 2, 3, 7, 9 and Table 2), new-node writes (Theorem 8, Algorithm 5), the initial S
 // by the fixed point of eq (03a), and queries.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace sr {
@@ -363,6 +365,16 @@ __global__ __launch_bounds__(kTreeT) void tree_init_kernel(SView S, int64_t n, i
   }
 }
 
+// Places a block's float64 S (nb x nb, leading dimension ldb) at the rows and columns of its
+// nodes: S[gid[a]][gid[b]] = Sb[a][b].
+__global__ __launch_bounds__(kB) void place_block_kernel(SView S, const int32_t* gid, int64_t nb,
+                                                         const double* Sb, int64_t ldb) {
+  const int64_t a = blockIdx.x;
+  const int64_t row = (int64_t)gid[a] * S.ld;
+  for (int64_t b = (int64_t)blockIdx.y * kB + threadIdx.x; b < nb; b += (int64_t)gridDim.y * kB)
+    s_put(S, row + gid[b], Sb[a * ldb + b]);
+}
+
 __global__ __launch_bounds__(kB) void fill_diag_kernel(double* A, int64_t n, int64_t ld,
                                                        double v) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
@@ -400,6 +412,14 @@ hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int
   const int64_t grid = n * ncb;
   if (grid >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   tree_init_kernel<<<(unsigned)grid, kTreeT, 0, s>>>(S, n, ncb, parent, depth, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_place_block(SView S, const int32_t* gid, int64_t nb, const double* Sb,
+                              int64_t ldb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  const unsigned gy = (unsigned)std::min<int64_t>((nb + kB - 1) / kB, 64);
+  place_block_kernel<<<dim3((unsigned)nb, gy), kB, 0, s>>>(S, gid, nb, Sb, ldb);
   return hipGetLastError();
 }
 

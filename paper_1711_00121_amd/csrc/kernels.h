@@ -289,6 +289,9 @@ constexpr int kTopkMax = 3072;
 hipError_t launch_topk(const SView& S, const double* vecs, int64_t ldv, const int32_t* q,
                        int nq, int64_t n, int k, int exclude_self, int32_t* out_idx,
                        double* out_val, hipStream_t s);
+// Places a block's float64 S at its nodes' rows and columns of the store.
+hipError_t launch_place_block(SView S, const int32_t* gid, int64_t nb, const double* Sb,
+                              int64_t ldb, hipStream_t s);
 // Writes S of a spanning forest (parent[v] = -1 for a root; depth[v] its level) into the
 // n x n block of the store by Example 1.2's closed form.
 hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int32_t* depth,

@@ -43,6 +43,17 @@ def default_config(**kw):
     return cfg
 
 
+def partition(n, src, dst, parts):
+    """Block labels from the library's breadth-first partitioner (host only)."""
+    src = _i32(src)
+    dst = _i32(dst)
+    out = np.empty(int(n), dtype=np.int32)
+    L.check(L.load().sr_partition(int(n), int(len(src)), _ptr(src, C.c_int32),
+                                  _ptr(dst, C.c_int32), int(parts), _ptr(out, C.c_int32)),
+            "sr_partition")
+    return out
+
+
 class Context:
     """One incremental-SimRank context on the current CUDA (HIP) device and stream.
 
@@ -54,10 +65,12 @@ class Context:
     """
 
     def __init__(self, n, src, dst, weight=None, S0=None, stream=None, init="fixed_point",
-                 **config):
+                 part=None, parts=None, **config):
         """``init="forest"`` seeds S from a breadth-first spanning forest and applies the
-        other edges as one batch (Example 1.2); the batch's statistics are kept in
-        ``self.init_stats``."""
+        other edges as one batch (Example 1.2); ``init="partitioned"`` computes S of the
+        blocks ``part`` (labels per node, or ``parts`` blocks from ``partition``) block by
+        block and applies the cross-block edges as one batch (Example 1.1). The batch's
+        statistics are kept in ``self.init_stats``."""
         self.lib = L.load()
         self.cfg = default_config(**config)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -80,6 +93,25 @@ class Context:
                 _ptr(dst, C.c_int32), C.byref(self.cfg), C.c_void_p(self.stream.cuda_stream),
                 C.byref(s))
             L.check(st, "init_simrank_tree")
+            self.init_stats = {f: getattr(s, f) for f, _ in L.sr_batch_stats._fields_}
+            self.init_stats["blocks_case"] = list(s.blocks_case)
+            self.h = handle
+            self.m0 = len(src)
+            return
+        if init == "partitioned":
+            if w is not None or s0 is not None:
+                raise ValueError("a partitioned context is unweighted and computes its own S")
+            if part is None:
+                part = partition(n, src, dst, parts)
+            self.part = _i32(part)
+            if len(self.part) != n:
+                raise ValueError("part needs one label per node")
+            s = L.sr_batch_stats()
+            st = self.lib.init_simrank_partitioned(
+                C.byref(handle), int(n), int(len(src)), _ptr(src, C.c_int32),
+                _ptr(dst, C.c_int32), _ptr(self.part, C.c_int32), C.byref(self.cfg),
+                C.c_void_p(self.stream.cuda_stream), C.byref(s))
+            L.check(st, "init_simrank_partitioned")
             self.init_stats = {f: getattr(s, f) for f, _ in L.sr_batch_stats._fields_}
             self.init_stats["blocks_case"] = list(s.blocks_case)
             self.h = handle

@@ -403,7 +403,7 @@ def communities(n, m, parts, p_cross, seed):
         members.append(perm[start:start + sz])
         group[perm[start:start + sz]] = p
         start += sz
-    n_cross = int(round(m * p_cross))
+    n_cross = int(round(m * p_cross)) if parts > 1 else 0
     src, dst = [], []
     left = m - n_cross
     for p, mem in enumerate(members):
