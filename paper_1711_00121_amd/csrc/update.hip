@@ -286,6 +286,8 @@ __device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64
   J = i + (t - (i * T - i * (i - 1) / 2));
 }
 
+constexpr int64_t kRectGroup = 8;
+
 // RECT (column mode, batches): a rectangular product accumulated into a float64 output,
 //     acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1]   (p < nrows, a < ncols),
 // over T row tiles (list positions) x TJ column tiles (nodes), without the symmetry; A rows
@@ -299,9 +301,15 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
   const int64_t t = (w % NXCD) * per + w / NXCD;
   int64_t I, J;
   if constexpr (RECT) {
+    // Tiles in groups of kRectGroup row tiles, column-major inside a group: the workgroups
+    // running together on one XCD share one column tile (a slice of the panel, read from HBM
+    // once per group) and the group's row tiles (gathered rows, small enough to stay cached).
     if (t >= T * TJ) return;
-    I = t / TJ;
-    J = t % TJ;
+    const int64_t gsz = kRectGroup * TJ;
+    const int64_t grp = t / gsz, in = t % gsz;
+    const int64_t gm = (T - grp * kRectGroup) < kRectGroup ? (T - grp * kRectGroup) : kRectGroup;
+    I = grp * kRectGroup + in % gm;
+    J = in / gm;
   } else {
     if (t >= T * (T + 1) / 2) return;
     tri_tile(t, T, I, J);
