@@ -8,7 +8,7 @@
 // buffer is sorted (bitonic, by value descending then id ascending), cut to k entries, and the
 // threshold becomes the k-th value. A later entry equal to the threshold has a larger id than
 // every kept one, so the strict comparison also keeps the tie rule. The row is read once.
-// For k <= 256 one wave per query does the same without workgroup barriers.
+// For k <= 1024 one wave per query does the same without workgroup barriers.
 #include <type_traits>
 
 #include "kernels.h"
@@ -191,12 +191,14 @@ __global__ __launch_bounds__(kT) void topk_kernel(SView S, const double* vecs, i
 // The same selection by one wave per query, for k <= kWaveK: no workgroup barriers, 16
 // entries per lane per group of loads (1,024 per group, two groups in flight). The buffer is
 // cut back to k whenever it reaches about 2k entries, so it never holds more than
-// 2 * kWaveK entries and each sort is small.
-constexpr int kWaveK = 256;
+// 2 * kWaveK entries and each sort is small. Two buffer sizes: k <= 256 in 512 entries (6 KB
+// of LDS, so registers rather than LDS bound the waves per CU) and k <= 1024 in 2,048.
+constexpr int kWaveK = 1024;
+constexpr int kWaveKSmall = 256;
 constexpr int kWCap = 2 * kWaveK;
 constexpr int kWU = 16;
 
-// Sorts the first N entries (N a power of two, 64 <= N <= kWCap). Each lane takes up to four
+// Sorts the first N entries (N a power of two, 64 <= N <= the buffer size). Each lane takes up to four
 // pairs of a step at once: all their reads, then the compare-exchanges and writes (the pairs of
 // one step are disjoint).
 __device__ __noinline__ void bitonic_wave(uint64_t* key, int32_t* id, int N) {
@@ -235,13 +237,14 @@ __device__ __noinline__ void bitonic_wave(uint64_t* key, int32_t* id, int N) {
   }
 }
 
-template <int PREC>
+template <int PREC, int CAP>
 __global__ __launch_bounds__(64) void topk_wave_kernel(SView S, const double* vecs, int64_t ldv,
                                                        const int32_t* q, int64_t n, int k,
                                                        int exclude_self, int32_t* out_idx,
                                                        double* out_val) {
-  __shared__ uint64_t key[kWCap];
-  __shared__ int32_t id[kWCap];
+  static_assert(CAP <= kWCap, "wave buffer");
+  __shared__ uint64_t key[CAP];
+  __shared__ int32_t id[CAP];
   const int t = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t x = q[t];
@@ -326,15 +329,22 @@ hipError_t launch_topk(const SView& S, const double* vecs, int64_t ldv, const in
   static_assert(kTopkMax == kCap - kT, "top-k bound");
   if (k < 1 || k > kTopkMax || n <= 0) return hipErrorInvalidValue;
   if (k <= kWaveK) {
-    if (vecs || S.prec == PREC_FP64)
-      topk_wave_kernel<PREC_FP64><<<nq, 64, 0, s>>>(S, vecs, ldv, q, n, k, exclude_self,
-                                                    out_idx, out_val);
-    else if (S.prec == PREC_HILO)
-      topk_wave_kernel<PREC_HILO><<<nq, 64, 0, s>>>(S, nullptr, 0, q, n, k, exclude_self,
-                                                    out_idx, out_val);
+    auto wave = [&](auto cap) {
+      constexpr int CAP = decltype(cap)::value;
+      if (vecs || S.prec == PREC_FP64)
+        topk_wave_kernel<PREC_FP64, CAP><<<nq, 64, 0, s>>>(S, vecs, ldv, q, n, k, exclude_self,
+                                                           out_idx, out_val);
+      else if (S.prec == PREC_HILO)
+        topk_wave_kernel<PREC_HILO, CAP><<<nq, 64, 0, s>>>(S, nullptr, 0, q, n, k,
+                                                           exclude_self, out_idx, out_val);
+      else
+        topk_wave_kernel<PREC_FP32, CAP><<<nq, 64, 0, s>>>(S, nullptr, 0, q, n, k,
+                                                           exclude_self, out_idx, out_val);
+    };
+    if (k <= kWaveKSmall)
+      wave(std::integral_constant<int, 2 * kWaveKSmall>{});
     else
-      topk_wave_kernel<PREC_FP32><<<nq, 64, 0, s>>>(S, nullptr, 0, q, n, k, exclude_self,
-                                                    out_idx, out_val);
+      wave(std::integral_constant<int, 2 * kWaveK>{});
     return hipGetLastError();
   }
   if (vecs) {
