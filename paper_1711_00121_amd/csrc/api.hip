@@ -1672,7 +1672,13 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
   const int pld = ctx->pld;
   const int chunk = ctx->cfg.batch_chunk > 0 ? ctx->cfg.batch_chunk : 1;
   const int64_t gstride = ctx->p_rows * pld;
-  // deferred panels (block-major); columns past 2(K+1) and rows past n stay zero
+  // Deferred blocks share one packed panel: block q's 2(K+1) columns are global columns
+  // q 2(K+1) .. (q + 1) 2(K+1) - 1, stored in slabs of 16 columns (node-major inside a slab),
+  // so the matrix-core pass runs over no padding but the last slab's tail. Rows past n stay
+  // zero. The slabs of `chunk` blocks fit in the chunk x pld columns allocated.
+  const int w = 2 * (K + 1);
+  const int64_t slab = ctx->p_rows * 16;
+  auto at = [&](int64_t col) { return ctx->Pb + (col / 16) * slab + col % 16; };
   if (!ctx->Pb) {
     if (dalloc(&ctx->Pb, gstride * chunk) != hipSuccess) return SR_ENOMEM;
     HC(hipMemsetAsync(ctx->Pb, 0, (size_t)gstride * chunk * 8, s));
@@ -1696,12 +1702,17 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
       q = 0;
       return SR_OK;
     }
+    // columns past the last block in its slab may hold an earlier pass's values: clear them
+    const int64_t rc = (int64_t)q * w;
+    if (rc % 16)
+      HC(hipMemset2DAsync(at(rc), 16 * 8, 0, (size_t)(16 - rc % 16) * 8, (size_t)ctx->p_rows,
+                          s));
     LowRankArgs la{};
     la.P = ctx->Pb;
-    la.pld = pld;
-    la.gstride = gstride;
+    la.pld = 16;
+    la.gstride = slab;
     la.p_rows = ctx->p_rows;
-    la.r = q * pld;
+    la.r = (int)((rc + 15) / 16 * 16);
     la.rows = ctx->d_ids;
     la.nrows = ncols;
     la.ncols = n;
@@ -1720,7 +1731,7 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
     ctx->last_plan.push_back((int32_t)b.dj);
     ctx->last_plan.push_back((int32_t)b.I.size());
     for (int32_t i : b.I) ctx->last_plan.push_back(i);
-    double* P = ctx->Pb + (int64_t)q * gstride;
+    const int64_t c0 = (int64_t)q * w;  // this block's first packed column
     // S[:, I] and S[:, j] on the current graph (PartialSim), Q S[:, I], then Table 2 (C0)
     const IdList il = idlist(b.I, 0, b.I.size());
     IdList lj;
@@ -1738,14 +1749,20 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
     ga.C = C;
     ga.xi0 = C;
     ga.I = il;
-    HC(launch_gamma(ga, n, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, P, pld, nullptr, s));
+    HC(launch_gamma(ga, n, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, at(c0), 16, nullptr,
+                    s));
     std::vector<std::pair<int32_t, int32_t>> e;
     for (int32_t i : b.I) e.push_back({i, b.j});
     r = edit_graph(ctx, e, b.op);
     if (r != SR_OK) return r;
-    for (int k = 0; k < K; ++k)
-      HC(launch_series_step(devq(ctx), heavy_args(ctx->hin), n, P, pld, k, C, 1.0, nullptr, s,
-                            ctx->pairs, ctx->node_cap));
+    // step k reads (xi_k, eta_k): from the panel at k = 0, else from the compact copy the
+    // previous step wrote; it writes (xi_{k+1}, eta_{k+1}) to the panel and a compact copy
+    for (int k = 0; k < K; ++k) {
+      const double* src = k == 0 ? at(c0) : ctx->pairs + ((k - 1) % 2) * 2 * ctx->node_cap;
+      double* cdst = ctx->pairs + (k % 2) * 2 * ctx->node_cap;
+      HC(launch_series_step_to(devq(ctx), heavy_args(ctx->hin), n, at(c0 + 2 * (k + 1)), 16,
+                               src, k == 0 ? 16 : 2, cdst, C, 1.0, s));
+    }
     if (++q == chunk) {
       r = flush();
       if (r != SR_OK) return r;

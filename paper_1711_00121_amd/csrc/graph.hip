@@ -530,6 +530,22 @@ hipError_t launch_spmv_qt2(const DevQ& q, const DevAdj& out, const HeavyArgs& h,
   return run(o, q, out, n, h, s);
 }
 
+hipError_t launch_series_step_to(const DevQ& q, const HeavyArgs& h, int64_t n, double* wbase,
+                                 int wld, const double* src, int sld, double* cdst, double sx,
+                                 double sy, hipStream_t s) {
+  Op o = blank();
+  o.kind = 1;
+  o.P = wbase;  // with k = -1 the new pair of row a goes to wbase + a * wld
+  o.pld = wld;
+  o.k = -1;
+  o.src = src;
+  o.sld = sld;
+  o.cdst = cdst;
+  o.sx = sx;
+  o.sy = sy;
+  return run(o, q, q.in, n, h, s);
+}
+
 hipError_t launch_series_step(const DevQ& q, const HeavyArgs& h, int64_t n, double* P, int pld,
                               int k, double sx, double sy, const AffLevel* aff, hipStream_t s,
                               double* pairs, int64_t pairs_cap) {

@@ -88,6 +88,11 @@ hipError_t launch_spmv_q2(const DevQ& q, const HeavyArgs& h, int64_t n, const do
 hipError_t launch_spmv_qt2(const DevQ& q, const DevAdj& out, const HeavyArgs& h, int64_t n,
                            const double* xd2, double* y2, double* yd2, double scale,
                            hipStream_t s);
+// The same step with explicit places: reads the (xi_k, eta_k) pair of row x at src + x * sld,
+// writes the new pair of row a to wbase + a * wld (and to cdst + 2 a when cdst is set).
+hipError_t launch_series_step_to(const DevQ& q, const HeavyArgs& h, int64_t n, double* wbase,
+                                 int wld, const double* src, int sld, double* cdst, double sx,
+                                 double sy, hipStream_t s);
 // One step of eq (16a) on the panel P (row a holds (xi_k, eta_k) pairs for k = 0..K, pld
 // doubles per row): xi_{k+1} = sx * Q xi_k, eta_{k+1} = sy * Q eta_k; optionally one
 // affected-area level in the same pass.
