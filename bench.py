@@ -790,6 +790,20 @@ def final_edges(s, d, stream):
             np.asarray([b for _, b in e], dtype=np.int64))
 
 
+def one_thread(fn):
+    """Runs a CPU-baseline leg with the BLAS and OpenMP pools held to one thread, so that the
+    `cores` it reports (1) is what it used."""
+    import functools
+
+    @functools.wraps(fn)
+    def run(*a, **k):
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            return fn(*a, **k)
+    return run
+
+
+@one_thread
 def cpu_baseline_columns(n, s, d, seconds, what):
     """The oracle on the host: converged single-source columns S[:, x] of the updated graph
     (eq (17) by PartialSim to a tail <= 1e-13), i.e. pair values of the updated S computed
@@ -812,6 +826,7 @@ def cpu_baseline_columns(n, s, d, seconds, what):
                       f"thread (scipy sparse products are single-threaded)"}
 
 
+@one_thread
 def cpu_baseline_delta_columns(n, s, d, i, j, cols, K, Kps, seconds):
     """The oracle's column-by-column Delta S (same K and PartialSim depth) for the first
     insertion, 8 columns per call until the time budget is used."""
@@ -830,6 +845,7 @@ def cpu_baseline_delta_columns(n, s, d, i, j, cols, K, Kps, seconds):
                                         f"(8 per oracle call), {dt:.1f} s on one host thread"}
 
 
+@one_thread
 def cpu_baseline_columns_batch(n, s, d, batch, cols, K, Kps, seconds):
     """The oracle's block-by-block Delta S columns of one batch, run on consecutive 4-edge
     slices of the batch (each on the graph the earlier slices left) until the time budget is
@@ -859,6 +875,7 @@ def cpu_baseline_columns_batch(n, s, d, batch, cols, K, Kps, seconds):
                       f"extrapolated linearly in edges"}
 
 
+@one_thread
 def cpu_baseline_forest(K, n=900, m=9000):
     """The oracle's whole forest-seeded pipeline (forest, closed form, Inc-bSR of the other
     edges) on a smaller graph of the same generator and density, scaled to S entries/s; its
@@ -877,6 +894,7 @@ def cpu_baseline_forest(K, n=900, m=9000):
                       f"{dt:.1f} s on one host thread"}
 
 
+@one_thread
 def cpu_baseline_topk(rows, queries, k, seconds):
     """The oracle's top-k selection on the same stored rows (copied to the host), cycling
     through them until the time budget is used."""
@@ -893,6 +911,7 @@ def cpu_baseline_topk(rows, queries, k, seconds):
                       f"{dt:.1f} s on one host thread"}
 
 
+@one_thread
 def cpu_baseline_partitioned(K, parts, p_cross, n=1200, m=12000):
     """The oracle's whole partitioned pipeline (partition, block fixed points, Inc-bSR of the
     cross edges) on a smaller graph of the same generator and density, scaled to S
@@ -912,6 +931,7 @@ def cpu_baseline_partitioned(K, parts, p_cross, n=1200, m=12000):
                       f"same density), {dt:.1f} s on one host thread"}
 
 
+@one_thread
 def cpu_baseline_gradient(n, s, d, w, a, b, seconds):
     """The oracle's per-edge gradient (no dense matrices; upstream dL/dS = 1 at each pair),
     timed on a bounded number of edges, scaled to edges/s."""
