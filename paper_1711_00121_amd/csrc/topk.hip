@@ -188,15 +188,16 @@ __global__ __launch_bounds__(kT) void topk_kernel(SView S, const double* vecs, i
   }
 }
 
-// The same selection by one wave per query, for k <= kWaveK: no workgroup barriers, 16
-// entries per lane per group of loads (1,024 per group, two groups in flight). The buffer is
+// The same selection by one wave per query, for k <= kWaveK: no workgroup barriers, 8
+// entries per lane per group of loads (512 per group, two groups in flight; 16 per lane took
+// 35% longer at k = 100, with twice the registers and half the waves). The buffer is
 // cut back to k whenever it reaches about 2k entries, so it never holds more than
 // 2 * kWaveK entries and each sort is small. Two buffer sizes: k <= 256 in 512 entries (6 KB
 // of LDS, so registers rather than LDS bound the waves per CU) and k <= 1024 in 2,048.
 constexpr int kWaveK = 1024;
 constexpr int kWaveKSmall = 256;
 constexpr int kWCap = 2 * kWaveK;
-constexpr int kWU = 16;
+constexpr int kWU = 8;
 
 // Sorts the first N entries (N a power of two, 64 <= N <= the buffer size). Each lane takes up to four
 // pairs of a step at once: all their reads, then the compare-exchanges and writes (the pairs of
