@@ -81,7 +81,7 @@ typedef struct sr_config {
   int32_t fused_batch;   /* 1: apply_batch defers low-rank blocks into fused passes;
                             0: each block updates S on its own                              */
   int32_t split_rows;    /* graph rows (in- or out-lists) with more entries are traversed in
-                            chunks of 8192 entries, one workgroup each, whose partial sums a
+                            chunks of 4096 entries, one workgroup each, whose partial sums a
                             second small launch adds; rows of 2049 .. split_rows entries take
                             one workgroup. 0 means 65536; otherwise at least 2048            */
   int32_t profile;       /* 1: time the S-update launches from creation on (as sr_profile(1)),

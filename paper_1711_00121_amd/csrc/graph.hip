@@ -5,7 +5,7 @@
 // Q[a][x] = 1/indeg(a) for an edge x -> a (section 3.1). Rows are in-lists by sink, so
 // (Q x)[a] gathers over a's in-neighbours and (Q^T x)[b] over b's out-neighbours.
 //
-// Power-law rows, four tiers, all in 1024-thread workgroups of one launch: a row of at most
+// Power-law rows, four tiers, all in 512-thread workgroups of one launch: a row of at most
 // kLight entries is handled by a group of 8 lanes, a medium row (at most kMedium entries,
 // listed by the host) by one wave, a heavy row (up to the split threshold) by a whole
 // workgroup, and a huge row is cut into chunks of kChunk entries, one workgroup each, whose
@@ -21,7 +21,7 @@ namespace sr {
 
 namespace {
 
-constexpr int kB = 1024;
+constexpr int kB = 512;
 constexpr int kG = 8;                   // lanes per light row
 constexpr int kRowsPerBlock = kB / kG;  // 128
 constexpr int kWaves = kB / 64;         // 16: medium rows per workgroup
@@ -323,12 +323,14 @@ __global__ __launch_bounds__(kB) void traverse_kernel(Op o, DevQ q, DevAdj L, in
   bid -= h.nheavy;
   if (bid < n_med_blocks) {
     // medium rows (kLight < len <= kMedium): one wave per row, 16 entries per lane per pass
+    // for Q x; 8 for the pair kinds, Q^T x, both bitmaps or weights: fewer registers let more
+    // waves share a CU (the pair products at n = 1M ran 15% faster with 8 and 512-thread
+    // workgroups than with 16 and 1024-thread ones)
     const int64_t mi = bid * kWaves + wid;
     if (mi >= h.nmed) return;
     const int64_t row = h.med[mi];
     const int len = L.len[row];
-    // (8 at a time with both bitmaps or weights, which would otherwise spill registers)
-    constexpr int UM = (AFF == 2 || WT) ? 8 : 16;
+    constexpr int UM = (AFF == 2 || WT || KIND != 0) ? 8 : 16;
     if (len > UM * 64)  // several passes: pipelined index loads
       accumulate<UM, KIND, WT, AFF, LDSB, true>(o, q, L, lbits, L.start[row], 0, len, lane64,
                                                 64, v0, v1, fa, fb);

@@ -40,7 +40,7 @@ struct IdList {
 constexpr int kLight = 64;
 constexpr int kMedium = 2048;
 constexpr int kSplitRows = 65536;
-constexpr int kChunk = 8192;
+constexpr int kChunk = 4096;
 struct HeavyArgs {
   const int32_t* med;    // medium row ids (device), ascending
   int32_t nmed;
