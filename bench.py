@@ -99,10 +99,16 @@ def common(args, cfg, value, unit, dt, steps, dtype="f64", extra_cfg=None):
             "data": "synthetic", "config": c}
 
 
-def hbm_roof(bytes_, ms, kernel, launches, algorithmic):
+def counters_for(args, name):
+    """The workload name under which committed HBM counters apply: none for resized runs."""
+    return name if not (args.n or args.m) else "resized"
+
+
+def hbm_roof(bytes_, ms, kernel, launches, algorithmic, workload):
     gbs = bytes_ / (ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic(kernel), "kernel": kernel,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic(kernel, workload),
+            "kernel": kernel,
             "launches": launches, "avg_ms": round(ms / max(launches, 1), 3),
             "algorithmic": algorithmic}
 
@@ -225,19 +231,21 @@ def run_batch(args):
         achieved = flops / (kern_ms / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": traffic("lowrank_gemm_kernel"),
+                "traffic": traffic("lowrank_gemm_kernel", counters_for(args, cfg["name"])),
                 "kernel": "lowrank_gemm_kernel (fused batch pass)",
                 "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                 "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
                                "block"}
     else:
         roof = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
-                        "16 B per pair-update (S value + compensation, read + write)")
+                        "16 B per pair-update (S value + compensation, read + write)",
+                        counters_for(args, cfg["name"]))
     plain_roof = None
     if sample:
         plain_roof = hbm_roof(16.0 * plain_pairs, plain_ms, "lowrank_strip_kernel",
                               plain_launches,
-                              "16 B per pair-update (S value + compensation, read + write)")
+                              "16 B per pair-update (S value + compensation, read + write)",
+                              counters_for(args, cfg["name"]))
     cpu = None
     if not args.no_cpu_baseline:
         applied = list(zip(batches[:args.warmup + args.steps], counts[:args.warmup + args.steps]))
@@ -300,7 +308,8 @@ def run_stream(args):
     out["edge_updates_per_s"] = done / dt
     out["mean_pairs_per_update"] = pairs / done
     out["roofline"] = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
-                               "16 B per pair-update (S value + compensation, read + write)")
+                               "16 B per pair-update (S value + compensation, read + write)",
+                               counters_for(args, cfg["name"]))
     out["hbm_rmw_ceiling_gbs"] = rmw_ceiling(8.0 * n * n)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
@@ -361,7 +370,7 @@ def run_columns(args):
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                       "traffic": traffic("lowrank_cols_kernel"),
+                       "traffic": traffic("lowrank_cols_kernel", counters_for(args, cfg["name"])),
                        "kernel": "lowrank_cols_kernel", "launches": launches,
                        "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "algorithmic": "4 (K + 1) flop and 4 B written per output value",
@@ -426,7 +435,7 @@ def run_columns_batch(args):
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                       "traffic": traffic("lowrank_gemm_kernel_rect"),
+                       "traffic": traffic("lowrank_gemm_kernel_rect", counters_for(args, "column_batch_n1m")),
                        "kernel": "lowrank_gemm_kernel (rectangular accumulate)",
                        "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "share_of_step": round(kern_ms / (1e3 * dt), 3),
@@ -502,7 +511,7 @@ def run_forest(args):
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                       "traffic": traffic("lowrank_gemm_kernel"),
+                       "traffic": traffic("lowrank_gemm_kernel", counters_for(args, "forest_seeded_n20k")),
                        "kernel": "lowrank_gemm_kernel (fused batch pass)",
                        "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "share_of_step": round(kern_ms / (1e3 * dt), 3),
@@ -579,7 +588,7 @@ def run_partitioned(args, parts=16, p_cross=0.01):
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                       "traffic": traffic("lowrank_gemm_kernel"),
+                       "traffic": traffic("lowrank_gemm_kernel", counters_for(args, "partitioned_n20k")),
                        "kernel": "lowrank_gemm_kernel (fused batch pass)",
                        "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "share_of_step": round(kern_ms / (1e3 * dt), 3),
@@ -635,7 +644,8 @@ def run_topk(args, nq=4096, k=100):
     res["metric"] = "top-k single-source queries/s from the stored S after updates"
     # each query reads its row of the store once: n entries of 8 B (value + compensation)
     res["roofline"] = hbm_roof(8.0 * n_now * nq * args.steps, kern_ms, "topk_kernel",
-                               launches, "one row of the store per query (8 B per entry)")
+                               launches, "one row of the store per query (8 B per entry)",
+                               counters_for(args, "topk_serving_n50k"))
     res["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         rows = np.stack([ctx.query_column(int(x)).cpu().numpy() for x in qs[0][:256]])
@@ -700,7 +710,7 @@ def run_adjoint(args):
     nbytes = 8.0 * n * n * 3.0 * launches
     out["roofline"] = hbm_roof(nbytes, kern_ms, "spmm_qt_rows_kernel", launches,
                                "n^2 x 8 B read + n^2 x 8 B written (+ 2 n^2 x 8 B read on "
-                               "every second launch)")
+                               "every second launch)", counters_for(args, cfg["name"]))
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_gradient(n, s, d, w, a, b, args.cpu_seconds)
@@ -742,9 +752,9 @@ def rmw_ceiling(nbytes):
     return round(gbs, 1)
 
 
-def traffic(kernel):
+def traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    kernel's source has changed since the counters were taken."""
+    counters were taken on another workload or the kernel's source has changed since."""
     import hashlib
     import re
     name = kernel.split(" ")[0]
@@ -755,7 +765,8 @@ def traffic(kernel):
     m_src = re.search(r"Source: `([^`]+)`", text)
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_src and m_sha and m_b):
+    m_w = re.search(r"workload:\s*(\S+)", text)
+    if not (m_src and m_sha and m_b and m_w) or m_w.group(1) != workload:
         return None
     src = os.path.join(ROOT, m_src.group(1))
     if not os.path.exists(src):
