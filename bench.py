@@ -758,7 +758,9 @@ def traffic(kernel, workload):
     import hashlib
     import re
     name = kernel.split(" ")[0]
-    path = os.path.join(ROOT, "profiles", f"{name}_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_pmc.md")
+    if not os.path.exists(path):
+        path = os.path.join(ROOT, "profiles", f"{name}_pmc.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
