@@ -192,3 +192,43 @@ def test_fullsize_adjoint_n20k():
     sums = np.bincount(d, weights=w * dw, minlength=n)
     assert np.abs(sums).max() < 1e-9 * scale
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_fullsize_topk_n50k():
+    """Top-k serving in the configuration bench.py times (n = 50k after one batch, 4,096
+    queries, k = 100, value + compensation store): sampled queries' lists are the oracle's
+    selection of the same stored rows, bit for bit, and the rows of the sampled queries agree
+    with the converged single-source columns of the updated graph within the 1e-6 bar."""
+    from oracle import serving as Sv
+    cfg = W.WORKLOADS[3]
+    n, m = cfg["n"], cfg["m"]
+    _say(f"top-k n={n} m={m}: generating")
+    s, d = W.chung_lu(n, m, seed=1003)
+    batches, counts = W.batch_stream(n, s, d, 1, 4096, seed=2003)
+    ctx = _ctx(n, s, d, C=C, K=40, s_prec="hilo", node_cap=counts[-1] + 64,
+               edge_cap=m + len(batches[0][0]) + 1024)
+    ctx.apply_batch(*batches[0])
+    n_now = ctx.sizes()[0]
+    q = W.rng(5003).choice(n_now, 4096, replace=False).astype(np.int32)
+    idx, val = ctx.query_topk(q, 100)
+    idx = idx.cpu().numpy()
+    val = val.cpu().numpy()
+    pick = W.rng(5103).choice(len(q), 6, replace=False)
+    tr = EdgeTracker(n, s, d)
+    plus, minus = OI.net_update(*batches[0])
+    for a, b in minus:
+        tr.apply(a, b, -1)
+    for a, b in plus:
+        tr.apply(a, b, 1)
+    Q = tr.Q()
+    for t in pick:
+        x = int(q[t])
+        row = ctx.query_column(x).cpu().numpy()
+        ri, rv = Sv.topk(row, x, 100)
+        assert np.array_equal(idx[t], ri) and np.array_equal(val[t], rv)
+        exact = O.single_source(Q, x, C)
+        err = maxabs(row, exact)
+        _say(f"query {x}: list exact; stored row vs converged column {err:.3e}")
+        assert err < 1e-6
+    ctx.close()
