@@ -232,3 +232,32 @@ def test_fullsize_topk_n50k():
         _say(f"query {x}: list exact; stored row vs converged column {err:.3e}")
         assert err < 1e-6
     ctx.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("init", ["forest", "partitioned"])
+def test_fullsize_seeded_n20k(init):
+    """The forest-seeded and partitioned all-pairs S at their benchmark sizes (n = 20k,
+    m = 200k; value + compensation store) with a deep series (K = 40): sampled columns against
+    the converged single-source columns of the graph, and exact symmetry."""
+    n, m = 20_000, 200_000
+    if init == "forest":
+        s, d = W.chung_lu(n, m, seed=1002)
+        kw = {}
+    else:
+        s, d, _ = W.communities(n, m, 16, 0.01, seed=1102)
+        kw = {"parts": 16}
+    _say(f"{init} n={n} m={m} K=40")
+    ctx = _ctx(n, s, d, init=init, C=C, K=40, s_prec="hilo", **kw)
+    _say(f"{init}: {ctx.init_stats['edges_in']} batch edges, {ctx.init_stats['blocks']} blocks")
+    Q = Gr.transition_matrix(n, s, d)
+    cols = W.rng(6001).choice(n, 5, replace=False)
+    for x in cols.tolist():
+        got = ctx.query_column(int(x)).cpu().numpy()
+        err = maxabs(got, O.single_source(Q, int(x), C))
+        _say(f"column {x}: max |S_gpu - S*| = {err:.3e}")
+        assert err < 1e-6
+    S = ctx.S()
+    assert bool((S == S.T).all())
+    del S
+    ctx.close()
