@@ -322,6 +322,31 @@ def test_column_batch_rejections_leave_state():
     dense.close()
 
 
+def test_column_batch_degenerate_inputs():
+    """An empty batch gives zero columns and leaves the graph; an empty column list still
+    applies the batch (the next batch's columns then follow the updated graph)."""
+    n = 400
+    s, d = W.chung_lu(n, 1600, seed=97)
+    ctx = ctx_for(n, s, d, mode="column", K=5, K_ps=10)
+    out = ctx.apply_batch_columns([], [], [], [0, 5, n - 1])
+    assert out.shape == (3, n) and float(out.abs().max()) == 0.0
+    assert ctx.sizes() == (n, len(s))
+    bi, bj, bo = _existing_batch(n, s, d, 98, 4, 2, 2)
+    ctx.apply_batch_columns(bi, bj, bo, [])
+    assert ctx.sizes() == (n, len(s) + 2)
+    # a second batch on the updated graph, against the oracle started from it
+    s2 = np.asarray([a for a, b in zip(s.tolist(), d.tolist())
+                     if (a, b) not in set(zip(bi[4:], bj[4:]))] + bi[:4], dtype=np.int64)
+    d2 = np.asarray([b for a, b in zip(s.tolist(), d.tolist())
+                     if (a, b) not in set(zip(bi[4:], bj[4:]))] + bj[:4], dtype=np.int64)
+    ci, cj, co = _existing_batch(n, s2, d2, 99, 3, 1, 2)
+    cols = np.array([0, 7, 200, n - 1])
+    got = ctx.apply_batch_columns(ci, cj, co, cols).cpu().numpy().T
+    ref = OI.delta_columns_batch(n, s2, d2, ci, cj, co, cols, C, 5, 10)
+    assert maxabs(got, ref) < 1e-12 * max(1.0, float(np.abs(ref).max()))
+    ctx.close()
+
+
 @pytest.mark.parametrize("K,n", [(0, 700), (3, 701), (4, 700), (6, 702), (8, 700), (10, 703),
                                  (12, 700), (15, 701)])
 def test_column_kernel_every_depth(K, n):

@@ -97,3 +97,21 @@ def test_partitioned_rejections():
     with pytest.raises(ValueError):
         ctx_for(n, s, d, init="partitioned", part=g[:-1])
     torch.cuda.synchronize()
+
+
+def test_partition_extremes():
+    """One block (no cross edges): the fixed point of the whole graph. Singleton blocks (every
+    edge crosses): the oracle's pipeline from S = (1 - C) I."""
+    n, m = 240, 1000
+    s, d, _ = W.communities(n, m, 3, 0.05, seed=991)
+    one = ctx_for(n, s, d, init="partitioned", parts=1, s_prec="fp64")
+    assert one.init_stats["edges_in"] == 0
+    exact = O.fixed_point(Gr.transition_matrix(n, s, d), C)
+    assert maxabs(one.S().cpu().numpy(), exact) < 1e-13
+    one.close()
+    lab = np.arange(n)
+    ref = Pt.partitioned(n, s, d, lab, C, 15)
+    sing = ctx_for(n, s, d, init="partitioned", part=lab, s_prec="fp64", K=15)
+    assert sing.init_stats["edges_in"] == m
+    assert maxabs(sing.S().cpu().numpy(), ref) < 1e-12
+    sing.close()

@@ -126,5 +126,7 @@ def test_topk_rejections():
         assert e.value.status == code
     idx, _ = ctx.query_topk([1], n, exclude_self=False)
     assert sorted(idx.cpu().numpy()[0].tolist()) == list(range(n))
+    idx, val = ctx.query_topk([], 5)                      # no queries: nothing to do
+    assert idx.shape == (0, 5) and val.shape == (0, 5)
     torch.cuda.synchronize()
     ctx.close()

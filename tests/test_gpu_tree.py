@@ -105,3 +105,23 @@ def test_forest_seeded_rejections():
     with pytest.raises(ValueError):
         ctx_for(n, s, d, init="forest", weight=np.ones(len(s)))
     torch.cuda.synchronize()
+
+
+def test_forest_degenerate_graphs():
+    """No edges: every node is a root and S = (1 - C) I; one node; a single path."""
+    n = 1100
+    ctx = ctx_for(n, np.zeros(0, np.int32), np.zeros(0, np.int32), init="forest",
+                  s_prec="fp64")
+    S = ctx.S().cpu().numpy()
+    assert np.array_equal(S, (1.0 - C) * np.eye(n))
+    ctx.close()
+    one = ctx_for(1, np.zeros(0, np.int32), np.zeros(0, np.int32), init="forest")
+    assert one.S().cpu().numpy().tolist() == [[1.0 - C]]
+    one.close()
+    n = 50                                     # a path 0 -> 1 -> ... -> 49 is its own tree
+    s = np.arange(n - 1, dtype=np.int32)
+    d = s + 1
+    ctx = ctx_for(n, s, d, init="forest", s_prec="fp64")
+    op, od = T.bfs_forest(n, s, d)
+    assert maxabs(ctx.S().cpu().numpy(), T.tree_simrank(op, od, C)) < 1e-15
+    ctx.close()
