@@ -411,17 +411,18 @@ def sink_blocks(edges):
     return blocks
 
 
-MAX_SOURCES = 60
-
-
-def plan_batch(n, src, dst, bi, bj, bop, max_sources=MAX_SOURCES):
+def plan_batch(n, src, dst, bi, bj, bop, max_sources=None):
     """Algorithm 6 planning with the readings: deletion blocks first (sinks ascending),
     then insertion blocks (sinks ascending); each insertion block is split at the time it
     is processed into sources already in V (processed first) and sources not yet in V;
-    a node joins V when a processed block creates it. A block of more than ``max_sources``
-    sources is taken as consecutive blocks of at most that many (sources ascending) with the
-    same sink: consecutive Table 2 updates of one sink compose to the update of their union,
-    so the split changes nothing but the series truncation of each part.
+    a node joins V when a processed block creates it. Every block is applied whole, as one
+    Table 2 update, whatever its number of sources.
+
+    ``max_sources`` (off by default) instead takes a block of more sources as consecutive
+    blocks of at most that many (sources ascending) with the same sink. Consecutive Table 2
+    updates of one sink compose to the update of their union, so such a split reaches the
+    same S as K grows; at a finite K each part has its own truncation. It exists only to
+    check that composition.
 
     New node ids must be exactly ``n .. n + N - 1``. Returns a list of dicts with keys
     ``case`` (0..3), ``op``, ``I`` (sorted sources), ``j``, ``dj`` (in-degree of j when the
@@ -473,7 +474,7 @@ def plan_batch(n, src, dst, bi, bj, bop, max_sources=MAX_SOURCES):
     return plan, n_new
 
 
-def inc_bsr(n, src, dst, S, bi, bj, bop, C, K, form="closed"):
+def inc_bsr(n, src, dst, S, bi, bj, bop, C, K, form="closed", max_sources=None):
     """Inc-bSR (Algorithm 6) evaluated densely block by block with Table 2.
 
     New-node blocks assume the new ids of a block are the next ids in processing order;
@@ -481,7 +482,7 @@ def inc_bsr(n, src, dst, S, bi, bj, bop, C, K, form="closed"):
     every not-yet-created node isolated (diagonal 1 - C, which is the SimRank of an
     isolated node) and the block formulas then act on the grown matrices.
     """
-    plan, n_new = plan_batch(n, src, dst, bi, bj, bop)
+    plan, n_new = plan_batch(n, src, dst, bi, bj, bop, max_sources=max_sources)
     S = grow(S, n_new - n)
     for t in range(n, n_new):
         S[t, t] = 1.0 - C

@@ -69,6 +69,10 @@ struct sr_ctx {
   int64_t ids_cap = 0;
   int64_t* d_cnt = nullptr;
   unsigned long long* d_max = nullptr;
+  double* d_sum = nullptr;  // sums over a block's sources of long lists (launch_sum_at)
+  int32_t* d_mm = nullptr;  // min / max of caller-supplied device ids (launch_ids_range)
+  int32_t* d_blk = nullptr;  // the sources of a batch's long blocks (IdList::dev targets)
+  int64_t blk_cap = 0;
   int64_t* h_cnt = nullptr;
   unsigned long long* h_max = nullptr;
 
@@ -130,11 +134,23 @@ AdjPtrs adjptrs(const sr_ctx* c) {
   return t;
 }
 
+// hipMalloc that leaves no sticky error behind on failure: HIP keeps the last error for
+// hipGetLastError, which the kernel launchers read after every launch, so a failed
+// allocation would otherwise be reported by the next, unrelated launch.
+hipError_t dmalloc(void** p, size_t bytes) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+  }
+  return e;
+}
+
 template <typename T>
 hipError_t dalloc(T** p, int64_t count) {
   *p = nullptr;
   if (count <= 0) count = 1;
-  return hipMalloc((void**)p, (size_t)count * sizeof(T));
+  return dmalloc((void**)p, (size_t)count * sizeof(T));
 }
 
 // Records row r's tier after an edit; a change marks the set for upload.
@@ -183,7 +199,7 @@ hipError_t upload_list(const std::vector<T>& v, T** d, int64_t* cap) {
     (void)hipFree(*d);
     *d = nullptr;
     const int64_t c = std::max<int64_t>(64, 2 * cnt);
-    hipError_t e = hipMalloc((void**)d, (size_t)c * sizeof(T));
+    hipError_t e = dmalloc((void**)d, (size_t)c * sizeof(T));
     if (e != hipSuccess) return e;
     *cap = c;
   }
@@ -229,9 +245,9 @@ sr_status heavy_sync(sr_ctx* ctx, HeavySet& H, const SlotList& L) {
       (void)hipFree(H.d_pflag);
       H.d_part = nullptr;
       H.d_pflag = nullptr;
-      e = hipMalloc((void**)&H.d_part, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 16);
+      e = dmalloc((void**)&H.d_part, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 16);
       if (e == hipSuccess)
-        e = hipMalloc((void**)&H.d_pflag, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 4);
+        e = dmalloc((void**)&H.d_pflag, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 4);
     }
   }
   if (e == hipErrorOutOfMemory) return SR_ENOMEM;
@@ -281,8 +297,19 @@ sr_status upload_graph(sr_ctx* ctx) {
   return SR_OK;
 }
 
+// Whether inserting the edges (i, j) cannot run out of slots in either list (checked by the
+// entry points before any launch, so that SR_ECAPACITY leaves the context unchanged).
+bool graph_fits(const sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>& ins) {
+  std::map<int32_t, int32_t> add_in, add_out;
+  for (const auto& ij : ins) {
+    add_in[ij.second]++;
+    add_out[ij.first]++;
+  }
+  return ctx->g.in.fits(add_in) && ctx->g.out.fits(add_out);
+}
+
 // Applies edge insertions (op > 0) or deletions to the host mirror and the device copy.
-// The caller has validated every edge.
+// The caller has validated every edge and checked graph_fits for the insertions.
 sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>& e, int op) {
   std::vector<Write> wi, wo;
   std::vector<int32_t> mi, mo;
@@ -308,13 +335,18 @@ sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>
   ctx->updated = true;
   {
     sr_status hs = heavy_refresh(ctx);
-    if (hs != SR_OK) return hs;
+    if (hs != SR_OK) {
+      // the mirror has changed: a failure here cannot leave the context as it was
+      ctx->poisoned = true;
+      return hs;
+    }
   }
-  if (full) {
-    sr_status st = upload_graph(ctx);
-    if (st != SR_OK) return st;
-    return cap_err ? SR_ECAPACITY : SR_OK;
+  if (cap_err) {
+    // not reachable after graph_fits; the mirror no longer matches the edges it lists
+    ctx->poisoned = true;
+    return SR_EHIP;
   }
+  if (full) return upload_graph(ctx);
   // Moved rows: upload their slots; then patch every touched (array, index) with the mirror's
   // final value (unique addresses per launch, so the writes of one launch commute).
   const SlotList* L[2] = {&ctx->g.in, &ctx->g.out};
@@ -379,11 +411,49 @@ hipError_t run_lowrank(sr_ctx* ctx, const LowRankArgs& la) {
   return profiled(ctx, [&]() { return launch_lowrank(la, ctx->stream); });
 }
 
-IdList idlist(const std::vector<int32_t>& v, size_t off, size_t cnt) {
+// Ids v[off .. off + cnt) as a kernel list: by value up to IdList::MAX, otherwise the device
+// copy at dev (which the caller has uploaded; a long list without one is a caller error).
+IdList idlist(const std::vector<int32_t>& v, size_t off, size_t cnt,
+              const int32_t* dev = nullptr) {
   IdList l;
   l.count = (int32_t)cnt;
-  for (size_t t = 0; t < cnt; ++t) l.id[t] = v[off + t];
+  if (cnt > (size_t)IdList::MAX) {
+    l.dev = dev;
+  } else {
+    for (size_t t = 0; t < cnt; ++t) l.id[t] = v[off + t];
+  }
   return l;
+}
+
+// Uploads the source lists longer than IdList::MAX of a batch's blocks, back to back, to
+// ctx->d_blk; dev_of[b] receives block b's device list (null for short lists).
+template <typename BlockT>
+sr_status stage_long_lists(sr_ctx* ctx, const std::vector<BlockT>& plan,
+                           std::vector<const int32_t*>& dev_of) {
+  dev_of.assign(plan.size(), nullptr);
+  std::vector<int32_t> ids;
+  std::vector<int64_t> off(plan.size(), -1);
+  for (size_t b = 0; b < plan.size(); ++b) {
+    if (plan[b].I.size() <= (size_t)IdList::MAX) continue;
+    off[b] = (int64_t)ids.size();
+    ids.insert(ids.end(), plan[b].I.begin(), plan[b].I.end());
+  }
+  if (ids.empty()) return SR_OK;
+  // earlier work may still read the previous lists
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail_hip(ctx);
+  if ((int64_t)ids.size() > ctx->blk_cap) {
+    (void)hipFree(ctx->d_blk);
+    ctx->d_blk = nullptr;
+    ctx->blk_cap = 0;
+    const int64_t c = std::max<int64_t>(4096, 2 * (int64_t)ids.size());
+    if (dmalloc((void**)&ctx->d_blk, (size_t)c * 4) != hipSuccess) return SR_ENOMEM;
+    ctx->blk_cap = c;
+  }
+  if (hipMemcpy(ctx->d_blk, ids.data(), ids.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail_hip(ctx);
+  for (size_t b = 0; b < plan.size(); ++b)
+    if (off[b] >= 0) dev_of[b] = ctx->d_blk + off[b];
+  return SR_OK;
 }
 
 AffArgs aff_args(const sr_ctx* c, int64_t n) {
@@ -418,7 +488,7 @@ struct FusedTarget {
 //   n_work: node count the kernels cover (includes new and not yet created nodes).
 sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int32_t>& I,
                         int32_t j, int64_t n_work, sr_update_stats* st,
-                        const FusedTarget* ft = nullptr) {
+                        const FusedTarget* ft = nullptr, const int32_t* I_dev = nullptr) {
   const double C = ctx->cfg.C;
   const int K = ctx->cfg.K;
   const int delta = (int)I.size();
@@ -438,10 +508,10 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   ga.dj = dj;
   ga.C = C;
   ga.xi0 = case_id == 2 ? C * (double)delta / (double)(dj + delta) : C;
-  ga.I = idlist(I, 0, case_id == 0 ? I.size() : 0);
+  ga.I = idlist(I, 0, case_id == 0 ? I.size() : 0, I_dev);
 
   // S[:, I] (with supports) and S[:, j] from the old S.
-  const IdList src_rows = idlist(I, 0, case_id == 0 ? I.size() : 0);
+  const IdList src_rows = ga.I;
   HC(launch_gather_rows(ctx->S, n_work, src_rows, 0, j, ctx->SI, ctx->Sj, ctx->suppI,
                         ctx->suppJ, s, ft ? ft->cI : nullptr, ft ? ft->cJ : nullptr));
   if (ft && !ft->incremental && ft->r_prev > 0)
@@ -464,6 +534,11 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
       if (dj > 0) HC(launch_gather_inrows(ctx->S, n_work, q, j, ctx->zsum, s));
       HC(launch_direct_z(ga, n_work, ctx->SI, ctx->zsum, ctx->zbuf, s));
       HC(launch_spmv_q(q, hin, n_work, ctx->zbuf, ctx->Qz, 1.0, s));
+    }
+    if (ga.I.dev) {
+      // a long list: the sum over I (of S[:, I], or of z) once, not per thread
+      HC(launch_sum_at(direct ? ctx->zbuf : ctx->SI, ga.I, ctx->d_sum, s));
+      ga.sumI = ctx->d_sum;
     }
   }
   if (st) HC(hipMemsetAsync(ctx->d_max, 0, sizeof(unsigned long long), s));
@@ -553,10 +628,10 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
 
 // C1 block (Theorem 8, Table 2 row C1): existing sources I, new sink j.
 sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_t n_work,
-                   const FusedTarget* ft = nullptr) {
+                   const FusedTarget* ft = nullptr, const int32_t* I_dev = nullptr) {
   hipStream_t s = ctx->stream;
   const double C = ctx->cfg.C;
-  const IdList il = idlist(I, 0, I.size());
+  const IdList il = idlist(I, 0, I.size(), I_dev);
   HC(launch_gather_rows(ctx->S, n_work, il, 0, -1, ctx->SI, nullptr, ctx->suppI, nullptr, s,
                         ft ? ft->cI : nullptr, nullptr));
   if (ft && !ft->incremental && ft->r_prev > 0)
@@ -564,7 +639,9 @@ sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_
                             nullptr, s));
   HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n_work, ctx->SI, ctx->ytmp,
                    C / (double)I.size(), s));
-  HC(launch_c1_border(ctx->S, n_work, j, ctx->ytmp, ctx->SI, il, C, s));
+  if (il.dev) HC(launch_sum_at(ctx->SI, il, ctx->d_sum, s));
+  HC(launch_c1_border(ctx->S, n_work, j, ctx->ytmp, ctx->SI, il, C, s,
+                      il.dev ? ctx->d_sum : nullptr));
   std::vector<std::pair<int32_t, int32_t>> e;
   for (int32_t i : I) e.push_back({i, j});
   return edit_graph(ctx, e, +1);
@@ -660,6 +737,19 @@ sr_status partial_sim2(sr_ctx* ctx, const IdList& a, const IdList& b, double* ou
 
 bool valid_ctx(sr_ctx* c) { return c != nullptr; }
 
+// Checks that every id of the device pair arrays lies in [0, n) before they are used as
+// addresses (synchronises the stream): SR_ERANGE otherwise.
+sr_status check_pair_ids(sr_ctx* ctx, int64_t np, const int32_t* a, const int32_t* b) {
+  if (np <= 0) return SR_OK;
+  HC(launch_ids_range(a, b, np, ctx->d_mm, ctx->stream));
+  HC(hipMemcpyAsync(ctx->h_cnt + 6, ctx->d_mm, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                    ctx->stream));
+  HC(hipStreamSynchronize(ctx->stream));
+  int32_t mm[2];
+  memcpy(mm, ctx->h_cnt + 6, sizeof(mm));
+  return (mm[0] < 0 || (int64_t)mm[1] >= ctx->g.n) ? SR_ERANGE : SR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -726,6 +816,9 @@ sr_status sr_destroy(sr_ctx* ctx) {
   heavy_free(ctx->hout);
   (void)hipFree(ctx->d_cnt);
   (void)hipFree(ctx->d_max);
+  (void)hipFree(ctx->d_sum);
+  (void)hipFree(ctx->d_mm);
+  (void)hipFree(ctx->d_blk);
   (void)hipHostFree(ctx->h_cnt);
   (void)hipHostFree(ctx->h_max);
   delete ctx;
@@ -760,6 +853,12 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   const int64_t node_cap = cfg.node_cap > 0 ? cfg.node_cap : n;
   const int64_t edge_cap = cfg.edge_cap > 0 ? cfg.edge_cap : 2 * m + 1024;
   if (node_cap < n || edge_cap < m || node_cap > ((int64_t)1 << 31) - 64) return SR_ECAPACITY;
+  // slot offsets are int32 (see the slot array sizing below)
+  if (edge_cap + edge_cap / 4 + 8 * node_cap + edge_cap / 2 + 4096 > ((int64_t)1 << 31) - 1)
+    return SR_ECAPACITY;
+  // a dense S of more than 2^52 entries (32 PiB) cannot be allocated; refusing here also
+  // keeps the byte count below from overflowing
+  if (cfg.mode == SR_DENSE && node_cap > ((int64_t)1 << 26)) return SR_ENOMEM;
   for (int64_t e = 0; e < m; ++e) {
     if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return SR_ERANGE;
     if (src[e] == dst[e]) return SR_ESELF;
@@ -849,6 +948,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   IC(dalloc(&ctx->rowlist, node_cap));
   IC(dalloc(&ctx->d_cnt, 8));
   IC(dalloc(&ctx->d_max, 1));
+  IC(dalloc(&ctx->d_sum, 4));
+  IC(dalloc(&ctx->d_mm, 4));
   IC(hipHostMalloc((void**)&ctx->h_cnt, 8 * sizeof(int64_t), hipHostMallocDefault));
   IC(hipHostMalloc((void**)&ctx->h_max, sizeof(unsigned long long), hipHostMallocDefault));
   if (hipMemset(ctx->P, 0, (size_t)ctx->p_rows * ctx->pld * 8) != hipSuccess ||
@@ -886,15 +987,15 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   ctx->S.ld = ld;
   const size_t cells = (size_t)node_cap * (size_t)ld;
   if (cfg.s_prec == SR_S_FP64) {
-    IC(hipMalloc(&ctx->S_mem[0], cells * 8));
+    IC(dmalloc((void**)&ctx->S_mem[0], cells * 8));
     ctx->S.d = (double*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 8));
   } else if (cfg.s_prec == SR_S_FP32_HILO) {
-    IC(hipMalloc(&ctx->S_mem[0], cells * 8));
+    IC(dmalloc((void**)&ctx->S_mem[0], cells * 8));
     ctx->S.hl = (float2*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 8));
   } else {
-    IC(hipMalloc(&ctx->S_mem[0], cells * 4));
+    IC(dmalloc((void**)&ctx->S_mem[0], cells * 4));
     ctx->S.hi = (float*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 4));
   }
@@ -922,7 +1023,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
     bc.edge_cap = 0;
     bc.profile = 0;
     int32_t* dg = nullptr;
-    hipError_t e = hipMalloc(&dg, (size_t)n * 4);
+    hipError_t e = dmalloc((void**)&dg, (size_t)n * 4);
     sr_status bst = SR_OK;
     for (int32_t p = 0; p < np && e == hipSuccess && bst == SR_OK; ++p) {
       const int64_t nb = (int64_t)mem[p].size();
@@ -949,8 +1050,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   if (tree_parent) {
     // S of the forest by Example 1.2's closed form, written straight into the store
     int32_t *dp = nullptr, *dd = nullptr;
-    hipError_t e = hipMalloc(&dp, (size_t)n * 4);
-    if (e == hipSuccess) e = hipMalloc(&dd, (size_t)n * 4);
+    hipError_t e = dmalloc((void**)&dp, (size_t)n * 4);
+    if (e == hipSuccess) e = dmalloc((void**)&dd, (size_t)n * 4);
     if (e == hipSuccess) e = hipMemcpy(dp, tree_parent, (size_t)n * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dd, tree_depth, (size_t)n * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_tree_init(ctx->S, n, dp, dd, cfg.C, ctx->stream);
@@ -1254,6 +1355,7 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
   const int64_t n_new = n + (case_id == 3 ? 2 : (case_id == 0 ? 0 : 1));
   if (n_new > ctx->node_cap) return SR_ECAPACITY;
   if (op > 0 && ctx->g.m + 1 > ctx->edge_cap) return SR_ECAPACITY;
+  if (op > 0 && !graph_fits(ctx, {{i, j}})) return SR_ECAPACITY;
 
   if (ctx->cfg.mode == SR_COLUMN) {
     if (case_id != 0 || op < 0) return SR_EMODE;
@@ -1390,6 +1492,12 @@ sr_status plan_batch(const sr_ctx* ctx, int64_t cnt, const int32_t* bi, const in
     }
   }
   if (ctx->g.m + ins > ctx->edge_cap) return SR_ECAPACITY;
+  {
+    std::vector<std::pair<int32_t, int32_t>> ie;
+    ie.reserve(plus.size());
+    for (const auto& ji : plus) ie.push_back({ji.second, ji.first});
+    if (!graph_fits(ctx, ie)) return SR_ECAPACITY;
+  }
   net_edges = (int64_t)(plus.size() + minus.size());
 
   std::vector<int64_t> deg_change;  // tracked lazily through a map
@@ -1399,28 +1507,24 @@ sr_status plan_batch(const sr_ctx* ctx, int64_t cnt, const int32_t* bi, const in
     auto it = dmod.find(j);
     return d + (it == dmod.end() ? 0 : it->second);
   };
-  const size_t cap = IdList::MAX;
-  auto push_split = [&](int case_id, int op, int32_t j, std::vector<int32_t>& I) {
-    for (size_t off = 0; off < I.size(); off += cap) {
-      Block b;
-      b.case_id = case_id;
-      b.op = op;
-      b.j = j;
-      b.dj = degree(j);
-      b.I.assign(I.begin() + off, I.begin() + std::min(I.size(), off + cap));
-      dmod[j] += op * (int64_t)b.I.size();
-      plan.push_back(b);
-      // after the first chunk of a new-node block the sink / sources exist
-      if (case_id == 1) case_id = 0;
-      if (case_id == 3) case_id = 2;
-    }
+  // one block per sink (and per old / new source split of an insertion block): Table 2
+  // applies the whole block as one rank-one update, whatever its size
+  auto push_block = [&](int case_id, int op, int32_t j, std::vector<int32_t>& I) {
+    Block b;
+    b.case_id = case_id;
+    b.op = op;
+    b.j = j;
+    b.dj = degree(j);
+    b.I = I;
+    dmod[j] += op * (int64_t)b.I.size();
+    plan.push_back(b);
   };
   // deletion blocks, sinks ascending
   for (size_t a = 0; a < minus.size();) {
     size_t b = a;
     std::vector<int32_t> I;
     while (b < minus.size() && minus[b].first == minus[a].first) I.push_back(minus[b++].second);
-    push_split(0, -1, minus[a].first, I);
+    push_block(0, -1, minus[a].first, I);
     a = b;
   }
   // insertion blocks, sinks ascending; split by source existence at processing time
@@ -1435,11 +1539,11 @@ sr_status plan_batch(const sr_ctx* ctx, int64_t cnt, const int32_t* bi, const in
       (exists(i) ? old_src : new_src).push_back(i);
     }
     if (!old_src.empty()) {
-      push_split(exists(j) ? 0 : 1, 1, j, old_src);
+      push_block(exists(j) ? 0 : 1, 1, j, old_src);
       created.insert(j);
     }
     if (!new_src.empty()) {
-      push_split(exists(j) ? 2 : 3, 1, j, new_src);
+      push_block(exists(j) ? 2 : 3, 1, j, new_src);
       created.insert(j);
       for (int32_t i : new_src) created.insert(i);
     }
@@ -1557,7 +1661,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
       ctx->corr_tab = nullptr;
       ctx->corr_tab_cap = 0;
       const int64_t c = std::max<int64_t>(1024, 2 * (int64_t)tab.size());
-      if (hipMalloc((void**)&ctx->corr_tab, (size_t)c * 4) != hipSuccess) return SR_ENOMEM;
+      if (dmalloc((void**)&ctx->corr_tab, (size_t)c * 4) != hipSuccess) return SR_ENOMEM;
       ctx->corr_tab_cap = c;
     }
     HC(hipMemcpy(ctx->corr_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
@@ -1573,6 +1677,9 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     cs.w = ctx->corr_w;
   }
 
+  std::vector<const int32_t*> dev_of;
+  r = stage_long_lists(ctx, plan, dev_of);
+  if (r != SR_OK) return r;
   ctx->last_plan.clear();
   int cur_chunk = -1;
   for (size_t bi = 0; bi < plan.size(); ++bi) {
@@ -1604,7 +1711,8 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     switch (b.case_id) {
       case 0:
       case 2:
-        r = lowrank_block(ctx, b.case_id, b.op, b.I, b.j, n_new, nullptr, fused ? &ft : nullptr);
+        r = lowrank_block(ctx, b.case_id, b.op, b.I, b.j, n_new, nullptr, fused ? &ft : nullptr,
+                          dev_of[bi]);
         ++lowrank;
         pairs += n_new * n_new;
         if (r == SR_OK && incremental) {
@@ -1617,7 +1725,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
         if (r == SR_OK && fused && ++q == chunk) r = flush();
         break;
       case 1:
-        r = c1_block(ctx, b.I, b.j, n_new, fused ? &ft : nullptr);
+        r = c1_block(ctx, b.I, b.j, n_new, fused ? &ft : nullptr, dev_of[bi]);
         pairs += 2 * n_new + 1;
         break;
       default:
@@ -1723,8 +1831,12 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
     q = 0;
     return SR_OK;
   };
+  std::vector<const int32_t*> dev_of;
+  r = stage_long_lists(ctx, plan, dev_of);
+  if (r != SR_OK) return r;
   ctx->last_plan.clear();
-  for (const Block& b : plan) {
+  for (size_t bx = 0; bx < plan.size(); ++bx) {
+    const Block& b = plan[bx];
     ctx->last_plan.push_back(b.case_id);
     ctx->last_plan.push_back(b.op);
     ctx->last_plan.push_back(b.j);
@@ -1733,13 +1845,14 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
     for (int32_t i : b.I) ctx->last_plan.push_back(i);
     const int64_t c0 = (int64_t)q * w;  // this block's first packed column
     // S[:, I] and S[:, j] on the current graph (PartialSim), Q S[:, I], then Table 2 (C0)
-    const IdList il = idlist(b.I, 0, b.I.size());
+    const IdList il = idlist(b.I, 0, b.I.size(), dev_of[bx]);
     IdList lj;
     lj.count = 1;
     lj.id[0] = b.j;
     r = partial_sim2(ctx, il, lj, ctx->SI, ctx->Sj);
     if (r != SR_OK) return r;
     HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->QSI, 1.0, s));
+    if (il.dev) HC(launch_sum_at(ctx->SI, il, ctx->d_sum, s));
     GammaArgs ga{};
     ga.kind = 0;
     ga.op = b.op;
@@ -1749,6 +1862,7 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
     ga.C = C;
     ga.xi0 = C;
     ga.I = il;
+    ga.sumI = il.dev ? ctx->d_sum : nullptr;
     HC(launch_gamma(ga, n, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, at(c0), 16, nullptr,
                     s));
     std::vector<std::pair<int32_t, int32_t>> e;
@@ -1903,6 +2017,8 @@ sr_status sr_gather_pairs(sr_ctx* ctx, int64_t np, const int32_t* a, const int32
   if (!valid_ctx(ctx) || np < 0 || (np > 0 && (!a || !b || !out))) return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
   if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+  const sr_status rs = check_pair_ids(ctx, np, a, b);
+  if (rs != SR_OK) return rs;
   HC(launch_gather_pairs(ctx->S, np, a, b, out, ctx->stream));
   return SR_OK;
 }
@@ -1956,6 +2072,10 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
     return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
   if (ctx->cfg.mode != SR_DENSE || ctx->updated) return SR_EMODE;
+  {
+    const sr_status rs = check_pair_ids(ctx, npairs, a_dev, b_dev);
+    if (rs != SR_OK) return rs;
+  }
   const int64_t n = ctx->g.n;
   const int64_t m = (int64_t)ctx->src0.size();
   const double C = ctx->cfg.C;

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kB) void gather_rows_kernel(SView S, int64_t n, IdL
   bool sup = false;
   if (in) {
     for (int t = 0; t < I.count; ++t) {
-      const double v = s_get(S, (int64_t)I.id[t] * S.ld + a);
+      const double v = s_get(S, (int64_t)I.at(t) * S.ld + a);
       s += v;
       sup |= (v != 0.0);
     }
@@ -81,8 +81,18 @@ __global__ __launch_bounds__(kB) void gather_inrows_kernel(SView S, int64_t n, D
 
 __device__ __forceinline__ double sum_at(const double* v, const IdList& I) {
   double s = 0.0;
-  for (int t = 0; t < I.count; ++t) s += v[I.id[t]];
+  for (int t = 0; t < I.count; ++t) s += v[I.at(t)];
   return s;
+}
+
+// One wave: out[0] = sum over the list of v[I.at(t)], lane-strided partial sums combined in a
+// fixed order.
+__global__ __launch_bounds__(64) void sum_at_kernel(const double* __restrict__ v, IdList I,
+                                                    double* __restrict__ out) {
+  double s = 0.0;
+  for (int t = threadIdx.x; t < I.count; t += 64) s += v[I.at(t)];
+  s = wave_sum(s, 64);
+  if (threadIdx.x == 0) out[0] = s;
 }
 
 __global__ __launch_bounds__(kB) void direct_z_kernel(GammaArgs g, int64_t n,
@@ -119,7 +129,7 @@ __global__ __launch_bounds__(kB) void gamma_kernel(GammaArgs g, int64_t n,
   if (a < n) {
     if (g.kind == 0) {
       // Theorem 3 (eqs (29aa), (29bb), (29b)), Theorem 9, Table 2 rows (C0).
-      const double SII = sum_at(SI, g.I);
+      const double SII = g.sumI ? *g.sumI : sum_at(SI, g.I);
       const double lam = SII / (d * d) + Sj[g.j] / C - (2.0 / d) * QSI[g.j] - 1.0 / C + 1.0;
       if (g.op > 0) {
         if (g.dj == 0) {
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(kB) void gamma_kernel(GammaArgs g, int64_t n,
       }
     } else if (g.kind == 1) {
       // Theorem 2, eq (20): w = Q z + (v^T z / 2) u with z = S v; gamma = u_j w.
-      const double zI = sum_at(z, g.I) / d;
+      const double zI = (g.sumI ? *g.sumI : sum_at(z, g.I)) / d;
       double vz, uj;
       if (g.op > 0) {
         vz = (g.dj == 0) ? zI : zI - Qz[g.j];
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(kB) void gamma_kernel(GammaArgs g, int64_t n,
 __global__ __launch_bounds__(kB) void c1_border_kernel(SView S, int64_t n_old, int32_t j,
                                                        const double* __restrict__ y,
                                                        const double* __restrict__ SI, IdList I,
-                                                       double C) {
+                                                       double C, const double* sumI) {
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (a < n_old && a != j) {
     const double v = y[a];
@@ -174,7 +184,7 @@ __global__ __launch_bounds__(kB) void c1_border_kernel(SView S, int64_t n_old, i
   }
   if (a == 0) {
     const double d = (double)I.count;
-    const double SII = sum_at(SI, I);
+    const double SII = sumI ? *sumI : sum_at(SI, I);
     s_put(S, (int64_t)j * S.ld + j, C / (d * d) * SII + 1.0 - C);
   }
 }
@@ -297,7 +307,7 @@ __global__ __launch_bounds__(kB) void indicator_kernel(double* x, int64_t n, IdL
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (a >= n) return;
   double v = 0.0;
-  for (int t = 0; t < ids.count; ++t) v = (ids.id[t] == a) ? 1.0 : v;
+  for (int t = 0; t < ids.count; ++t) v = (ids.at(t) == a) ? 1.0 : v;
   x[a] = v;
   if (xd) {
     double r = 0.0;
@@ -314,12 +324,54 @@ __global__ __launch_bounds__(kB) void indicator2_kernel(double* x2, int64_t n, I
   const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
   if (a >= n) return;
   double u = 0.0, v = 0.0;
-  for (int t = 0; t < ia.count; ++t) u = (ia.id[t] == a) ? 1.0 : u;
-  for (int t = 0; t < ib.count; ++t) v = (ib.id[t] == a) ? 1.0 : v;
+  for (int t = 0; t < ia.count; ++t) u = (ia.at(t) == a) ? 1.0 : u;
+  for (int t = 0; t < ib.count; ++t) v = (ib.at(t) == a) ? 1.0 : v;
   *reinterpret_cast<double2*>(x2 + 2 * a) = make_double2(u, v);
   const double d = dq.W ? dq.W[a] : (double)dq.in.len[a];
   const double r = d > 0.0 ? 1.0 / d : 0.0;
   *reinterpret_cast<double2*>(xd2 + 2 * a) = make_double2(u * r, v * r);
+}
+
+// mm[0] = min and mm[1] = max over the np pairs' ids a[p], b[p] (mm preset by the launcher's
+// first kernel to INT32_MAX, INT32_MIN).
+__global__ void ids_range_init_kernel(int32_t* mm) {
+  mm[0] = 2147483647;
+  mm[1] = -2147483647 - 1;
+}
+
+__global__ __launch_bounds__(kB) void ids_range_kernel(const int32_t* __restrict__ a,
+                                                       const int32_t* __restrict__ b, int64_t np,
+                                                       int32_t* mm) {
+  int lo = 2147483647, hi = -2147483647 - 1;
+  for (int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * kB) {
+    const int x = a[p], y = b[p];
+    lo = min(lo, min(x, y));
+    hi = max(hi, max(x, y));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(mm, lo);
+    atomicMax(mm + 1, hi);
+  }
+}
+
+// Long id lists: after a zero fill, one thread per listed id sets its entry (the ids of a
+// list are distinct). x has stride `stride` doubles per node and offset `half`; xd (optional)
+// receives the entry divided by the node's row weight of Q (0 where that is 0).
+__global__ __launch_bounds__(kB) void indicator_scatter_kernel(double* x, IdList ids, int stride,
+                                                               int half, DevQ dq, double* xd) {
+  const int t = blockIdx.x * kB + threadIdx.x;
+  if (t >= ids.count) return;
+  const int64_t a = ids.at(t);
+  x[stride * a + half] = 1.0;
+  if (xd) {
+    const double d = dq.W ? dq.W[a] : (double)dq.in.len[a];
+    xd[stride * a + half] = d > 0.0 ? 1.0 / d : 0.0;
+  }
 }
 
 // S of a spanning forest (Example 1.2): row a of the tile, columns c0 + t, t < kTreeCols.
@@ -391,17 +443,58 @@ inline unsigned g1(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
 }  // namespace
 
+// A list held in device memory is written by a zero fill and a scatter (no thread loops over
+// a long list).
+static IdList empty_list() {
+  IdList e;
+  e.count = 0;
+  e.dev = nullptr;
+  return e;
+}
+
 hipError_t launch_indicator(double* x, int64_t n, const IdList& ids, hipStream_t s,
                             const DevQ* dq, double* xd) {
   if (n <= 0) return hipSuccess;
-  indicator_kernel<<<g1(n), kB, 0, s>>>(x, n, ids, dq ? *dq : DevQ{}, dq ? xd : nullptr);
-  return hipGetLastError();
+  const DevQ q = dq ? *dq : DevQ{};
+  double* xo = dq ? xd : nullptr;
+  indicator_kernel<<<g1(n), kB, 0, s>>>(x, n, ids.dev ? empty_list() : ids, q, xo);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && ids.dev && ids.count > 0) {
+    indicator_scatter_kernel<<<g1(ids.count), kB, 0, s>>>(x, ids, 1, 0, q, xo);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_indicator2(double* x2, int64_t n, const IdList& a, const IdList& b,
                              hipStream_t s, const DevQ& dq, double* xd2) {
   if (n <= 0) return hipSuccess;
-  indicator2_kernel<<<g1(n), kB, 0, s>>>(x2, n, a, b, dq, xd2);
+  indicator2_kernel<<<g1(n), kB, 0, s>>>(x2, n, a.dev ? empty_list() : a,
+                                         b.dev ? empty_list() : b, dq, xd2);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.dev && a.count > 0) {
+    indicator_scatter_kernel<<<g1(a.count), kB, 0, s>>>(x2, a, 2, 0, dq, xd2);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && b.dev && b.count > 0) {
+    indicator_scatter_kernel<<<g1(b.count), kB, 0, s>>>(x2, b, 2, 1, dq, xd2);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_ids_range(const int32_t* a, const int32_t* b, int64_t np, int32_t* mm,
+                            hipStream_t s) {
+  ids_range_init_kernel<<<1, 1, 0, s>>>(mm);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || np <= 0) return e;
+  const int64_t blocks = std::min<int64_t>((np + kB - 1) / kB, 1024);
+  ids_range_kernel<<<(unsigned)blocks, kB, 0, s>>>(a, b, np, mm);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_at(const double* v, const IdList& I, double* out, hipStream_t s) {
+  sum_at_kernel<<<1, 64, 0, s>>>(v, I, out);
   return hipGetLastError();
 }
 
@@ -462,8 +555,9 @@ hipError_t launch_gamma(const GammaArgs& g, int64_t n, const double* SI, const d
 }
 
 hipError_t launch_c1_border(SView S, int64_t n_old, int32_t j, const double* y,
-                            const double* SI, const IdList& I, double C, hipStream_t s) {
-  c1_border_kernel<<<g1(n_old > 0 ? n_old : 1), kB, 0, s>>>(S, n_old, j, y, SI, I, C);
+                            const double* SI, const IdList& I, double C, hipStream_t s,
+                            const double* sumI) {
+  c1_border_kernel<<<g1(n_old > 0 ? n_old : 1), kB, 0, s>>>(S, n_old, j, y, SI, I, C, sumI);
   return hipGetLastError();
 }
 

@@ -23,9 +23,22 @@ struct SlotList {
   std::vector<int32_t> idx;
   std::vector<double> w;  // per slot weights (weighted graphs only)
   int64_t used = 0;
+  int64_t need = 0;  // slots a repack would take now: sum over rows of packed_cap(len)
   bool weighted = false;
 
   static int32_t slack_cap(int32_t l) { return l + std::max<int32_t>(4, l / 4); }
+  static int64_t packed_cap(int64_t l) { return l ? slack_cap((int32_t)l) : 0; }
+
+  // Whether appending add[r] entries to each listed row r (rows ascending or not) is
+  // guaranteed to succeed: a repack after all of them, plus one fresh row, fits the slot
+  // array. Every insertion path (in place, row move, repack) succeeds when this holds.
+  template <typename Map>
+  bool fits(const Map& add) const {
+    int64_t after = need;
+    for (const auto& ra : add)
+      after += packed_cap((int64_t)len[ra.first] + ra.second) - packed_cap(len[ra.first]);
+    return after + 4 <= (int64_t)idx.size();
+  }
 
   // Builds rows of nodes [0, node_cap) from (row, val) pairs in edge order.
   void build(int64_t node_cap, int64_t slot_cap, const std::vector<int32_t>& row,
@@ -41,6 +54,7 @@ struct SlotList {
       pos += cap[r];
     }
     used = pos;
+    need = pos;
     idx.assign(std::max<int64_t>(slot_cap, pos), -1);
     weighted = wts != nullptr;
     if (weighted) w.assign(idx.size(), 0.0);
@@ -55,9 +69,9 @@ struct SlotList {
 
   // Rebuilds with fresh slack (row order preserved). Returns false if slot_cap is too small.
   bool repack() {
-    int64_t need = 0;
-    for (size_t r = 0; r < len.size(); ++r) need += len[r] ? slack_cap(len[r]) : 0;
-    if (need > (int64_t)idx.size()) return false;
+    int64_t tot = 0;
+    for (size_t r = 0; r < len.size(); ++r) tot += packed_cap(len[r]);
+    if (tot > (int64_t)idx.size()) return false;
     std::vector<int32_t> nidx(idx.size(), -1);
     std::vector<double> nw;
     if (weighted) nw.assign(idx.size(), 0.0);
@@ -75,6 +89,7 @@ struct SlotList {
     idx.swap(nidx);
     if (weighted) w.swap(nw);
     used = pos;
+    need = pos;
     return true;
   }
 
@@ -86,10 +101,18 @@ struct SlotList {
 
   // Appends v to row r. Returns 0 on an in-place edit (writes appended to out), 1 when the row
   // moved (its whole content must be uploaded: rows_moved gets r), 2 when the slot array was
-  // repacked (the caller uploads everything), 3 when even a repack has no room (the mirror
-  // stays consistent but repacked; the caller uploads everything and reports capacity).
+  // repacked (the caller uploads everything), 3 when even a repack has no room: nothing is
+  // appended (the rows may have been repacked, which the caller must upload). Callers check
+  // fits() first, under which 3 does not occur.
   int insert(int32_t r, int32_t v, double wt, std::vector<Write>& out,
              std::vector<int32_t>& rows_moved) {
+    const int rc = insert_impl(r, v, wt, out, rows_moved);
+    if (rc != 3) need += packed_cap(len[r]) - packed_cap(len[r] - 1);
+    return rc;
+  }
+
+  int insert_impl(int32_t r, int32_t v, double wt, std::vector<Write>& out,
+                  std::vector<int32_t>& rows_moved) {
     if (len[r] < cap[r]) {
       const int32_t p = start[r] + len[r];
       idx[p] = v;
@@ -146,6 +169,7 @@ struct SlotList {
     }
     idx[last] = -1;
     len[r]--;
+    need += packed_cap(len[r]) - packed_cap(len[r] + 1);
     out.push_back({1, r, len[r]});
     return true;
   }

@@ -23,11 +23,15 @@ struct AdjPtrs {
 };
 hipError_t launch_patch(const AdjPtrs& t, const Patch& p, hipStream_t s);
 
-// Row lists passed by value (sources I of a block, up to 60 per launch).
+// A list of node ids (the sources I of a block). Up to MAX ids travel by value in the
+// kernel arguments; a longer list lives in device memory (dev, count entries), so a block of
+// any size is one launch sequence. Kernels read entry t with at(t).
 struct IdList {
   static constexpr int MAX = 60;
-  int32_t count;
+  int32_t count = 0;
   int32_t id[MAX];
+  const int32_t* dev = nullptr;  // device ids when count > MAX, else null
+  __host__ __device__ int32_t at(int t) const { return dev ? dev[t] : id[t]; }
 };
 
 // ---------------------------------------------------------------------------------------
@@ -125,6 +129,10 @@ struct GammaArgs {
   double C;
   double xi0;       // xi_0 = xi0 * e_j
   IdList I;         // sources (for S_II and the direct form's v)
+  // When set, the sum over I of the closed form's S[:, I] (kind 0: S_II) or of the direct
+  // form's z (kind 1), precomputed by launch_sum_at; long lists use it so that no thread
+  // loops over I.
+  const double* sumI;
 };
 // Writes column 0 of the panel: (xi_0, eta_0) = (xi0 e_j, gamma). Inputs: SI = S[:, I],
 // Sj = S[:, j], QSI = Q_old S[:, I]; the direct form also needs zsum = sum over in_old(j)
@@ -133,14 +141,22 @@ struct GammaArgs {
 hipError_t launch_gamma(const GammaArgs& g, int64_t n, const double* SI, const double* Sj,
                         const double* QSI, const double* zbuf, const double* Qz, double* P,
                         int pld, unsigned long long* maxabs, hipStream_t s);
+// mm[0] = min, mm[1] = max over the ids a[p], b[p], p < np (device int32 arrays); with
+// np = 0, mm = (INT32_MAX, INT32_MIN).
+hipError_t launch_ids_range(const int32_t* a, const int32_t* b, int64_t np, int32_t* mm,
+                            hipStream_t s);
+// out[0] = sum_{t < I.count} v[I.at(t)] in a fixed order (one wave).
+hipError_t launch_sum_at(const double* v, const IdList& I, double* out, hipStream_t s);
 // Direct form step 1: z = S v into zbuf, from SI and zsum (see Theorem 2, eq (20)).
 hipError_t launch_direct_z(const GammaArgs& g, int64_t n, const double* SI,
                            const double* zsum, double* zbuf, hipStream_t s);
 
 // C1 border (Theorem 8, Table 2 row C1): S[j][a] = S[a][j] = y[a] for a < n_old,
-// S[j][j] = corner = (C/delta^2) S_II + 1 - C (S_II read from SI at the sources).
+// S[j][j] = corner = (C/delta^2) S_II + 1 - C (S_II read from SI at the sources, or from
+// *sumI when set).
 hipError_t launch_c1_border(SView S, int64_t n_old, int32_t j, const double* y,
-                            const double* SI, const IdList& I, double C, hipStream_t s);
+                            const double* SI, const IdList& I, double C, hipStream_t s,
+                            const double* sumI = nullptr);
 // Writes S[id][id] = val[t] for a short list (new-node diagonals).
 struct DiagList {
   static constexpr int MAX = 30;
@@ -260,8 +276,6 @@ hipError_t launch_corr_update(const double* Pseg, int pld, int64_t n, const Corr
 hipError_t launch_panel_correct(const double* P, int pld, int64_t gstride, int r, int64_t n,
                                 const IdList& I, int32_t j, double* wts, double* SI,
                                 double* Sj, hipStream_t s);
-// Plain reference form of the same update (one thread per entry, no MFMA), for checks.
-hipError_t launch_lowrank_ref(const LowRankArgs& a, hipStream_t s);
 // out[a] = sum_{c < r} P[a][c] * P[x][c ^ 1] for a < n (Delta S[:, x], eq (71)), float64.
 hipError_t launch_delta_col(const double* P, int pld, int r, int64_t n, int32_t x, double* out,
                             hipStream_t s);

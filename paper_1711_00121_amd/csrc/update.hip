@@ -26,13 +26,6 @@ constexpr int RC = 32;    // panel columns staged per pass
 constexpr int LP = RC + 1;  // LDS row pitch in doubles (odd pitch spreads banks)
 constexpr int NT = 256;
 
-__device__ __forceinline__ bool pair_in(const uint32_t* Ah, const uint32_t* Bh, bool ra, bool rb,
-                                        int64_t b) {
-  if (!Ah) return true;
-  const bool ca = bit_get(Ah, b), cb = bit_get(Bh, b);
-  return (ra && cb) || (rb && ca);
-}
-
 // An S entry as loaded (no arithmetic on it until it is needed, so that the load can stay in
 // flight): FP64 value, or FP32 value and compensation.
 template <int PREC>
@@ -459,27 +452,6 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
   }
 }
 
-__global__ __launch_bounds__(256) void lowrank_ref_kernel(LowRankArgs g) {
-  const int64_t nrows = g.nrows_dev ? *g.nrows_dev : g.nrows;
-  const int64_t t = blockIdx.x;
-  if (t >= nrows) return;
-  const int64_t b = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  if (b >= g.ncols) return;
-  const bool packed = g.out == nullptr && g.Ahat != nullptr && g.rows != nullptr;
-  const int64_t a = g.rows ? ((int64_t)g.rows[t] >> (packed ? 2 : 0)) : t;
-  if (g.out == nullptr && g.Ahat) {
-    if (!pair_in(g.Ahat, g.Bhat, bit_get(g.Ahat, a), bit_get(g.Bhat, a), b)) return;
-  }
-  double d = 0.0;
-  for (int c = 0; c < g.r; ++c) d += g.P[a * g.pld + c] * g.P[b * g.pld + (c ^ 1)];
-  if (g.out) {
-    g.out[t * g.ld_out + b] = (float)d;
-  } else {
-    const int64_t off = a * g.S.ld + b;
-    s_put(g.S, off, s_get(g.S, off) + d);
-  }
-}
-
 __global__ __launch_bounds__(256) void delta_col_kernel(const double* __restrict__ P, int pld,
                                                        int r, int64_t n, int32_t x,
                                                        double* __restrict__ out) {
@@ -498,7 +470,7 @@ __global__ __launch_bounds__(256) void panel_weights_kernel(const double* __rest
   const int cs = col ^ 1;
   const double* base = P + (int64_t)(cs / pld) * gstride + cs % pld;
   double w = 0.0;
-  for (int t = 0; t < I.count; ++t) w += base[(int64_t)I.id[t] * pld];
+  for (int t = 0; t < I.count; ++t) w += base[(int64_t)I.at(t) * pld];
   wts[col] = w;
   wts[r + col] = j >= 0 ? base[(int64_t)j * pld] : 0.0;
 }
@@ -831,14 +803,6 @@ hipError_t launch_lowrank_acc(const LowRankArgs& a, hipStream_t s) {
   const int64_t tiles = T * TJ;
   const int64_t per = (tiles + NXCD - 1) / NXCD;
   lowrank_gemm_kernel<PREC_FP64, true><<<(unsigned)(per * NXCD), NT, 0, s>>>(a, T, per, TJ);
-  return hipGetLastError();
-}
-
-hipError_t launch_lowrank_ref(const LowRankArgs& a, hipStream_t s) {
-  const int64_t nrows = a.nrows_dev ? a.ncols : a.nrows;  // upper bound; kernel checks
-  if (a.ncols <= 0 || nrows <= 0) return hipSuccess;
-  dim3 grid((unsigned)nrows, (unsigned)((a.ncols + 255) / 256));
-  lowrank_ref_kernel<<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

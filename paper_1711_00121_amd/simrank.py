@@ -126,6 +126,7 @@ class Context:
         L.check(st, "init_simrank")
         self.h = handle
         self.m0 = len(src)
+        self.weights = w
 
     # ------------------------------------------------------------------ updates
     def apply_edge_update(self, i, j, op=1, stats=False):
@@ -286,13 +287,23 @@ class Context:
 class SimRankPairs(torch.autograd.Function):
     """``S[a, b]`` for the context's graph as a function of its edge weights.
 
-    ``forward(weights, context, a, b)`` returns the pair values; ``weights`` must be the
-    (m,) tensor the context was built from. ``backward`` calls the library's adjoint and
+    ``forward(weights, context, a, b)`` returns the pair values; ``weights`` must equal the
+    (m,) weights the context was built from (all ones for an unweighted context), else
+    ValueError. ``backward`` calls the library's adjoint and
     returns dL/dweights.
     """
 
     @staticmethod
     def forward(ctx, weights, context, a, b):
+        # the context holds S of the weights it was built with: any other weights would get
+        # stale values and gradients, so they are refused
+        ref = getattr(context, "weights", None)
+        if ref is None:
+            ref = np.ones(context.m0)
+        w = weights.detach().to(device="cpu", dtype=torch.float64).numpy()
+        if w.shape != ref.shape or not np.array_equal(w, ref):
+            raise ValueError("weights differ from those the context was built with; build a "
+                             "new Context for new weights")
         a = torch.as_tensor(a, dtype=torch.int32, device="cuda").contiguous()
         b = torch.as_tensor(b, dtype=torch.int32, device="cuda").contiguous()
         ctx.context = context

@@ -97,3 +97,28 @@ int main(void) {
         if "." in key:
             t, f = key.split(".")
             assert getattr(getattr(_lib, t), f).offset == int(val), key
+
+
+def test_simrank_pairs_refuses_other_weights_before_any_gpu_work():
+    """SimRankPairs checks the weights against the context's before touching the device."""
+    import numpy as np
+    import torch
+
+    from paper_1711_00121_amd import simrank_pairs
+
+    class Ctx:
+        m0 = 4
+        weights = np.array([1.0, 2.0, 0.5, 1.5])
+
+    with pytest.raises(ValueError):
+        simrank_pairs(torch.tensor([1.0, 2.0, 0.5, 1.25], dtype=torch.float64), Ctx(), [0], [1])
+    with pytest.raises(ValueError):
+        simrank_pairs(torch.ones(3, dtype=torch.float64), Ctx(), [0], [1])
+
+    class Unweighted:
+        m0 = 3
+        weights = None
+
+    with pytest.raises(ValueError):
+        simrank_pairs(torch.tensor([1.0, 1.0, 2.0], dtype=torch.float64), Unweighted(), [0],
+                      [1])

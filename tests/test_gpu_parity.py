@@ -208,15 +208,7 @@ def test_batches_match_oracle_plan_and_recompute():
         plan_or, n_new = OI.plan_batch(tr.n, cs, cd, bi, bj, bo)
         st = ctx.apply_batch(bi, bj, bo, stats=True)
         plan = ctx.last_plan()
-        # the library splits a block only past 60 sources; merge such splits back
-        merged = []
-        for b in plan:
-            if merged and merged[-1]["j"] == b["j"] and merged[-1]["op"] == b["op"] and \
-                    len(merged[-1]["I"]) == 60:
-                merged[-1]["I"] += b["I"]
-            else:
-                merged.append(dict(b))
-        assert [(b["case"], b["op"], b["j"], b["dj"], b["I"]) for b in merged] == \
+        assert [(b["case"], b["op"], b["j"], b["dj"], b["I"]) for b in plan] == \
                [(b["case"], b["op"], b["j"], b["dj"], b["I"]) for b in plan_or]
         plus, minus = OI.net_update(bi, bj, bo)
         for (i, j) in minus:
@@ -226,6 +218,63 @@ def test_batches_match_oracle_plan_and_recompute():
         tr.n = nn
         assert st["n_after"] == nn
         assert maxabs(ctx.S().cpu().numpy(), tr.exact(C)) < TOL
+
+
+def long_block_batches(n, s, d):
+    """Three batches whose similar-sink blocks have more than 60 sources each: 130 existing
+    sources into an existing sink (C0), 70 existing sources into a new sink (C1), 65 new
+    sources into an existing sink (C2), 64 new sources into a new sink (C3); then 70
+    deletions from a sink that keeps 64 in-edges (d_j > delta) beside 61 insertions into
+    another sink; then the deletion of all 64 in-edges of that sink (d_j = delta)."""
+    es = set(zip(s.tolist(), d.tolist()))
+    b1 = [(a, 0) for a in range(1, n) if (a, 0) not in es][:130]
+    b1 += [(a, n) for a in range(10, 80)]
+    b1 += [(n + 1 + t, 7) for t in range(65)]
+    b1 += [(n + 67 + t, n + 66) for t in range(64)]
+    es1 = es | set(b1)
+    d2 = [(a, 0, -1) for (a, _) in b1[:70]]
+    i2 = [(a, 7, 1) for a in range(100, n) if (a, 7) not in es1][:61]
+    es2 = (es1 - {(a, 0) for a, _, _ in d2}) | {(a, 7) for a, _, _ in i2}
+    d3 = sorted((a, 0, -1) for (a, j) in es2 if j == 0)
+    out = [([a for a, _ in b1], [j for _, j in b1], [1] * len(b1))]
+    for bt in (d2 + i2, d3):
+        out.append(([e[0] for e in bt], [e[1] for e in bt], [e[2] for e in bt]))
+    return out
+
+
+@pytest.mark.parametrize("fused,chunk", [(False, 64), (True, 2), (True, 64)])
+def test_long_blocks_are_single_updates(fused, chunk):
+    """Blocks of more than 60 sources (device-resident source lists) in every case: the
+    library's plan equals the oracle's unsplit Algorithm 6 plan, S matches the oracle's
+    Inc-bSR at the same K (K-matched, 1e-12) and the converged recompute (1e-6)."""
+    n, K = 400, 15
+    s, d = W.chung_lu(n, 2400, seed=81)
+    batches = long_block_batches(n, s, d)
+    ctx = ctx_for(n, s, d, s_prec="fp64", K=K, node_cap=n + 140, fused_batch=fused,
+                  batch_chunk=chunk)
+    tr = EdgeTracker(n, s, d)
+    S_or = O.fixed_point(tr.Q(), C)
+    assert maxabs(ctx.S().cpu().numpy(), S_or) < 1e-13
+    sizes = []
+    for bi, bj, bo in batches:
+        cs, cd = tr.arrays()
+        S_or, plan_or = OI.inc_bsr(tr.n, cs, cd, S_or, bi, bj, bo, C, K)
+        ctx.apply_batch(bi, bj, bo)
+        plan = ctx.last_plan()
+        assert [(b["case"], b["op"], b["j"], b["dj"], b["I"]) for b in plan] == \
+               [(b["case"], b["op"], b["j"], b["dj"], b["I"]) for b in plan_or]
+        sizes += [(b["case"], b["op"], len(b["I"])) for b in plan]
+        plus, minus = OI.net_update(bi, bj, bo)
+        for (i, j) in minus:
+            tr.apply(i, j, -1)
+        for (i, j) in plus:
+            tr.apply(i, j, 1)
+        S = ctx.S().cpu().numpy()
+        assert maxabs(S, S_or) < 1e-12
+        assert maxabs(S, tr.exact(C)) < TOL
+    assert sizes == [(0, 1, 130), (2, 1, 65), (1, 1, 70), (3, 1, 64), (0, -1, 70), (0, 1, 61),
+                     (0, -1, 64)]
+    ctx.close()
 
 
 def test_column_mode_delta_columns():

@@ -197,9 +197,9 @@ def test_column_batch_rejects_new_nodes():
         I.delta_columns_batch(n, s, d, [1], [n], [1], [0], C, 5, 5)
 
 
-def test_long_blocks_split_into_consecutive_blocks_of_one_sink():
-    """A sink with more than 60 sources is taken as consecutive blocks of at most 60 (sources
-    ascending); a new sink's later parts find it existing (case C1 then C0)."""
+def test_long_blocks_are_one_block_each():
+    """Algorithm 6 applies a sink's whole block as one Table 2 update: 130 existing sources
+    into sink 0 and 70 existing sources into the new sink 200 give two blocks."""
     n = 200
     src, dst = [1], [2]
     bi = list(range(3, 133))                      # 130 existing sources into sink 0
@@ -208,17 +208,29 @@ def test_long_blocks_split_into_consecutive_blocks_of_one_sink():
     bj += [200] * 70
     plan, n_new = I.plan_batch(n, src, dst, bi, bj, [1] * len(bi))
     assert n_new == 201
+    assert [(b["case"], b["j"], len(b["I"]), b["dj"]) for b in plan] == \
+        [(0, 0, 130, 0), (1, 200, 70, 0)]
+    assert plan[0]["I"] == list(range(3, 133)) and plan[1]["I"] == list(range(10, 80))
+
+
+def test_optional_split_takes_consecutive_blocks_of_one_sink():
+    """With max_sources the same batch becomes consecutive blocks of at most 60 (sources
+    ascending); a new sink's later parts find it existing (case C1 then C0)."""
+    n = 200
+    src, dst = [1], [2]
+    bi = list(range(3, 133)) + list(range(10, 80))
+    bj = [0] * 130 + [200] * 70
+    plan, _ = I.plan_batch(n, src, dst, bi, bj, [1] * len(bi), max_sources=60)
     sizes = [(b["case"], b["j"], len(b["I"]), b["dj"]) for b in plan]
     assert sizes == [(0, 0, 60, 0), (0, 0, 60, 60), (0, 0, 10, 120),
                      (1, 200, 60, 0), (0, 200, 10, 60)]
     assert plan[0]["I"] == list(range(3, 63)) and plan[2]["I"] == list(range(123, 133))
-    whole, _ = I.plan_batch(n, src, dst, bi, bj, [1] * len(bi), max_sources=None)
-    assert [len(b["I"]) for b in whole] == [130, 70]
 
 
 def test_split_blocks_compose_to_recompute():
-    """Inc-bSR with the 60-source split and without it both reach the recompute of the
-    updated graph at a deep series (the split only changes each part's truncation)."""
+    """Consecutive Table 2 updates of one sink compose: Inc-bSR with a 60-source split and
+    without it both reach the recompute of the updated graph at a deep series (the split
+    only changes each part's truncation)."""
     n = 90
     s, d = W.chung_lu(n, 300, seed=741)
     es = set(zip(s.tolist(), d.tolist()))
@@ -226,9 +238,12 @@ def test_split_blocks_compose_to_recompute():
     bi = [a for a, _ in add]
     bj = [b for _, b in add]
     S0 = O.fixed_point(Gr.transition_matrix(n, s, d), C)
-    S1, plan = I.inc_bsr(n, s, d, S0, bi, bj, [1] * len(bi), C, 60)
-    assert [len(b["I"]) for b in plan] == [60, 10]
     s2 = np.concatenate([s, bi])
     d2 = np.concatenate([d, bj])
     exact = O.fixed_point(Gr.transition_matrix(n, s2, d2), C)
+    S1, plan = I.inc_bsr(n, s, d, S0, bi, bj, [1] * len(bi), C, 60, max_sources=60)
+    assert [len(b["I"]) for b in plan] == [60, 10]
     assert np.abs(S1 - exact).max() < 1e-11
+    S2, plan = I.inc_bsr(n, s, d, S0, bi, bj, [1] * len(bi), C, 60)
+    assert [len(b["I"]) for b in plan] == [70]
+    assert np.abs(S2 - exact).max() < 1e-11
