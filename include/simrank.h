@@ -226,6 +226,19 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
 sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
                      int32_t exclude_self, int32_t* idx_dev, double* val_dev);
 
+/* query_topk for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same selection, bit for bit, but
+ * the query ids are staged in a static per-GPU device array of 65,536 ids (256 KiB, held until
+ * the process ends) instead of a buffer the context allocates; the call neither allocates nor
+ * frees memory and does not synchronise the stream itself. q: host array of nq ids, copied to
+ * the array by a copy enqueued on the context's stream: keep it unchanged until that stream
+ * has run the call's work. SR_ECAPACITY for nq > 65536 (nothing is launched); otherwise as
+ * query_topk. Every call on a
+ * GPU shares that GPU's array: calls on different streams of one GPU that overlap in time
+ * race on it (calls on one stream are ordered). */
+sr_status query_topk_noalloc(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
+                             int32_t exclude_self, int32_t* idx_dev, double* val_dev);
+
 /* Gathers S[a[p], b[p]] for npairs pairs into out_dev (float64); a_dev, b_dev device int32.
  * Dense mode. */
 sr_status sr_gather_pairs(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev,

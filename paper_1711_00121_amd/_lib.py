@@ -92,6 +92,7 @@ SIGNATURES = {
     "query_column": (C.c_int, [P, C.c_int32, C.c_int32, P]),
     "query_columns": (C.c_int, [P, I32P, C.c_int32, P, C.c_int64]),
     "query_topk": (C.c_int, [P, I32P, C.c_int32, C.c_int32, C.c_int32, P, P]),
+    "query_topk_noalloc": (C.c_int, [P, I32P, C.c_int32, C.c_int32, C.c_int32, P, P]),
     "sr_gather_pairs": (C.c_int, [P, C.c_int64, P, P, P]),
     "backward": (C.c_int, [P, C.c_int64, P, P, P, P]),
     "sr_get_aff": (C.c_int, [P, C.c_int32, P, C.POINTER(C.c_int64), P,

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <vector>
@@ -13,6 +14,14 @@
 #include "simrank.h"
 
 using namespace sr;
+
+// Staging area of query_topk_noalloc: the query ids of one call, in a file-scope device array
+// so that the call allocates nothing. Every GPU the library runs on holds its own copy, at its
+// own address, until the process ends; calls on one GPU share it and see the last call's ids.
+// In host code `scratch` is a host-side stand-in, not a device address: host code uses only
+// the address hipGetSymbolAddress returns for the device (scratch_ptr below).
+constexpr int64_t kScratchIds = 65536;  // 256 KiB per GPU
+static __device__ __align__(256) int32_t scratch[kScratchIds];
 
 // Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
 // process them in chunks (see graph.hip).
@@ -36,6 +45,7 @@ struct HeavySet {
 struct sr_ctx {
   sr_config cfg{};
   hipStream_t stream = nullptr;
+  int device = 0;  // the GPU that was current at init (its allocations live there)
   bool poisoned = false;
   bool weighted = false;
   bool updated = false;  // graph changed since init
@@ -737,6 +747,26 @@ sr_status partial_sim2(sr_ctx* ctx, const IdList& a, const IdList& b, double* ou
 
 bool valid_ctx(sr_ctx* c) { return c != nullptr; }
 
+// Device addresses of `scratch`, one per GPU, resolved once per device at context creation
+// (with that device current) and kept for the life of the process.
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+int32_t* scratch_ptr[kMaxDevices] = {};
+
+sr_status resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return SR_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[dev]) return SR_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    return SR_EHIP;
+  }
+  scratch_ptr[dev] = static_cast<int32_t*>(p);
+  return SR_OK;
+}
+
 // Checks that every id of the device pair arrays lies in [0, n) before they are used as
 // addresses (synchronises the stream): SR_ERANGE otherwise.
 sr_status check_pair_ids(sr_ctx* ctx, int64_t np, const int32_t* a, const int32_t* b) {
@@ -870,6 +900,18 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   ctx->hin.split = ctx->hout.split = cfg.split_rows;
   ctx->profiling = cfg.profile != 0;
   ctx->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return SR_EHIP;
+  }
+  {
+    const sr_status rs = resolve_scratch(ctx->device);
+    if (rs != SR_OK) {
+      delete ctx;
+      return rs;
+    }
+  }
   ctx->node_cap = node_cap;
   ctx->edge_cap = edge_cap;
   ctx->weighted = weight != nullptr;
@@ -2008,6 +2050,43 @@ sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
         return launch_topk(ctx->S, ctx->Sj, 0, ctx->d_ids + t + 1, 1, n, k, ex,
                            idx_dev + (int64_t)(t + 1) * k, val_dev + (int64_t)(t + 1) * k, s);
       }));
+  }
+  return SR_OK;
+}
+
+sr_status query_topk_noalloc(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
+                             int32_t exclude_self, int32_t* idx_dev, double* val_dev) {
+  if (!valid_ctx(ctx) || nq < 0 || (nq > 0 && (!q || !idx_dev || !val_dev))) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  const int64_t n = ctx->g.n;
+  if (k < 1 || k > kTopkMax || k > n - (exclude_self ? 1 : 0)) return SR_EINVAL;
+  if (nq > kScratchIds) return SR_ECAPACITY;
+  for (int32_t t = 0; t < nq; ++t)
+    if (q[t] < 0 || q[t] >= n) return SR_ERANGE;
+  if (nq == 0) return SR_OK;
+  int32_t* ids = (ctx->device >= 0 && ctx->device < kMaxDevices) ? scratch_ptr[ctx->device]
+                                                                 : nullptr;
+  if (!ids) return SR_EHIP;
+  hipStream_t s = ctx->stream;
+  const int ex = exclude_self ? 1 : 0;
+  // stream-ordered: an earlier call's kernels on this stream have read the previous ids
+  HC(hipMemcpyAsync(ids, q, (size_t)nq * 4, hipMemcpyHostToDevice, s));
+  if (ctx->cfg.mode == SR_DENSE) {
+    HC(launch_topk(ctx->S, nullptr, 0, ids, nq, n, k, ex, idx_dev, val_dev, s));
+    return SR_OK;
+  }
+  for (int32_t t = 0; t < nq; t += 2) {
+    IdList a, b;
+    a.count = b.count = 1;
+    a.id[0] = q[t];
+    b.id[0] = q[t + 1 < nq ? t + 1 : t];
+    sr_status r = partial_sim2(ctx, a, b, ctx->SI, ctx->Sj);
+    if (r != SR_OK) return r;
+    HC(launch_topk(ctx->S, ctx->SI, 0, ids + t, 1, n, k, ex, idx_dev + (int64_t)t * k,
+                   val_dev + (int64_t)t * k, s));
+    if (t + 1 < nq)
+      HC(launch_topk(ctx->S, ctx->Sj, 0, ids + t + 1, 1, n, k, ex,
+                     idx_dev + (int64_t)(t + 1) * k, val_dev + (int64_t)(t + 1) * k, s));
   }
   return SR_OK;
 }
