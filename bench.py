@@ -42,6 +42,9 @@ METRIC = ("ΔS pair-updates/s + edge updates/s at n=50k vs plain GPU path; % HBM
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 C = 0.6
+# the oracle's all-core leg uses at most this many host threads (a GPU machine's CPU share)
+MAX_ORACLE_WORKERS = 16
+ORACLE_POOL = None
 
 
 def log(*a):
@@ -70,6 +73,9 @@ def main():
     ap.add_argument("--cb-edges", default="48,16,16",
                     help="columns_batch: insertions, deletions, insertions sharing one sink")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fp64-shadow", action="store_true",
+                    help="batch: replay the same batches on a float64 store afterwards "
+                         "(untimed) and report the store's gap on sampled rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -80,18 +86,26 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    global ORACLE_POOL
+    if not args.no_cpu_baseline:
+        # the oracle's worker processes start before this process touches the GPU
+        ORACLE_POOL = OraclePool(min(len(os.sched_getaffinity(0)), MAX_ORACLE_WORKERS))
     import torch
     torch.cuda.set_device(0)
     run = {"batch": run_batch, "stream": run_stream, "columns": run_columns,
            "columns_batch": run_columns_batch, "forest": run_forest,
            "partitioned": run_partitioned, "topk": run_topk,
            "adjoint": run_adjoint}[args.workload]
-    print(json.dumps(run(args)), flush=True)
+    out = run(args)
+    if ORACLE_POOL is not None:
+        ORACLE_POOL.close()
+    print(json.dumps(out), flush=True)
 
 
 def common(args, cfg, value, unit, dt, steps, dtype="f64", extra_cfg=None):
     c = {"workload": cfg["name"], "n": args.n or cfg["n"], "m": args.m or cfg["m"],
-         "C": cfg["C"], "K": cfg["K"], "parallelism": "single GPU"}
+         "C": cfg["C"], "K": cfg["K"], "parallelism": "single GPU", "steps": steps,
+         "warmup": args.warmup}
     c.update(extra_cfg or {})
     return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * dt / max(steps, 1),
@@ -100,8 +114,12 @@ def common(args, cfg, value, unit, dt, steps, dtype="f64", extra_cfg=None):
 
 
 def counters_for(args, name):
-    """The workload name under which committed HBM counters apply: none for resized runs."""
-    return name if not (args.n or args.m) else "resized"
+    """The configuration under which committed HBM counters apply: the workload name with the
+    run's steps and warmup (the graph and S grow from step to step, so counters taken on
+    another run length describe another state); none for resized runs."""
+    if args.n or args.m:
+        return "resized"
+    return f"{name} steps={args.steps} warmup={args.warmup}"
 
 
 def hbm_roof(bytes_, ms, kernel, launches, algorithmic, workload):
@@ -141,93 +159,134 @@ def run_batch(args):
         torch.cuda.synchronize()
         log(f"bench: warmup batch {w} ({len(bi)} edges) done")
 
+    n_first = ctx.sizes()[0]
     ctx.profile(True)
     ctx.profile_read(reset=True)
-    edges = pairs = lowrank = passes = 0
-    n_nodes = []
+    edges_in = edges_net = pairs = lowrank = passes = 0
+    flops = 0.0
+    # net edges per Table 2 case (C0 insertions and deletions apart), from the batch plans
+    mix = {"C0+": 0, "C0-": 0, "C1": 0, "C2": 0, "C3": 0}
+    plan_s = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         bi, bj, bo = batches[args.warmup + k]
         st = ctx.apply_batch(bi, bj, bo, stats=True)
-        edges += len(bi)
+        tp = time.perf_counter()
+        for b in ctx.last_plan():
+            key = ("C0+" if b["op"] > 0 else "C0-") if b["case"] == 0 else f"C{b['case']}"
+            mix[key] += len(b["I"])
+        plan_s += time.perf_counter() - tp
+        edges_in += len(bi)
+        edges_net += st["edges_net"]
         pairs += st["pairs"]
         lowrank += st["lowrank_blocks"]
         passes += st["fused_passes"]
-        n_nodes.append(st["n_after"])
-        log(f"bench: step {k}: {len(bi)} edges, {st['blocks']} blocks "
-            f"({st['lowrank_blocks']} low-rank), {st['fused_passes']} fused passes")
+        nt = float(st["n_after"])
+        # Delta S is symmetric: a low-rank block's work is its n (n + 1) / 2 distinct entries
+        # at 2 (K + 1) multiply-adds each, n the node count of the batch that applies it
+        flops += nt * (nt + 1.0) * 2 * (K + 1) * st["lowrank_blocks"]
+        log(f"bench: step {k}: {len(bi)} edges ({st['edges_net']} net), {st['blocks']} blocks "
+            f"({st['lowrank_blocks']} low-rank), {st['fused_passes']} fused passes, "
+            f"n = {st['n_after']}")
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = time.perf_counter() - t0 - plan_s  # the plan copies are bookkeeping, not timed
     kern_ms, launches = ctx.profile_read(reset=True)
     ctx.profile(False)
+    n_last, m_last = ctx.sizes()
+    assert sum(mix.values()) == edges_net
 
-    # Plain GPU path: the next batch's edges between existing nodes, one apply_edge_update each
-    # (pruned single-edge update, same precision), keeping edges whose net effect in the batch
-    # is this single operation.
+    # Accuracy of the timed state: stored rows against the oracle's converged columns of the
+    # graph after the timed batches (the hub, the newest node, sinks of the last batch, and
+    # two uniform nodes), and exact symmetry of sampled entries.
+    applied = list(zip(batches[:args.warmup + args.steps], counts[:args.warmup + args.steps]))
+    fn, fs, fd = graph_after(n, s, d, applied)
+    assert fn == n_last and len(fs) == m_last
+    accuracy = None
+    if ORACLE_POOL is not None:
+        indeg = np.bincount(np.asarray(fd), minlength=fn)
+        last_sinks = list(dict.fromkeys(int(x) for x in batches[args.warmup + args.steps - 1][1]))
+        g = np.random.default_rng(11)
+        xs = list(dict.fromkeys([int(np.argmax(indeg)), fn - 1] + last_sinks[:4] +
+                                [int(x) for x in g.integers(fn, size=2)]))
+        exact = oracle_columns(fn, fs, fd, xs)
+        got = np.stack([ctx.query_column(x).cpu().numpy() for x in xs])
+        pa = g.integers(fn, size=200000).astype(np.int32)
+        pb = g.integers(fn, size=200000).astype(np.int32)
+        sym = int((ctx.gather_pairs(pa, pb) != ctx.gather_pairs(pb, pa)).sum())
+        accuracy = {"vs": "oracle FP64 converged single-source columns of the graph after the "
+                          "timed batches (tail <= 1e-13)",
+                    "nodes": xs, "max_abs": float(np.abs(got - exact).max()),
+                    "bar": 1e-6, "asymmetric_pairs_of_200000": sym}
+        log(f"bench: accuracy of the timed state {accuracy['max_abs']:.2e} on {len(xs)} columns")
+
+    if args.fp64_shadow:
+        # the same batches on a float64 store: the value + compensation store's gap from it
+        g = np.random.default_rng(13)
+        rows = list(dict.fromkeys((accuracy["nodes"] if accuracy else []) +
+                                  [int(x) for x in g.integers(n_last, size=56)]))
+        got = torch.stack([ctx.query_column(x) for x in rows])
+        ref = Context(n, s, d, C=C, K=K, s_prec="fp64", node_cap=counts[-1] + 64,
+                      split_rows=args.split_rows,
+                      edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
+                      fused_batch=not args.no_fused, batch_chunk=args.chunk)
+        for t in range(args.warmup + args.steps):
+            ref.apply_batch(*batches[t])
+            log(f"bench: float64-store replay, batch {t} done")
+        gap = float((got - torch.stack([ref.query_column(x) for x in rows])).abs().max())
+        ref.close()
+        del got
+        torch.cuda.empty_cache()
+        accuracy = dict(accuracy or {})
+        accuracy.update({"store_gap_vs_fp64_store": gap, "store_gap_rows": len(rows)})
+        log(f"bench: store gap vs float64 store {gap:.2e} on {len(rows)} rows")
+
+    # Plain GPU path: one apply_edge_update per edge on the same state and precision, per
+    # Table 2 case: C0 insertions and deletions from the next batch (edges whose net effect in
+    # it is that single operation), then single edges into a new sink (C1), from a new source
+    # (C2) and between two new nodes (C3). The batched path is compared with these per-case
+    # times weighted by the timed batches' own case mix.
     from collections import Counter
     bi, bj, bo = batches[args.warmup + args.steps]
-    cur_n = ctx.sizes()[0]
     cnt = Counter((int(a), int(b)) for a, b in zip(bi, bj))
-    sample, seen = [], set()
+    ins, dels = [], []
     for a, b, o in zip(bi.tolist(), bj.tolist(), bo.tolist()):
-        if a < cur_n and b < cur_n and (a, b) not in seen and cnt[(a, b)] == 1:
-            seen.add((a, b))
-            sample.append((a, b, o))
-    sample = sample[:args.plain_edges]
+        if a < n_last and b < n_last and cnt[(a, b)] == 1:
+            (ins if o > 0 else dels).append((a, b, o))
+    sample = ins[:args.plain_edges] + dels[:args.plain_edges // 2]
     ctx.profile(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    times = {"C0+": [], "C0-": []}
     plain_pairs = 0
     for a, b, o in sample:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         plain_pairs += ctx.apply_edge_update(a, b, o, stats=True)["pairs"]
-    torch.cuda.synchronize()
-    dt_plain = time.perf_counter() - t1
+        times["C0+" if o > 0 else "C0-"].append(time.perf_counter() - t1)
     plain_ms, plain_launches = ctx.profile_read(reset=True)
     ctx.profile(False)
-
-    from paper_1711_00121_amd._lib import SR_EEXIST, SimRankError
-    # Per case (Table 2 rows C0-C3), single edges on the plain path: an edge between existing
-    # nodes, into a new sink, from a new source, and between two new nodes (ids dense).
-    per_case = {}
-    rng = np.random.default_rng(4203)
-    es_cur = set()
-    for case in ("C0", "C1", "C2", "C3"):
-        times = []
+    for case in ("C1", "C2", "C3"):
+        times[case] = []
+        rng = np.random.default_rng(4203)
         for _ in range(args.case_edges):
             n_cur = ctx.sizes()[0]
-            if case == "C0":
-                while True:
-                    a, b = (int(v) for v in rng.integers(n_cur, size=2))
-                    if a != b and (a, b) not in es_cur:
-                        break
-                es_cur.add((a, b))
-            elif case == "C1":
+            if case == "C1":
                 a, b = int(rng.integers(n_cur)), n_cur
             elif case == "C2":
                 a, b = n_cur, int(rng.integers(n_cur))
             else:
                 a, b = n_cur, n_cur + 1
             torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            try:
-                ctx.apply_edge_update(a, b, 1)
-            except SimRankError as e:  # an existing edge drawn for C0: skip it
-                if e.status != SR_EEXIST:
-                    raise
-                continue
+            t1 = time.perf_counter()
+            ctx.apply_edge_update(a, b, 1)
             torch.cuda.synchronize()
-            times.append((time.perf_counter() - t2) * 1e3)
-        per_case[case] = round(float(np.mean(times)), 3) if times else None
+            times[case].append(time.perf_counter() - t1)
+    per_case = {c: (1e3 * float(np.mean(v)) if v else None) for c, v in times.items()}
+    weighted = sum(mix[c] * per_case[c] for c in mix if mix[c]) / max(edges_net, 1) \
+        if all(per_case[c] is not None for c in mix if mix[c]) else None
+    plain_rate = 1e3 / weighted if weighted else None
+    edge_rate = edges_net / dt
 
-    edge_rate = edges / dt
-    plain_edge_rate = len(sample) / dt_plain if sample else None
-    nf = float(np.mean(n_nodes))
-    pld = 2 * (K + 1)
     if passes:
-        # Delta S is symmetric: the method's work per low-rank block is its n (n + 1) / 2
-        # distinct entries at 2 (K + 1) multiply-adds each
-        flops = nf * (nf + 1.0) * pld * lowrank
         achieved = flops / (kern_ms / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
@@ -235,7 +294,7 @@ def run_batch(args):
                 "kernel": "lowrank_gemm_kernel (fused batch pass)",
                 "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                 "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
-                               "block"}
+                               "block, n the node count of its batch"}
     else:
         roof = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
                         "16 B per pair-update (S value + compensation, read + write)",
@@ -245,26 +304,32 @@ def run_batch(args):
         plain_roof = hbm_roof(16.0 * plain_pairs, plain_ms, "lowrank_strip_kernel",
                               plain_launches,
                               "16 B per pair-update (S value + compensation, read + write)",
-                              counters_for(args, cfg["name"]))
+                              counters_for(args, cfg["name"] + "_plain"))
     cpu = None
-    if not args.no_cpu_baseline:
-        applied = list(zip(batches[:args.warmup + args.steps], counts[:args.warmup + args.steps]))
-        cpu = cpu_baseline_columns(*graph_after(n, s, d, applied), args.cpu_seconds,
+    if ORACLE_POOL is not None:
+        cpu = cpu_baseline_columns(fn, fs, fd, args.cpu_seconds,
                                    "the graph after the timed batches")
     out = common(args, cfg, pairs / dt, "pair-updates/s", dt, args.steps,
                  extra_cfg={"s_store": "f32 value + f32 compensation",
                             "max_batch": args.max_batch, "batch_chunk": args.chunk,
-                            "fused": not args.no_fused})
+                            "fused": not args.no_fused, "n_first": n_first, "n_last": n_last,
+                            "m_last": m_last})
     out.update({
-        "edge_updates_per_s": edge_rate, "edges": edges, "lowrank_blocks": lowrank,
-        "plain_ms_per_edge_by_case": per_case,
-        "fused_passes": passes,
-        "plain_gpu": {"edges": len(sample), "edge_updates_per_s": plain_edge_rate,
-                      "pair_updates_per_s": plain_pairs / dt_plain if sample else None,
+        "edge_updates_per_s": edge_rate, "edges_net": edges_net, "edges_in": edges_in,
+        "edges_in_per_s": edges_in / dt, "net_edges_by_case": mix,
+        "lowrank_blocks": lowrank, "fused_passes": passes,
+        "plain_gpu": {"ms_per_edge_by_case": per_case,
+                      "edges_timed_by_case": {c: len(v) for c, v in times.items()},
+                      "ms_per_edge_at_batch_mix": weighted,
+                      "edge_updates_per_s": plain_rate,
+                      "c0_pair_updates_per_s": (plain_pairs / (sum(times["C0+"]) +
+                                                               sum(times["C0-"])))
+                      if sample else None,
                       "roofline": plain_roof},
-        "speedup_edges_vs_plain": (edge_rate / plain_edge_rate) if plain_edge_rate else None,
+        "speedup_edges_vs_plain": (edge_rate / plain_rate) if plain_rate else None,
         "roofline": roof,
-        "hbm_rmw_ceiling_gbs": rmw_ceiling(8.0 * nf * nf),
+        "accuracy": accuracy,
+        "hbm_rmw_ceiling_gbs": rmw_ceiling(8.0 * n_last * n_last),
         "cpu_baseline": cpu,
     })
     return out
@@ -311,9 +376,33 @@ def run_stream(args):
                                "16 B per pair-update (S value + compensation, read + write)",
                                counters_for(args, cfg["name"]))
     out["hbm_rmw_ceiling_gbs"] = rmw_ceiling(8.0 * n * n)
+    # Precision: the same stream on a float64 store (untimed), and both against the
+    # oracle's converged columns of the final graph at sampled nodes.
+    ref = Context(n, s, d, C=C, K=K, s_prec="fp64", prune=True)
+    for i, j, op in stream:
+        ref.apply_edge_update(i, j, op)
+    torch.cuda.synchronize()
+    S_hilo = ctx.S()
+    gap = float((S_hilo - ref.S()).abs().max())
+    del S_hilo
+    torch.cuda.empty_cache()
+    fs, fd = final_edges(s, d, stream)
+    out["accuracy"] = {"store_gap_vs_fp64_store": gap}
+    if not args.no_cpu_baseline:
+        import numpy as np
+        indeg = np.bincount(fd, minlength=n)
+        xs = list(dict.fromkeys([int(np.argmax(indeg))] + [int(x) for x in stream[-1][:2]] +
+                                [int(x) for x in np.random.default_rng(12).integers(n, size=5)]))
+        exact = oracle_columns(n, fs, fd, xs)
+        got = np.stack([ctx.query_column(x).cpu().numpy() for x in xs])
+        got64 = np.stack([ref.query_column(x).cpu().numpy() for x in xs])
+        out["accuracy"].update({
+            "vs": "oracle FP64 converged single-source columns of the final graph",
+            "nodes": xs, "max_abs": float(np.abs(got - exact).max()),
+            "max_abs_fp64_store": float(np.abs(got64 - exact).max()), "bar": 1e-6})
+    ref.close()
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
-        fs, fd = final_edges(s, d, stream)
         out["cpu_baseline"] = cpu_baseline_columns(n, fs, fd, args.cpu_seconds,
                                                    "the graph after the stream")
     return out
@@ -520,7 +609,7 @@ def run_forest(args):
     ctx.close()
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_forest(K)
+        out["cpu_baseline"] = cpu_baseline_forest(K, args.cpu_seconds)
     return out
 
 
@@ -597,7 +686,7 @@ def run_partitioned(args, parts=16, p_cross=0.01):
     ctx.close()
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_partitioned(K, parts, p_cross)
+        out["cpu_baseline"] = cpu_baseline_partitioned(K, parts, p_cross, args.cpu_seconds)
     return out
 
 
@@ -754,7 +843,8 @@ def rmw_ceiling(nbytes):
 
 def traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    counters were taken on another workload or the kernel's source has changed since."""
+    counters were taken on another workload or run configuration (steps, warmup), or the
+    kernel's source has changed since."""
     import hashlib
     import re
     name = kernel.split(" ")[0]
@@ -767,7 +857,7 @@ def traffic(kernel, workload):
     m_src = re.search(r"Source: `([^`]+)`", text)
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    m_w = re.search(r"workload:\s*(\S+)", text)
+    m_w = re.search(r"^workload:\s*(.+?)\s*$", text, flags=re.M)
     if not (m_src and m_sha and m_b and m_w) or m_w.group(1) != workload:
         return None
     src = os.path.join(ROOT, m_src.group(1))
@@ -776,6 +866,129 @@ def traffic(kernel, workload):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
         return None
     return float(m_b.group(1))
+
+
+def host_cpu():
+    """The host CPU the oracle runs on: model name and logical CPU counts."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+_ORACLE_STATE = {}
+
+
+def _oracle_state(kind, path):
+    """Per-worker state of an oracle task kind, loaded once from the npz at `path`."""
+    import numpy as np
+    key = (kind, path)
+    if key in _ORACLE_STATE:
+        return _ORACLE_STATE[key]
+    z = dict(np.load(path, allow_pickle=False))
+    if kind in ("columns", "delta_columns"):
+        from oracle import graph as Gr
+        n = int(z["n"])
+        z["Q"] = Gr.transition_matrix(n, z["s"], z["d"])
+    _ORACLE_STATE.clear()
+    _ORACLE_STATE[key] = z
+    return z
+
+
+def oracle_task(kind, path, arg):
+    """One unit of oracle work (runs in a worker process, one BLAS thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        if kind == "warm":  # load the inputs of task kind `arg`
+            _oracle_state(arg, path)
+            time.sleep(0.2)  # so that every worker takes one
+            return None
+        z = _oracle_state(kind, path)
+        if kind == "columns":
+            from oracle import simrank as O
+            return O.single_source(z["Q"], int(arg), float(z["C"]), tol=1e-13)
+        if kind == "delta_columns":
+            from oracle import incremental as OI
+            OI.delta_columns_c0(int(z["n"]), z["s"], z["d"], int(z["i"]), int(z["j"]),
+                                z["cols"][arg:arg + 8], float(z["C"]), int(z["K"]),
+                                int(z["Kps"]))
+            return None
+        if kind == "gradient":
+            from oracle import adjoint as OA
+            OA.grad_weight_edges(int(z["n"]), z["s"], z["d"], z["w"], z["a"], z["b"], None,
+                                 float(z["C"]), [int(arg)], g_pairs=np.ones(len(z["a"])))
+            return None
+        if kind == "topk":
+            from oracle import serving as Sv
+            r = int(arg) % len(z["q"])
+            Sv.topk(z["rows"][r], int(z["q"][r]), int(z["k"]))
+            return None
+        if kind == "forest":
+            from oracle import tree as OT
+            OT.tree_seeded(int(z["n"]), z["s"], z["d"], float(z["C"]), int(z["K"]))
+            return None
+        if kind == "partitioned":
+            from oracle import partition as OP
+            lab = OP.bfs_partition(int(z["n"]), z["s"], z["d"], int(z["parts"]))
+            OP.partitioned(int(z["n"]), z["s"], z["d"], lab, float(z["C"]), int(z["K"]))
+            return None
+    raise ValueError(kind)
+
+
+class OraclePool:
+    """Worker processes for the oracle's all-core leg. They are spawned before the benchmark
+    touches the GPU; each task's inputs travel as an npz file that a worker loads once."""
+
+    def __init__(self, workers):
+        import multiprocessing as mp
+        import tempfile
+        self.workers = max(1, int(workers))
+        self.pool = mp.get_context("spawn").Pool(self.workers)
+        self.dir = tempfile.mkdtemp(prefix="oracle_")
+        self.files = 0
+
+    def stage(self, **arrays):
+        import numpy as np
+        path = os.path.join(self.dir, f"in{self.files}.npz")
+        self.files += 1
+        np.savez(path, **{k: np.asarray(v) for k, v in arrays.items()})
+        return path
+
+    def map(self, kind, path, args):
+        """Runs the tasks to completion (untimed) and returns their results in order."""
+        return self.pool.starmap(oracle_task, [(kind, path, a) for a in args])
+
+    def rate(self, kind, path, args, seconds):
+        """Runs tasks from `args` (cycled) on every worker until `seconds` have passed;
+        returns (tasks done, wall seconds). Loading the inputs is not timed."""
+        # every worker loads the inputs once, untimed
+        self.pool.starmap(oracle_task, [("warm", path, kind)] * self.workers, chunksize=1)
+        t0 = time.perf_counter()
+        pending, done, t = [], 0, 0
+        while True:
+            while len(pending) < 2 * self.workers and time.perf_counter() - t0 < seconds:
+                pending.append(self.pool.apply_async(oracle_task,
+                                                     (kind, path, args[t % len(args)])))
+                t += 1
+            if not pending:
+                break
+            pending.pop(0).get()
+            done += 1
+        return done, time.perf_counter() - t0
+
+    def close(self):
+        import shutil
+        self.pool.terminate()
+        self.pool.join()
+        shutil.rmtree(self.dir, ignore_errors=True)
 
 
 def graph_after(n, s, d, applied):
@@ -803,165 +1016,133 @@ def final_edges(s, d, stream):
             np.asarray([b for _, b in e], dtype=np.int64))
 
 
-def one_thread(fn):
-    """Runs a CPU-baseline leg with the BLAS and OpenMP pools held to one thread, so that the
-    `cores` it reports (1) is what it used."""
-    import functools
+def oracle_baseline(kind, path, args, seconds, units_per_task, unit, sample):
+    """The oracle timed on the host: an all-core leg (the worker pool, one thread each) and a
+    one-thread leg (this process), each on a bounded number of tasks. `value` is the all-core
+    rate; `cores` the worker count it used."""
+    p = ORACLE_POOL
+    t_all = 0.6 * seconds
+    done, dt = p.rate(kind, path, args, t_all)
+    from threadpoolctl import threadpool_limits
+    oracle_task("warm", path, kind)
+    t0 = time.perf_counter()
+    done1 = 0
+    with threadpool_limits(1):
+        while time.perf_counter() - t0 < 0.4 * seconds:
+            oracle_task(kind, path, args[done1 % len(args)])
+            done1 += 1
+    dt1 = time.perf_counter() - t0
+    return {"value": done * units_per_task / dt, "unit": unit, "cores": p.workers,
+            "kind": "oracle", "sample": f"{sample}; all-core: {done} tasks in {dt:.1f} s on "
+                                        f"{p.workers} worker processes (one thread each)",
+            "host": host_cpu(),
+            "one_thread": {"value": done1 * units_per_task / dt1, "tasks": done1,
+                           "seconds": round(dt1, 2)}}
 
-    @functools.wraps(fn)
-    def run(*a, **k):
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(1):
-            return fn(*a, **k)
-    return run
 
-
-@one_thread
-def cpu_baseline_columns(n, s, d, seconds, what):
+def cpu_baseline_columns(n, s, d, seconds, what, xs=None):
     """The oracle on the host: converged single-source columns S[:, x] of the updated graph
     (eq (17) by PartialSim to a tail <= 1e-13), i.e. pair values of the updated S computed
-    from scratch, timed on a bounded sample of columns."""
+    from scratch, timed on a bounded sample of columns (x uniform)."""
     import numpy as np
-
-    from oracle import graph as Gr
-    from oracle import simrank as O
-    Q = Gr.transition_matrix(n, s, d)
-    rng = np.random.default_rng(7)
-    t0 = time.perf_counter()
-    cols = 0
-    while time.perf_counter() - t0 < seconds:
-        O.single_source(Q, int(rng.integers(n)), C, tol=1e-13)
-        cols += 1
-    dt = time.perf_counter() - t0
-    return {"value": cols * n / dt, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cols} converged single-source columns S[:, x] (x uniform) of {what} "
-                      f"(n={n}), oracle PartialSim to a tail <= 1e-13, {dt:.1f} s on one host "
-                      f"thread (scipy sparse products are single-threaded)"}
+    path = ORACLE_POOL.stage(n=n, s=np.asarray(s, np.int64), d=np.asarray(d, np.int64), C=C)
+    xs = list(np.random.default_rng(7).integers(n, size=512)) if xs is None else xs
+    return oracle_baseline("columns", path, xs, seconds, float(n), "pair-updates/s",
+                           f"converged single-source columns S[:, x] (x uniform) of {what} "
+                           f"(n={n}), oracle PartialSim to a tail <= 1e-13")
 
 
-@one_thread
+def oracle_columns(n, s, d, xs):
+    """Converged single-source columns of the graph at the nodes xs (all-core, untimed)."""
+    import numpy as np
+    path = ORACLE_POOL.stage(n=n, s=np.asarray(s, np.int64), d=np.asarray(d, np.int64), C=C)
+    return np.stack(ORACLE_POOL.map("columns", path, [int(x) for x in xs]))
+
+
 def cpu_baseline_delta_columns(n, s, d, i, j, cols, K, Kps, seconds):
     """The oracle's column-by-column Delta S (same K and PartialSim depth) for the first
-    insertion, 8 columns per call until the time budget is used."""
+    insertion, 8 columns per task."""
     import numpy as np
-
-    from oracle import incremental as OI
-    t0 = time.perf_counter()
-    done = 0
-    while time.perf_counter() - t0 < seconds and done < len(cols):
-        OI.delta_columns_c0(n, s.astype(np.int64), d.astype(np.int64), i, j,
-                            cols[done:done + 8], C, K, Kps)
-        done += 8
-    dt = time.perf_counter() - t0
-    return {"value": float(n) * done / dt, "unit": "pair-values/s", "cores": 1,
-            "kind": "oracle", "sample": f"{done} Delta S columns of one insertion "
-                                        f"(8 per oracle call), {dt:.1f} s on one host thread"}
+    path = ORACLE_POOL.stage(n=n, s=np.asarray(s, np.int64), d=np.asarray(d, np.int64), i=i,
+                             j=j, cols=np.asarray(cols), C=C, K=K, Kps=Kps)
+    return oracle_baseline("delta_columns", path, list(range(0, len(cols) - 8, 8)), seconds,
+                           8.0 * n, "pair-values/s",
+                           "Delta S columns of one insertion, 8 per oracle call")
 
 
-@one_thread
 def cpu_baseline_columns_batch(n, s, d, batch, cols, K, Kps, seconds):
     """The oracle's block-by-block Delta S columns of one batch, run on consecutive 4-edge
     slices of the batch (each on the graph the earlier slices left) until the time budget is
-    used; the whole batch's time is extrapolated linearly in edges."""
+    used, in this process on one thread; the whole batch's time is extrapolated linearly in
+    edges. (The slices depend on each other, so there is no all-core leg.)"""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import incremental as OI
     bi, bj, bo = batch
     cur_s, cur_d = s.astype(np.int64), d.astype(np.int64)
     t0 = time.perf_counter()
     done = 0
-    while time.perf_counter() - t0 < seconds and done < len(bi):
-        sl = slice(done, min(done + 4, len(bi)))
-        OI.delta_columns_batch(n, cur_s, cur_d, bi[sl], bj[sl], bo[sl], cols, C, K, Kps)
-        ins, dels = bo[sl] > 0, bo[sl] < 0
-        drop = np.isin(cur_s * n + cur_d,
-                       bi[sl][dels].astype(np.int64) * n + bj[sl][dels].astype(np.int64))
-        cur_s = np.concatenate([cur_s[~drop], bi[sl][ins].astype(np.int64)])
-        cur_d = np.concatenate([cur_d[~drop], bj[sl][ins].astype(np.int64)])
-        done = sl.stop
+    with threadpool_limits(1):
+        while time.perf_counter() - t0 < seconds and done < len(bi):
+            sl = slice(done, min(done + 4, len(bi)))
+            OI.delta_columns_batch(n, cur_s, cur_d, bi[sl], bj[sl], bo[sl], cols, C, K, Kps)
+            ins, dels = bo[sl] > 0, bo[sl] < 0
+            drop = np.isin(cur_s * n + cur_d,
+                           bi[sl][dels].astype(np.int64) * n + bj[sl][dels].astype(np.int64))
+            cur_s = np.concatenate([cur_s[~drop], bi[sl][ins].astype(np.int64)])
+            cur_d = np.concatenate([cur_d[~drop], bj[sl][ins].astype(np.int64)])
+            done = sl.stop
     dt = time.perf_counter() - t0
     per_batch = dt * len(bi) / done
     return {"value": float(n) * len(cols) / per_batch, "unit": "pair-values/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"{done} of {len(bi)} edges of one batch in 4-edge slices, "
-                      f"{len(cols)} columns, {dt:.1f} s on one host thread; batch time "
-                      f"extrapolated linearly in edges"}
+                      f"{len(cols)} columns, {dt:.1f} s on one host thread (the slices depend "
+                      f"on each other); batch time extrapolated linearly in edges"}
 
 
-@one_thread
-def cpu_baseline_forest(K, n=900, m=9000):
+def cpu_baseline_forest(K, seconds, n=900, m=9000):
     """The oracle's whole forest-seeded pipeline (forest, closed form, Inc-bSR of the other
-    edges) on a smaller graph of the same generator and density, scaled to S entries/s; its
-    dense products are held to one BLAS thread."""
-    from threadpoolctl import threadpool_limits
-
+    edges) on a smaller graph of the same generator and density, scaled to S entries/s; the
+    all-core leg runs independent pipelines side by side."""
     import workloads as W
-    from oracle import tree as OT
     s, d = W.chung_lu(n, m, seed=1002)
-    t0 = time.perf_counter()
-    with threadpool_limits(1):
-        OT.tree_seeded(n, s.astype("int64"), d.astype("int64"), C, K)
-    dt = time.perf_counter() - t0
-    return {"value": float(n) * n / dt, "unit": "S entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole pipeline at n = {n}, m = {m} (same generator and density), "
-                      f"{dt:.1f} s on one host thread"}
+    path = ORACLE_POOL.stage(n=n, s=s.astype("int64"), d=d.astype("int64"), C=C, K=K)
+    return oracle_baseline("forest", path, [0], seconds, float(n) * n, "S entries/s",
+                           f"the whole pipeline at n = {n}, m = {m} (same generator and "
+                           f"density)")
 
 
-@one_thread
 def cpu_baseline_topk(rows, queries, k, seconds):
-    """The oracle's top-k selection on the same stored rows (copied to the host), cycling
-    through them until the time budget is used."""
-    from oracle import serving as Sv
-    t0 = time.perf_counter()
-    done = 0
-    while time.perf_counter() - t0 < seconds:
-        r = done % len(queries)
-        Sv.topk(rows[r], int(queries[r]), k)
-        done += 1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} selections over {len(queries)} stored rows of the same S, "
-                      f"{dt:.1f} s on one host thread"}
+    """The oracle's top-k selection on the same stored rows (copied to the host)."""
+    import numpy as np
+    path = ORACLE_POOL.stage(rows=rows, q=np.asarray(queries), k=k)
+    return oracle_baseline("topk", path, list(range(len(queries))), seconds, 1.0, "queries/s",
+                           f"selections over {len(queries)} stored rows of the same S")
 
 
-@one_thread
-def cpu_baseline_partitioned(K, parts, p_cross, n=1200, m=12000):
+def cpu_baseline_partitioned(K, parts, p_cross, seconds, n=1200, m=12000):
     """The oracle's whole partitioned pipeline (partition, block fixed points, Inc-bSR of the
     cross edges) on a smaller graph of the same generator and density, scaled to S
-    entries/s; its dense products are held to one BLAS thread."""
-    from threadpoolctl import threadpool_limits
-
+    entries/s; the all-core leg runs independent pipelines side by side."""
     import workloads as W
-    from oracle import partition as OP
     s, d, _ = W.communities(n, m, parts, p_cross, seed=1102)
-    t0 = time.perf_counter()
-    with threadpool_limits(1):
-        lab = OP.bfs_partition(n, s, d, parts)
-        OP.partitioned(n, s, d, lab, C, K)
-    dt = time.perf_counter() - t0
-    return {"value": float(n) * n / dt, "unit": "S entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole pipeline at n = {n}, m = {m} ({parts} planted communities, "
-                      f"same density), {dt:.1f} s on one host thread"}
+    path = ORACLE_POOL.stage(n=n, s=s, d=d, C=C, K=K, parts=parts)
+    return oracle_baseline("partitioned", path, [0], seconds, float(n) * n, "S entries/s",
+                           f"the whole pipeline at n = {n}, m = {m} ({parts} planted "
+                           f"communities, same density)")
 
 
-@one_thread
 def cpu_baseline_gradient(n, s, d, w, a, b, seconds):
     """The oracle's per-edge gradient (no dense matrices; upstream dL/dS = 1 at each pair),
-    timed on a bounded number of edges, scaled to edges/s."""
+    one edge per task, scaled to edges/s."""
     import numpy as np
-
-    from oracle import adjoint as OA
-    t0 = time.perf_counter()
-    done = 0
-    g = np.ones(len(a))
-    while time.perf_counter() - t0 < seconds:
-        OA.grad_weight_edges(n, s.astype(np.int64), d.astype(np.int64), w, a, b, None, C,
-                             [done], g_pairs=g)
-        done += 1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "edge-gradients/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} edge-weight gradients by the oracle's per-edge adjoint form, "
-                      f"{dt:.1f} s on one host thread"}
+    path = ORACLE_POOL.stage(n=n, s=np.asarray(s, np.int64), d=np.asarray(d, np.int64), w=w,
+                             a=a, b=b, C=C)
+    return oracle_baseline("gradient", path, list(range(len(s))), seconds, 1.0,
+                           "edge-gradients/s",
+                           "edge-weight gradients by the oracle's per-edge adjoint form")
 
 
 if __name__ == "__main__":
