@@ -172,9 +172,12 @@ sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int
 
 /* Applies one edge update, op = +1 insert or -1 delete (Algorithms 1 and 2, Theorem 9;
  * node insertions: Algorithms 3, 4, 5 with the new ids i == n (C2), j == n (C1), or
- * i == n, j == n + 1 (C3)). Dense mode updates S; column mode keeps the series vectors of
- * this update for query_columns / query_column(SR_COL_DELTA) and supports insertions
- * between existing nodes only. stats: NULL, or filled after synchronising. */
+ * i == n, j == n + 1 (C3)). Dense mode updates S. Column mode (Algorithm 7) stores no S: it
+ * computes the columns the update needs by PartialSim on the current graph (S[:, i] and
+ * S[:, j] for C0, S[:, i] for C1, S[:, j] for C2) and keeps this update's Delta S in factored
+ * form for query_columns / query_column(SR_COL_DELTA): the series panel (C0, C2), the new
+ * sink's column (C1), the new diagonals (C3). Deletions are between existing nodes (C0).
+ * stats: NULL, or filled after synchronising. */
 sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
                             sr_update_stats* stats);
 
@@ -207,12 +210,16 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* src,
 
 /* Writes column x as n float64 values to out_dev (device). what = SR_COL_S: the current
  * S[:, x] (dense mode). what = SR_COL_DELTA: Delta S[:, x] of the last apply_edge_update
- * (both modes; eq (71): M_K[:, x] + M_K[x, :]^T). */
+ * (both modes): eq (71), M_K[:, x] + M_K[x, :]^T, for C0 and C2 (with the new source's own
+ * column (1 - C) e_i), the new sink's column and border entry for C1 (Theorem 8), the new
+ * diagonals for C3; n is the node count after the update and a new node's old column counts
+ * as zero. SR_EMODE when the last call was not a unit update. */
 sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev);
 
 /* Writes ncols columns as float32 to out_dev (device), column c at out_dev + c * ld_out,
  * ld_out >= n. cols: host array of node ids. Column mode: Delta S[:, cols] of the last
- * apply_edge_update, by eq (71) for all columns at once. Dense mode: S[:, cols]. */
+ * apply_edge_update, as query_column(SR_COL_DELTA) (eq (71) for all columns at once in the
+ * low-rank cases). Dense mode: S[:, cols]. */
 sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* out_dev,
                         int64_t ld_out);
 

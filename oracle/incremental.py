@@ -648,12 +648,15 @@ def delta_columns_batch(n, src, dst, bi, bj, bop, cols, C, K, K_ps):
     return out
 
 
-def inc_sr_all_p_column(n, src, dst, S_col_x, x, edges, C, K):
+def inc_sr_all_p_column(n, src, dst, S_col_x, x, edges, C, K, K_ps=None):
     """Algorithm 7 (Inc-SR-All-P) for one column x over a sequence of insertions ``edges``
-    (each ``(i, j)``; new nodes take the next ids), with PartialSim at depth K as printed.
+    (each ``(i, j)``; new nodes take the next ids), with PartialSim at depth K as printed
+    (``K_ps`` sets another PartialSim depth; the series keeps depth K).
 
-    Returns the new column (length = final node count)."""
+    Returns the new column (length = final node count). With ``S_col_x`` zero it returns
+    the column of Delta S (the new nodes' entries included)."""
     from .simrank import partial_sim
+    Kp = K if K_ps is None else K_ps
     col = np.array(S_col_x, dtype=np.float64, copy=True)
     s = list(np.asarray(src).tolist())
     t = list(np.asarray(dst).tolist())
@@ -663,8 +666,8 @@ def inc_sr_all_p_column(n, src, dst, S_col_x, x, edges, C, K):
         d = in_degrees(cur_n, s, t)
         i_in, j_in = i < cur_n, j < cur_n
         if i_in and j_in:                                   # case C0
-            Si = partial_sim(Q, i, K, C)
-            Sj = partial_sim(Q, j, K, C)
+            Si = partial_sim(Q, i, Kp, C)
+            Sj = partial_sim(Q, j, Kp, C)
             w = Q @ Si
             lam = Si[i] + Sj[j] / C - 2.0 * w[j] - 1.0 / C + 1.0
             ej = np.zeros(cur_n)
@@ -691,7 +694,7 @@ def inc_sr_all_p_column(n, src, dst, S_col_x, x, edges, C, K):
                 nn = xi[x] * eta + nn
             col = col + m + nn
         elif i_in and not j_in:                             # case C1
-            Si = partial_sim(Q, i, K, C)
+            Si = partial_sim(Q, i, Kp, C)
             y = C * (Q @ Si)
             if x == j:
                 col = np.concatenate([y, [C * Si[i] + 1.0 - C]])
@@ -702,7 +705,7 @@ def inc_sr_all_p_column(n, src, dst, S_col_x, x, edges, C, K):
             if x == i:
                 col = np.concatenate([np.zeros(cur_n), [1.0 - C]])
             else:
-                Sj = partial_sim(Q, j, K, C)
+                Sj = partial_sim(Q, j, Kp, C)
                 ej = np.zeros(cur_n)
                 ej[j] = 1.0
                 z = ((Sj[j] - (1.0 - C) ** 2) / (2.0 * C * (d[j] + 1)) + (1.0 - C) / C) * ej \

@@ -87,6 +87,12 @@ struct sr_ctx {
   unsigned long long* h_max = nullptr;
 
   int last_r = 0;          // panel columns of the last unit update (0: none)
+  // The last unit update, for its Delta S columns: case (-1 none), its new nodes' ids and
+  // diagonals, and for C1 the new sink's column (ylast, its diagonal at j).
+  int last_case = -1;
+  int32_t last_i = -1, last_j = -1;
+  double last_vi = 0.0, last_vj = 0.0;
+  double* ylast = nullptr;
   bool last_aff = false;   // AFF bitmaps hold the last update
   std::vector<int32_t> last_plan;
 
@@ -647,10 +653,12 @@ sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_
   if (ft && !ft->incremental && ft->r_prev > 0)
     HC(launch_panel_correct(ft->P, ft->pld, ft->gstride, ft->r_prev, n_work, il, -1, ctx->wts, ctx->SI,
                             nullptr, s));
-  HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n_work, ctx->SI, ctx->ytmp,
+  // y = (C / delta) Q S[:, I] and the corner into ylast (kept as the update's Delta S column)
+  HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n_work, ctx->SI, ctx->ylast,
                    C / (double)I.size(), s));
   if (il.dev) HC(launch_sum_at(ctx->SI, il, ctx->d_sum, s));
-  HC(launch_c1_border(ctx->S, n_work, j, ctx->ytmp, ctx->SI, il, C, s,
+  HC(launch_c1_corner(ctx->ylast, j, ctx->SI, il, C, s, il.dev ? ctx->d_sum : nullptr));
+  HC(launch_c1_border(ctx->S, n_work, j, ctx->ylast, ctx->SI, il, C, s,
                       il.dev ? ctx->d_sum : nullptr));
   std::vector<std::pair<int32_t, int32_t>> e;
   for (int32_t i : I) e.push_back({i, j});
@@ -833,7 +841,7 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)hipFree(ctx->d_W);
   (void)hipFree(ctx->S_mem[0]);
   (void)hipFree(ctx->S_mem[1]);
-  double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp,
+  double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp, ctx->ylast,
                   ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd, ctx->corr,
                   ctx->corr_w};
   for (double* p : dd) (void)hipFree(p);
@@ -978,6 +986,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   IC(dalloc(&ctx->Qz, node_cap));
   IC(dalloc(&ctx->zsum, node_cap));
   IC(dalloc(&ctx->ytmp, node_cap));
+  IC(dalloc(&ctx->ylast, node_cap));
   ctx->p_rows = (node_cap + 127) / 128 * 128;
   IC(dalloc(&ctx->P, ctx->p_rows * ctx->pld));
   IC(dalloc(&ctx->pairs, 4 * node_cap));
@@ -1399,48 +1408,93 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
   if (op > 0 && ctx->g.m + 1 > ctx->edge_cap) return SR_ECAPACITY;
   if (op > 0 && !graph_fits(ctx, {{i, j}})) return SR_ECAPACITY;
 
+  ctx->last_case = -1;
+  ctx->last_r = 0;
   if (ctx->cfg.mode == SR_COLUMN) {
-    if (case_id != 0 || op < 0) return SR_EMODE;
-    // Algorithm 7, case C0: old columns by PartialSim, gamma, series on the new graph.
+    // Algorithm 7 (column method): S is not stored; the old columns an update needs come
+    // from PartialSim on the current graph, and the update's Delta S columns are kept in
+    // factored form for query_columns / query_column(SR_COL_DELTA).
+    hipStream_t s = ctx->stream;
+    const double C = ctx->cfg.C;
+    const int K = ctx->cfg.K;
     IdList li, lj;
     li.count = lj.count = 1;
     li.id[0] = i;
     lj.id[0] = j;
-    sr_status r = partial_sim2(ctx, li, lj, ctx->SI, ctx->Sj);
-    if (r != SR_OK) return r;
-    hipStream_t s = ctx->stream;
-    const double C = ctx->cfg.C;
-    HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->QSI, 1.0, s));
-    GammaArgs ga{};
-    ga.kind = 0;
-    ga.op = 1;
-    ga.j = j;
-    ga.delta = 1;
-    ga.dj = ctx->g.in.len[j];
-    ga.C = C;
-    ga.xi0 = C;
-    ga.I.count = 1;
-    ga.I.id[0] = i;
-    if (stats) HC(hipMemsetAsync(ctx->d_max, 0, 8, s));
-    HC(launch_gamma(ga, n, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, ctx->P, ctx->pld,
-                    stats ? ctx->d_max : nullptr, s));
-    r = edit_graph(ctx, {{i, j}}, +1);
-    if (r != SR_OK) return r;
-    for (int k = 0; k < ctx->cfg.K; ++k)
-      HC(launch_series_step(devq(ctx), heavy_args(ctx->hin), n, ctx->P, ctx->pld, k, C, 1.0,
-                            nullptr, s, ctx->pairs, ctx->node_cap));
-    ctx->last_r = 2 * (ctx->cfg.K + 1);
     if (stats) {
-      HC(hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost, s));
-      HC(hipStreamSynchronize(s));
-      double gmax;
-      memcpy(&gmax, ctx->h_max, 8);
       memset(stats, 0, sizeof(*stats));
-      stats->case_id = 0;
-      stats->op = 1;
-      stats->d_j = ga.dj;
-      stats->n_after = n;
-      stats->bound = 2.0 * pow(C, ctx->cfg.K + 2) / (1.0 - C) * gmax;
+      HC(hipMemsetAsync(ctx->d_max, 0, 8, s));
+    }
+    const int64_t dj = ctx->g.in.len[j < n ? j : 0] * (j < n ? 1 : 0);
+    double xi0 = C;
+    sr_status r = SR_OK;
+    if (case_id == 0 || case_id == 2) {
+      GammaArgs ga{};
+      ga.op = op;
+      ga.j = j;
+      ga.delta = 1;
+      ga.dj = dj;
+      ga.C = C;
+      if (case_id == 0) {
+        // Table 2 row C0 (Theorem 3 insertion, Theorem 9 deletion): S[:, i], S[:, j]
+        r = partial_sim2(ctx, li, lj, ctx->SI, ctx->Sj);
+        if (r != SR_OK) return r;
+        HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->QSI, 1.0, s));
+        ga.kind = 0;
+        ga.I = li;
+      } else {
+        // C2: the new source joins as an isolated node, then Table 2 row C2 (eq (60)) on
+        // the grown graph; S[:, j] on it is zero at the new node
+        ctx->g.n = n_new;
+        r = partial_sim(ctx, lj, ctx->Sj);
+        if (r != SR_OK) return r;
+        ga.kind = 2;
+        xi0 = C / (double)(dj + 1);
+      }
+      ga.xi0 = xi0;
+      HC(launch_gamma(ga, n_new, ctx->SI, ctx->Sj, ctx->QSI, nullptr, nullptr, ctx->P, ctx->pld,
+                      stats ? ctx->d_max : nullptr, s));
+      r = edit_graph(ctx, {{i, j}}, op);
+      if (r != SR_OK) return r;
+      for (int k = 0; k < K; ++k)
+        HC(launch_series_step(devq(ctx), heavy_args(ctx->hin), n_new, ctx->P, ctx->pld, k, C,
+                              1.0, nullptr, s, ctx->pairs, ctx->node_cap));
+      ctx->last_r = 2 * (K + 1);
+    } else if (case_id == 1) {
+      // Theorem 8 / Table 2 row C1: the new sink's column y = C Q S[:, i] on the old graph,
+      // its diagonal C S_ii + 1 - C; every other column only gains its entry y[x] at j
+      r = partial_sim(ctx, li, ctx->SI);
+      if (r != SR_OK) return r;
+      HC(launch_spmv_q(devq(ctx), heavy_args(ctx->hin), n, ctx->SI, ctx->ylast, C, s));
+      HC(launch_c1_corner(ctx->ylast, j, ctx->SI, li, C, s));
+      ctx->g.n = n_new;
+      r = edit_graph(ctx, {{i, j}}, +1);
+      if (r != SR_OK) return r;
+    } else {
+      // Algorithm 5 / Table 2 row C3 with one source: two new nodes, diagonals only
+      ctx->g.n = n_new;
+      r = edit_graph(ctx, {{i, j}}, +1);
+      if (r != SR_OK) return r;
+    }
+    ctx->last_case = case_id;
+    ctx->last_i = i;
+    ctx->last_j = j;
+    ctx->last_vi = 1.0 - C;
+    ctx->last_vj = (1.0 - C) * (1.0 + C);
+    if (stats) {
+      stats->case_id = case_id;
+      stats->op = op;
+      stats->d_j = dj;
+      stats->n_after = n_new;
+      if (case_id == 0 || case_id == 2) {
+        HC(hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        double gmax;
+        memcpy(&gmax, ctx->h_max, 8);
+        stats->bound = 2.0 * xi0 * pow(C, K + 1) / (1.0 - C) * gmax;
+      } else {
+        HC(hipStreamSynchronize(s));
+      }
     }
     return SR_OK;
   }
@@ -1464,6 +1518,11 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
     ctx->last_r = 0;
   }
   if (r != SR_OK) return r;
+  ctx->last_case = case_id;
+  ctx->last_i = i;
+  ctx->last_j = j;
+  ctx->last_vi = 1.0 - C;
+  ctx->last_vj = (1.0 - C) * (1.0 + C);
   if (stats) {
     stats->case_id = case_id;
     stats->op = op;
@@ -1780,6 +1839,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   r = flush();
   if (r != SR_OK) return r;
   ctx->last_r = 0;
+  ctx->last_case = -1;
   if (stats) {
     HC(hipStreamSynchronize(ctx->stream));
     memset(stats, 0, sizeof(*stats));
@@ -1927,6 +1987,7 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
   r = flush();
   if (r != SR_OK) return r;
   ctx->last_r = 0;  // the single-update series state no longer describes the graph
+  ctx->last_case = -1;
   if (stats) {
     HC(hipStreamSynchronize(s));
     memset(stats, 0, sizeof(*stats));
@@ -1951,6 +2012,43 @@ sr_status sr_last_plan(sr_ctx* ctx, int32_t* out, int64_t cap, int64_t* len) {
 
 // ------------------------------------------------------------------------------ queries
 
+// Delta S columns of the last unit update (eq (71) for the low-rank cases C0 and C2; the new
+// sink's column for C1; the new diagonals for C3): the list rows (device, ncols) or the single
+// column x, as float32 (out32) or float64 (out64) rows of ld values.
+static sr_status delta_columns(sr_ctx* ctx, const int32_t* rows, int32_t x, int32_t ncols,
+                               float* out32, double* out64, int64_t ld) {
+  const int64_t n = ctx->g.n;
+  hipStream_t s = ctx->stream;
+  const int c = ctx->last_case;
+  if (c < 0) return SR_EMODE;
+  if (c == 0 || c == 2) {
+    if (ctx->last_r == 0) return SR_EMODE;
+    if (out64) {
+      HC(launch_delta_col(ctx->P, ctx->pld, ctx->last_r, n, x, out64, s));
+    } else {
+      LowRankArgs la{};
+      la.P = ctx->P;
+      la.pld = ctx->pld;
+      la.gstride = ctx->p_rows * ctx->pld;
+      la.p_rows = ctx->p_rows;
+      la.r = ctx->last_r;
+      la.rows = rows;
+      la.nrows = ncols;
+      la.ncols = n;
+      la.out = out32;
+      la.ld_out = ld;
+      HC(run_lowrank(ctx, la));
+    }
+    if (c == 2)  // the new source's own column
+      HC(launch_node_cols(rows, x, ncols, n, 2, ctx->last_i, ctx->last_j, nullptr, ctx->last_vi,
+                          0.0, out32, out64, ld, s));
+    return SR_OK;
+  }
+  HC(launch_node_cols(rows, x, ncols, n, c, ctx->last_i, ctx->last_j, ctx->ylast, ctx->last_vi,
+                      ctx->last_vj, out32, out64, ld, s));
+  return SR_OK;
+}
+
 sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev) {
   if (!valid_ctx(ctx) || !out_dev) return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
@@ -1962,9 +2060,7 @@ sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev) {
     return SR_OK;
   }
   if (what != SR_COL_DELTA) return SR_EINVAL;
-  if (ctx->last_r == 0) return SR_EMODE;
-  HC(launch_delta_col(ctx->P, ctx->pld, ctx->last_r, n, x, out_dev, ctx->stream));
-  return SR_OK;
+  return delta_columns(ctx, nullptr, x, 1, nullptr, out_dev, n);
 }
 
 sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* out_dev,
@@ -1990,20 +2086,7 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
     HC(launch_rows_to_f32(ctx->S, n, ctx->d_ids, ncols, out_dev, ld_out, ctx->stream));
     return SR_OK;
   }
-  if (ctx->last_r == 0) return SR_EMODE;
-  LowRankArgs la{};
-  la.P = ctx->P;
-  la.pld = ctx->pld;
-  la.gstride = ctx->p_rows * ctx->pld;
-  la.p_rows = ctx->p_rows;
-  la.r = ctx->last_r;
-  la.rows = ctx->d_ids;
-  la.nrows = ncols;
-  la.ncols = n;
-  la.out = out_dev;
-  la.ld_out = ld_out;
-  HC(run_lowrank(ctx, la));
-  return SR_OK;
+  return delta_columns(ctx, ctx->d_ids, -1, ncols, out_dev, nullptr, ld_out);
 }
 
 sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,

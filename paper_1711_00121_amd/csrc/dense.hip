@@ -359,6 +359,58 @@ __global__ __launch_bounds__(kB) void ids_range_kernel(const int32_t* __restrict
   }
 }
 
+// Delta S columns of a node insertion without a low-rank part (column method, Algorithm 7 with
+// Theorem 8 / Table 2 rows C1 and C3). Column x = rows[t] (or x when rows is null), nodes
+// a < n:
+//   kind 1 (C1, new sink j): y holds the new column of j (y[j] its diagonal), so
+//          value = x == j ? y[a] : (a == j ? y[x] : 0)
+//   kind 3 (C3, new nodes i and j): value = a == x ? (x == i ? vi : (x == j ? vj : 0)) : 0
+// written as float32 (out32, row t at out32 + t ld) or float64 (out64).
+__global__ __launch_bounds__(kB) void node_cols_kernel(const int32_t* __restrict__ rows,
+                                                       int32_t x0, int64_t nrows, int64_t n,
+                                                       int kind,
+                                                       int32_t i, int32_t j,
+                                                       const double* __restrict__ y, double vi,
+                                                       double vj, float* out32, double* out64,
+                                                       int64_t ld) {
+  const int64_t a = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (a >= n) return;
+  for (int64_t t = blockIdx.y; t < nrows; t += gridDim.y) {
+    const int32_t x = rows ? rows[t] : x0;
+    double v = 0.0;
+    if (kind == 1) {
+      v = (x == j) ? y[a] : (a == j ? y[x] : 0.0);
+    } else if (a == x) {
+      v = x == i ? vi : (x == j ? vj : 0.0);
+    }
+    if (out32)
+      out32[t * ld + a] = (float)v;
+    else
+      out64[t * ld + a] = v;
+  }
+}
+
+// Case C2 after the panel product: the new source i is isolated apart from its out-edge, so
+// its own column is vi e_i, which the panel (zero at row i) leaves out.
+__global__ void node_fix_kernel(const int32_t* __restrict__ rows, int32_t x0, int32_t nrows,
+                                int32_t i, double vi, float* out32, double* out64, int64_t ld) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const int32_t x = rows ? rows[t] : x0;
+  if (x != i) return;
+  if (out32)
+    out32[(int64_t)t * ld + i] = (float)vi;
+  else
+    out64[(int64_t)t * ld + i] = vi;
+}
+
+// y[j] = C / delta^2 S_II + 1 - C: the new sink's diagonal (Theorem 8, Table 2 row C1).
+__global__ void c1_corner_kernel(double* y, int32_t j, const double* __restrict__ SI, IdList I,
+                                 double C, const double* sumI) {
+  const double d = (double)I.count;
+  y[j] = C / (d * d) * (sumI ? *sumI : sum_at(SI, I)) + 1.0 - C;
+}
+
 // Long id lists: after a zero fill, one thread per listed id sets its entry (the ids of a
 // list are distinct). x has stride `stride` doubles per node and offset `half`; xd (optional)
 // receives the entry divided by the node's row weight of Q (0 where that is 0).
@@ -490,6 +542,27 @@ hipError_t launch_ids_range(const int32_t* a, const int32_t* b, int64_t np, int3
   if (e != hipSuccess || np <= 0) return e;
   const int64_t blocks = std::min<int64_t>((np + kB - 1) / kB, 1024);
   ids_range_kernel<<<(unsigned)blocks, kB, 0, s>>>(a, b, np, mm);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_cols(const int32_t* rows, int32_t x, int32_t nrows, int64_t n, int kind,
+                            int32_t i, int32_t j, const double* y, double vi, double vj,
+                            float* out32, double* out64, int64_t ld, hipStream_t s) {
+  if (nrows <= 0 || n <= 0) return hipSuccess;
+  if (kind == 2) {
+    node_fix_kernel<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(rows, x, nrows, i, vi, out32,
+                                                                    out64, ld);
+  } else {
+    const unsigned gy = (unsigned)std::min<int64_t>(nrows, 65535);
+    node_cols_kernel<<<dim3(g1(n), gy), kB, 0, s>>>(rows, x, nrows, n, kind, i, j, y, vi, vj,
+                                                    out32, out64, ld);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_c1_corner(double* y, int32_t j, const double* SI, const IdList& I, double C,
+                            hipStream_t s, const double* sumI) {
+  c1_corner_kernel<<<1, 1, 0, s>>>(y, j, SI, I, C, sumI);
   return hipGetLastError();
 }
 

@@ -157,6 +157,16 @@ hipError_t launch_direct_z(const GammaArgs& g, int64_t n, const double* SI,
 hipError_t launch_c1_border(SView S, int64_t n_old, int32_t j, const double* y,
                             const double* SI, const IdList& I, double C, hipStream_t s,
                             const double* sumI = nullptr);
+// y[j] = (C / delta^2) S_II + 1 - C (S_II from SI at the sources, or *sumI when set).
+hipError_t launch_c1_corner(double* y, int32_t j, const double* SI, const IdList& I, double C,
+                            hipStream_t s, const double* sumI = nullptr);
+// Delta S columns of the last node insertion in column mode, for the list rows (device, nrows
+// columns; or the single column x when rows is null): kind 1 (C1) from the new sink's column y,
+// kind 3 (C3) from the new diagonals vi, vj, kind 2 (C2) only sets entry i of column i to vi
+// (after the panel product). Output float32 (out32) or float64 (out64), row t at t * ld.
+hipError_t launch_node_cols(const int32_t* rows, int32_t x, int32_t nrows, int64_t n, int kind,
+                            int32_t i, int32_t j, const double* y, double vi, double vj,
+                            float* out32, double* out64, int64_t ld, hipStream_t s);
 // Writes S[id][id] = val[t] for a short list (new-node diagonals).
 struct DiagList {
   static constexpr int MAX = 30;

@@ -205,7 +205,7 @@ def test_fullsize_columns_n1m():
     ii, jj = W.insertion_stream(n, s, d, 1, seed=2004)
     i, j = int(ii[0]), int(jj[0])
     block = W.column_sample(n, cfg["block"] - 2, seed=3004, extra=[i, j])[:cfg["block"]]
-    ctx = _ctx(n, s, d, C=C, K=K, K_ps=Kps, mode="column")
+    ctx = _ctx(n, s, d, C=C, K=K, K_ps=Kps, mode="column", node_cap=n + 1)
     ctx.apply_edge_update(i, j, 1)
     out = ctx.query_columns(block)
     torch.cuda.synchronize()
@@ -223,6 +223,17 @@ def test_fullsize_columns_n1m():
     # (half an ulp: 2^-24 relative)
     assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) * 1.01 + 1e-13)
     assert err < 1e-6
+    # then a new source into the same sink (case C2, Algorithm 7 on the grown graph)
+    ctx.apply_edge_update(n, j, 1)
+    s1 = np.concatenate([s, [i]]).astype(np.int64)
+    d1 = np.concatenate([d, [j]]).astype(np.int64)
+    xs = [j, n, i, int(W.rng(6005).integers(n))]
+    got = np.stack([ctx.query_column(x, what="delta").cpu().numpy() for x in xs], 1)
+    ref = np.stack([OI.inc_sr_all_p_column(n, s1, d1, np.zeros(n), x, [(n, j)], C, K,
+                                           K_ps=Kps) for x in xs], 1)
+    err = maxabs(got, ref)
+    _say(f"C2 at n={n}: max |dS_gpu - dS_oracle| over {len(xs)} columns = {err:.3e}")
+    assert got.shape == (n + 1, len(xs)) and err < 1e-12
     ctx.close()
 
 

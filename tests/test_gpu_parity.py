@@ -220,6 +220,60 @@ def test_batches_match_oracle_plan_and_recompute():
         assert maxabs(ctx.S().cpu().numpy(), tr.exact(C)) < TOL
 
 
+def _pad(v, n):
+    return np.concatenate([v, np.zeros(n - len(v))])
+
+
+def test_column_mode_all_cases():
+    """Algorithm 7 in column mode for every case of a unit update: an insertion between
+    existing nodes (C0), into a new sink (C1), from a new source (C2), between two new nodes
+    (C3), and a deletion (Theorem 9). The Delta S columns (float64 single columns and the
+    float32 list) match the oracle's column method at the same K and PartialSim depth, and
+    with a deep PartialSim the converged recompute's change of S (1e-6); the new nodes' own
+    columns included."""
+    n, K = 1500, 10
+    s, d = W.chung_lu(n, 9000, seed=991)
+    es = set(zip(s.tolist(), d.tolist()))
+    i0, j0 = next((a, b) for a in range(3, n) for b in range(7, n)
+                  if a != b and (a, b) not in es)
+    dele = sorted(es)[17]
+    seq = [(i0, j0, 1), (5, n, 1), (n + 1, 9, 1), (n + 2, n + 3, 1), (dele[0], dele[1], -1)]
+    lit = ctx_for(n, s, d, mode="column", K=K, K_ps=K, node_cap=n + 8)
+    deep = ctx_for(n, s, d, mode="column", K=K, K_ps=40, node_cap=n + 8)
+    cur_n = n
+    cur_s, cur_d = s.astype(np.int64), d.astype(np.int64)
+    for (i, j, op) in seq:
+        st = lit.apply_edge_update(i, j, op, stats=True)
+        deep.apply_edge_update(i, j, op)
+        n2, s2, d2 = Gr.apply_edges(cur_n, cur_s, cur_d, [i], [j], [op])
+        assert lit.sizes()[0] == n2 and st["n_after"] == n2
+        cols = np.unique(np.concatenate([W.column_sample(cur_n, 24, seed=992 + i),
+                                         [i, j, 0, n2 - 1]])).astype(np.int32)
+        cols = cols[cols < n2]
+        # oracle, K-matched: Algorithm 7 (insertions) or the block column method (deletion)
+        if op > 0:
+            ref = np.stack([OI.inc_sr_all_p_column(cur_n, cur_s, cur_d, np.zeros(cur_n), int(x),
+                                                   [(i, j)], C, K) for x in cols], 1)
+        else:
+            ref = OI.delta_columns_batch(cur_n, cur_s, cur_d, [i], [j], [-1], cols, C, K, K)
+        got64 = np.stack([lit.query_column(int(x), what="delta").cpu().numpy() for x in cols], 1)
+        got32 = lit.query_columns(cols).double().cpu().numpy().T
+        assert got64.shape == ref.shape == (n2, len(cols))
+        assert maxabs(got64, ref) < 1e-12, (i, j, op)
+        assert maxabs(got32, ref) < 1e-7, (i, j, op)
+        # converged: the change of S* (new nodes' old columns are zero)
+        Qo = Gr.transition_matrix(cur_n, cur_s, cur_d)
+        Qn = Gr.transition_matrix(n2, s2, d2)
+        exact = np.stack([O.single_source(Qn, int(x), C) -
+                          (_pad(O.single_source(Qo, int(x), C), n2) if x < cur_n else 0.0)
+                          for x in cols], 1)
+        gd = np.stack([deep.query_column(int(x), what="delta").cpu().numpy() for x in cols], 1)
+        assert maxabs(gd, exact) < TOL, (i, j, op, maxabs(gd, exact))
+        cur_n, cur_s, cur_d = n2, s2.astype(np.int64), d2.astype(np.int64)
+    lit.close()
+    deep.close()
+
+
 def long_block_batches(n, s, d):
     """Three batches whose similar-sink blocks have more than 60 sources each: 130 existing
     sources into an existing sink (C0), 70 existing sources into a new sink (C1), 65 new
