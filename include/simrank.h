@@ -122,9 +122,10 @@ typedef struct sr_batch_stats {
 sr_status sr_default_config(sr_config* cfg);
 
 /* Creates a context for the digraph with n nodes and m edges src[e] -> dst[e] (host arrays,
- * no self-loops, no duplicates). weight: host float64 per edge, or NULL for an unweighted
- * graph (a weighted graph supports init, queries and backward; incremental updates of a
- * weighted graph return SR_EMODE). S0: NULL to compute the initial S on the device by the
+ * no self-loops, no duplicates). weight: host float64 per edge (> 0), or NULL for an
+ * unweighted graph; Q is row-normalised, Q[x][y] = w(y -> x) / W_x. A weighted graph
+ * supports unit updates in dense mode (apply_edge_update, apply_weight_update), queries and
+ * backward; its batches and column-mode updates return SR_EMODE. S0: NULL to compute the initial S on the device by the
  * fixed-point iteration of eq (03a) until the max-abs step is <= cfg->init_tol; otherwise a
  * device pointer to an n x n float64 row-major S (leading dimension n), which is copied.
  * In column mode S is never stored and S0 must be NULL. hip_stream: a hipStream_t (NULL for
@@ -180,6 +181,20 @@ sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int
  * stats: NULL, or filled after synchronising. */
 sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
                             sr_update_stats* stats);
+
+/* Weighted graphs: sets the weight of edge i -> j to w >= 0, as one rank-one update of the
+ * row-normalised Q, the weighted analogue of Theorems 1 and 9 (Delta Q = e_j a (e_i -
+ * Q[j, :])^T with a = dw / (W_j + dw), dw the weight change, W_j j's in-weight sum; the
+ * forms of an empty row before or after are the unweighted ones), solved like
+ * apply_edge_update with Theorem 3's closed form in a (it rests only on the fixed-point
+ * identity of eq (33)). w > 0 on a missing edge inserts it (new nodes as apply_edge_update:
+ * j == n, i == n, or i == n and j == n + 1), w == 0 deletes an existing edge, any other w
+ * changes its weight; w equal to the current weight changes nothing. apply_edge_update on
+ * a weighted graph inserts with weight 1. SR_EMODE for an unweighted context or in column
+ * mode, SR_EINVAL for a negative or non-finite w, SR_ENOENT for w == 0 on a missing edge;
+ * otherwise as apply_edge_update. stats: NULL, or filled after synchronising. */
+sr_status apply_weight_update(sr_ctx* ctx, int32_t i, int32_t j, double w,
+                              sr_update_stats* stats);
 
 /* Applies a batch of cnt edge updates (host arrays; op[e] = +1 or -1) by Algorithm 6:
  * cancellation of insert/delete pairs, similar-sink partition, deletion blocks, then
@@ -251,13 +266,15 @@ sr_status query_topk_noalloc(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t 
 sr_status sr_gather_pairs(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev,
                           const int32_t* b_dev, double* out_dev);
 
-/* Reverse-mode derivative of a loss L(S) with respect to the edge weights of the initial
- * graph (weighted or unweighted; an unweighted graph has all weights 1). Inputs: npairs
- * pairs (a_dev[p], b_dev[p]) with dL/dS[a,b] = g_dev[p] (all device arrays). Solves the
- * transposed Sylvester equation Lam = G + C Q^T Lam Q to the init tolerance and writes
- * dL/dw for every edge, in the order of init_simrank's edge arrays, to dL_dw_dev (device,
- * m float64). Requires a dense-mode context whose graph has not been updated since init
- * (SR_EMODE otherwise). Allocates three n x n float64 work matrices for the call. */
+/* Reverse-mode derivative of a loss L(S) with respect to the edge weights of the current
+ * graph (weighted or unweighted; an unweighted graph has all weights 1), using the stored S
+ * (after updates: the incrementally maintained one). Inputs: npairs pairs
+ * (a_dev[p], b_dev[p]) with dL/dS[a,b] = g_dev[p] (all device arrays; ids outside [0, n) are
+ * SR_ERANGE before any launch, which synchronises the stream). Solves the transposed
+ * Sylvester equation Lam = G + C Q^T Lam Q to the init tolerance and writes dL/dw for every
+ * current edge to dL_dw_dev (device, m float64, m the current edge count) in the order of
+ * sr_edges: init_simrank's edge order until the first update, sinks ascending after it.
+ * Dense mode (SR_EMODE otherwise). Allocates four n x n float64 work matrices for the call. */
 sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int32_t* b_dev,
                    const double* g_dev, double* dL_dw_dev);
 
@@ -271,6 +288,13 @@ sr_status sr_get_aff(sr_ctx* ctx, int32_t level, int32_t* A_dev, int64_t* nA, in
 /* Copies S[0:n, 0:n] as float64 into out_dev (device) with leading dimension ld >= n.
  * Dense mode. */
 sr_status sr_copy_S(sr_ctx* ctx, double* out_dev, int64_t ld);
+
+/* The current edges: src[e] -> dst[e] with weight w[e] (1 for an unweighted graph), host
+ * arrays of capacity cap (any may be NULL), in the order backward reports dL/dw: the edge
+ * arrays given to init_simrank until the first update, then by sink ascending (slot order
+ * within a sink). *m receives the edge count; nothing is written when cap < *m. */
+sr_status sr_edges(sr_ctx* ctx, int32_t* src, int32_t* dst, double* w, int64_t cap,
+                   int64_t* m);
 
 /* Current node and edge counts. */
 sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m);

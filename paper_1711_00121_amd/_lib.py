@@ -86,6 +86,8 @@ SIGNATURES = {
                                            C.POINTER(sr_config), P, C.POINTER(sr_batch_stats)]),
     "apply_edge_update": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(sr_update_stats)]),
+    "apply_weight_update": (C.c_int, [P, C.c_int32, C.c_int32, C.c_double,
+                                      C.POINTER(sr_update_stats)]),
     "apply_batch": (C.c_int, [P, C.c_int64, I32P, I32P, I8P, C.POINTER(sr_batch_stats)]),
     "apply_batch_columns": (C.c_int, [P, C.c_int64, I32P, I32P, I8P, I32P, C.c_int32, P,
                                       C.c_int64, C.POINTER(sr_batch_stats)]),
@@ -99,6 +101,7 @@ SIGNATURES = {
                              C.POINTER(C.c_int64)]),
     "sr_copy_S": (C.c_int, [P, P, C.c_int64]),
     "sr_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sr_edges": (C.c_int, [P, I32P, I32P, F64P, C.c_int64, C.POINTER(C.c_int64)]),
     "sr_last_plan": (C.c_int, [P, I32P, C.c_int64, C.POINTER(C.c_int64)]),
     "sr_synchronize": (C.c_int, [P]),
     "sr_destroy": (C.c_int, [P]),

@@ -57,6 +57,7 @@ struct sr_ctx {
   std::vector<int32_t> slot_edge0;  // in-list slot -> initial edge index
 
   int32_t* d_adj[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<double> Wsum;  // weighted graphs: in-weight sums (the host copy of d_W)
   double* d_in_w = nullptr;
   double* d_out_w = nullptr;
   double* d_W = nullptr;
@@ -326,15 +327,67 @@ bool graph_fits(const sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>
 
 // Applies edge insertions (op > 0) or deletions to the host mirror and the device copy.
 // The caller has validated every edge and checked graph_fits for the insertions.
-sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>& e, int op) {
+// Weighted graphs: the in-weight sum of sink j from its row of the mirror, in slot order.
+double row_weight(const sr_ctx* ctx, int32_t j) {
+  const SlotList& L = ctx->g.in;
+  double w = 0.0;
+  for (int32_t p = 0; p < L.len[j]; ++p) w += L.w[L.start[j] + p];
+  return w;
+}
+
+WPtrs wptrs(const sr_ctx* c) {
+  WPtrs t;
+  t.p[0] = c->d_in_w;
+  t.p[1] = c->d_out_w;
+  t.p[2] = c->d_W;
+  return t;
+}
+
+// Launches the weight writes (array, index, value) in patches.
+sr_status patch_weights(sr_ctx* ctx, const std::vector<std::pair<std::pair<int32_t, int32_t>,
+                                                                double>>& wr) {
+  WPatch p;
+  p.count = 0;
+  for (const auto& x : wr) {
+    p.array[p.count] = x.first.first;
+    p.index[p.count] = x.first.second;
+    p.value[p.count] = x.second;
+    if (++p.count == WPatch::MAX) {
+      HC(launch_patch_w(wptrs(ctx), p, ctx->stream));
+      p.count = 0;
+    }
+  }
+  if (p.count) HC(launch_patch_w(wptrs(ctx), p, ctx->stream));
+  return SR_OK;
+}
+
+// Weighted graphs: sets the weight of the existing edge i -> j to w (mirror and device: the
+// two slot weights and W[j]).
+sr_status reweight_edge(sr_ctx* ctx, int32_t i, int32_t j, double w) {
+  SlotList& in = ctx->g.in;
+  SlotList& out = ctx->g.out;
+  const int32_t pi = in.find(j, i), po = out.find(i, j);
+  if (pi < 0 || po < 0) return SR_ENOENT;
+  in.w[in.start[j] + pi] = w;
+  out.w[out.start[i] + po] = w;
+  ctx->Wsum[j] = row_weight(ctx, j);
+  ctx->updated = true;
+  return patch_weights(ctx, {{{0, in.start[j] + pi}, w},
+                             {{1, out.start[i] + po}, w},
+                             {{2, j}, ctx->Wsum[j]}});
+}
+
+sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>& e, int op,
+                     const std::vector<double>* wts = nullptr) {
   std::vector<Write> wi, wo;
   std::vector<int32_t> mi, mo;
   bool full = false, cap_err = false;
-  for (auto& ij : e) {
-    const int32_t i = ij.first, j = ij.second;
+  for (size_t k = 0; k < e.size(); ++k) {
+    const int32_t i = e[k].first, j = e[k].second;
     if (op > 0) {
-      const int r1 = ctx->g.in.insert(j, i, 1.0, wi, mi);
-      const int r2 = ctx->g.out.insert(i, j, 1.0, wo, mo);
+      const double wt = wts ? (*wts)[k] : 1.0;
+      const int r1 = ctx->g.in.insert(j, i, wt, wi, mi);
+      const int r2 = ctx->g.out.insert(i, j, wt, wo, mo);
       full |= (r1 >= 2) || (r2 >= 2);
       cap_err |= (r1 == 3) || (r2 == 3);
       ctx->g.edges.insert(HostGraph::key(i, j));
@@ -349,6 +402,15 @@ sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>
     heavy_touch(ctx->hout, ctx->g.out, i);
   }
   ctx->updated = true;
+  std::vector<std::pair<std::pair<int32_t, int32_t>, double>> wr;  // weight writes
+  if (ctx->weighted) {
+    std::set<int32_t> sinks;
+    for (auto& ij : e) sinks.insert(ij.second);
+    for (int32_t j : sinks) {
+      ctx->Wsum[j] = row_weight(ctx, j);
+      wr.push_back({{2, j}, ctx->Wsum[j]});
+    }
+  }
   {
     sr_status hs = heavy_refresh(ctx);
     if (hs != SR_OK) {
@@ -362,7 +424,12 @@ sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>
     ctx->poisoned = true;
     return SR_EHIP;
   }
-  if (full) return upload_graph(ctx);
+  if (full) {
+    sr_status us = upload_graph(ctx);
+    if (us == SR_OK && ctx->weighted)
+      HC(hipMemcpy(ctx->d_W, ctx->Wsum.data(), ctx->Wsum.size() * 8, hipMemcpyHostToDevice));
+    return us;
+  }
   // Moved rows: upload their slots; then patch every touched (array, index) with the mirror's
   // final value (unique addresses per launch, so the writes of one launch commute).
   const SlotList* L[2] = {&ctx->g.in, &ctx->g.out};
@@ -378,6 +445,9 @@ sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>
       const int32_t st = L[l]->start[r], ln = L[l]->len[r];
       HC(hipMemcpy(ctx->d_adj[3 * l + 2] + st, L[l]->idx.data() + st, (size_t)ln * 4,
                    hipMemcpyHostToDevice));
+      if (ctx->weighted)
+        HC(hipMemcpy((l == 0 ? ctx->d_in_w : ctx->d_out_w) + st, L[l]->w.data() + st,
+                     (size_t)ln * 8, hipMemcpyHostToDevice));
       Wv[l]->push_back({0, r, 0});
       Wv[l]->push_back({1, r, 0});
     }
@@ -400,6 +470,12 @@ sr_status edit_graph(sr_ctx* ctx, const std::vector<std::pair<int32_t, int32_t>>
     }
   }
   if (p.count) HC(launch_patch(adjptrs(ctx), p, ctx->stream));
+  if (ctx->weighted) {
+    // the weight of every slot whose index was written moves with it
+    for (auto& t : touched)
+      if (t.first % 3 == 2) wr.push_back({{t.first / 3, t.second}, L[t.first / 3]->w[t.second]});
+    return patch_weights(ctx, wr);
+  }
   return SR_OK;
 }
 
@@ -502,9 +578,13 @@ struct FusedTarget {
 // affected areas, graph edit, K series steps on the new graph, and the S update.
 //   case_id 0: sources I exist; case_id 2: sources I are new nodes (isolated until now).
 //   n_work: node count the kernels cover (includes new and not yet created nodes).
+//   Weighted graphs (one source): alpha != 0 is the scale a of Delta Q = e_j a (e_i -
+//   Q[j, :])^T (case 0: gamma kind 3; case 2: a = w / (W_j + w)); reweight: the edge exists
+//   and only its weight becomes wt, otherwise insertions carry the weight wt.
 sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int32_t>& I,
                         int32_t j, int64_t n_work, sr_update_stats* st,
-                        const FusedTarget* ft = nullptr, const int32_t* I_dev = nullptr) {
+                        const FusedTarget* ft = nullptr, const int32_t* I_dev = nullptr,
+                        double alpha = 0.0, bool reweight = false, double wt = 1.0) {
   const double C = ctx->cfg.C;
   const int K = ctx->cfg.K;
   const int delta = (int)I.size();
@@ -512,18 +592,21 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   const bool prune = ctx->cfg.prune != 0 && ft == nullptr;
   double* P = ft ? ft->P + (int64_t)(ft->r_prev / ft->pld) * ft->gstride : ctx->P;
   const int pld = ctx->pld;
-  const bool direct = (case_id == 0) && ctx->cfg.gamma_form == SR_GAMMA_DIRECT;
+  const bool direct = (case_id == 0) && ctx->cfg.gamma_form == SR_GAMMA_DIRECT &&
+                      !ctx->weighted && alpha == 0.0;
   hipStream_t s = ctx->stream;
   const DevQ q = devq(ctx);
 
   GammaArgs ga{};
-  ga.kind = case_id == 2 ? 2 : (direct ? 1 : 0);
+  ga.kind = case_id == 2 ? 2 : (alpha != 0.0 ? 3 : (direct ? 1 : 0));
+  ga.alpha = alpha;
   ga.op = op;
   ga.j = j;
   ga.delta = delta;
   ga.dj = dj;
   ga.C = C;
-  ga.xi0 = case_id == 2 ? C * (double)delta / (double)(dj + delta) : C;
+  ga.xi0 = case_id == 2 ? (alpha > 0.0 ? C * alpha : C * (double)delta / (double)(dj + delta))
+                       : C;
   ga.I = idlist(I, 0, case_id == 0 ? I.size() : 0, I_dev);
 
   // S[:, I] (with supports) and S[:, j] from the old S.
@@ -570,7 +653,8 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   // Graph edit.
   std::vector<std::pair<int32_t, int32_t>> edges;
   for (int32_t i : I) edges.push_back({i, j});
-  sr_status es = edit_graph(ctx, edges, op);
+  const std::vector<double> wts(I.size(), wt);
+  sr_status es = reweight ? reweight_edge(ctx, I[0], j, wt) : edit_graph(ctx, edges, op, &wts);
   if (es != SR_OK) return es;
   const DevQ q_new = devq(ctx);
   const HeavyArgs hin_new = heavy_args(ctx->hin);
@@ -644,7 +728,8 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
 
 // C1 block (Theorem 8, Table 2 row C1): existing sources I, new sink j.
 sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_t n_work,
-                   const FusedTarget* ft = nullptr, const int32_t* I_dev = nullptr) {
+                   const FusedTarget* ft = nullptr, const int32_t* I_dev = nullptr,
+                   double wt = 1.0) {
   hipStream_t s = ctx->stream;
   const double C = ctx->cfg.C;
   const IdList il = idlist(I, 0, I.size(), I_dev);
@@ -662,7 +747,8 @@ sr_status c1_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, int64_
                       il.dev ? ctx->d_sum : nullptr));
   std::vector<std::pair<int32_t, int32_t>> e;
   for (int32_t i : I) e.push_back({i, j});
-  return edit_graph(ctx, e, +1);
+  const std::vector<double> wts(I.size(), wt);
+  return edit_graph(ctx, e, +1, &wts);
 }
 
 sr_status set_diags(sr_ctx* ctx, const std::vector<std::pair<int32_t, double>>& d) {
@@ -681,7 +767,7 @@ sr_status set_diags(sr_ctx* ctx, const std::vector<std::pair<int32_t, double>>& 
 }
 
 // C3 block (Algorithm 5, Table 2 row C3): new sources I and new sink j.
-sr_status c3_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j) {
+sr_status c3_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j, double wt = 1.0) {
   const double C = ctx->cfg.C;
   std::vector<std::pair<int32_t, double>> d;
   for (int32_t i : I) d.push_back({i, 1.0 - C});
@@ -690,7 +776,8 @@ sr_status c3_block(sr_ctx* ctx, const std::vector<int32_t>& I, int32_t j) {
   if (r != SR_OK) return r;
   std::vector<std::pair<int32_t, int32_t>> e;
   for (int32_t i : I) e.push_back({i, j});
-  return edit_graph(ctx, e, +1);
+  const std::vector<double> wts(I.size(), wt);
+  return edit_graph(ctx, e, +1, &wts);
 }
 
 // PartialSim (section 7): column q of the K_ps-term SimRank into out (n values).
@@ -754,6 +841,17 @@ sr_status partial_sim2(sr_ctx* ctx, const IdList& a, const IdList& b, double* ou
 }
 
 bool valid_ctx(sr_ctx* c) { return c != nullptr; }
+
+// The current edges in sink-major slot order: slot -> position (the order sr_edges reports
+// after an update), -1 for unused slots.
+std::vector<int32_t> slot_edges(const sr_ctx* ctx) {
+  const SlotList& L = ctx->g.in;
+  std::vector<int32_t> se(L.idx.size(), -1);
+  int32_t k = 0;
+  for (int64_t j = 0; j < ctx->g.n; ++j)
+    for (int32_t p = 0; p < L.len[j]; ++p) se[L.start[j] + p] = k++;
+  return se;
+}
 
 // Device addresses of `scratch`, one per GPU, resolved once per device at context creation
 // (with that device current) and kept for the life of the process.
@@ -968,7 +1066,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
     IC(dalloc(&ctx->d_in_w, slots));
     IC(dalloc(&ctx->d_out_w, (int64_t)ctx->g.out.idx.size()));
     IC(dalloc(&ctx->d_W, node_cap));
-    std::vector<double> Wsum(node_cap, 0.0);
+    std::vector<double>& Wsum = ctx->Wsum;
+    Wsum.assign(node_cap, 0.0);
     for (int64_t e = 0; e < m; ++e) Wsum[dst[e]] += weight[e];
     if (hipMemcpy(ctx->d_W, Wsum.data(), node_cap * 8, hipMemcpyHostToDevice) != hipSuccess) {
       sr_destroy(ctx);
@@ -1376,12 +1475,12 @@ sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int
   return SR_OK;
 }
 
-sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
-                            sr_update_stats* stats) {
-  if (!valid_ctx(ctx)) return SR_EINVAL;
-  if (ctx->poisoned) return SR_EHIP;
-  if (op != 1 && op != -1) return SR_EINVAL;
-  if (ctx->weighted) return SR_EMODE;
+}  // extern "C"
+
+// One unit update: op = +1 inserts i -> j (weight w_new on a weighted graph), -1 deletes it;
+// reweight (weighted graphs) changes the weight of the existing edge from w_old to w_new.
+static sr_status unit_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op, double w_old,
+                             double w_new, bool reweight, sr_update_stats* stats) {
   const int64_t n = ctx->g.n;
   if (i < 0 || j < 0) return SR_ERANGE;
   if (i == j) return SR_ESELF;
@@ -1400,13 +1499,14 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
   if (op < 0 && case_id != 0) return SR_ENOENT;
   if (case_id == 0) {
     const bool has = ctx->g.has(i, j);
-    if (op > 0 && has) return SR_EEXIST;
-    if (op < 0 && !has) return SR_ENOENT;
+    if (op > 0 && has && !reweight) return SR_EEXIST;
+    if ((op < 0 || reweight) && !has) return SR_ENOENT;
   }
+  if (ctx->weighted && ctx->cfg.mode == SR_COLUMN) return SR_EMODE;
   const int64_t n_new = n + (case_id == 3 ? 2 : (case_id == 0 ? 0 : 1));
   if (n_new > ctx->node_cap) return SR_ECAPACITY;
-  if (op > 0 && ctx->g.m + 1 > ctx->edge_cap) return SR_ECAPACITY;
-  if (op > 0 && !graph_fits(ctx, {{i, j}})) return SR_ECAPACITY;
+  if (op > 0 && !reweight && ctx->g.m + 1 > ctx->edge_cap) return SR_ECAPACITY;
+  if (op > 0 && !reweight && !graph_fits(ctx, {{i, j}})) return SR_ECAPACITY;
 
   ctx->last_case = -1;
   ctx->last_r = 0;
@@ -1503,18 +1603,33 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
   sr_status r = SR_OK;
   const double C = ctx->cfg.C;
   if (case_id == 0) {
-    r = lowrank_block(ctx, 0, op, {i}, j, n, stats);
+    // weighted graphs: the scale a of Delta Q = e_j a (e_i - Q[j, :])^T; the two cases
+    // where row j of Q is empty before or after take the weight-free unweighted forms
+    double alpha = 0.0;
+    if (ctx->weighted) {
+      const double Wj = ctx->Wsum[j];
+      const int64_t dj = ctx->g.in.len[j];
+      if (reweight)
+        alpha = (w_new - w_old) / (Wj + (w_new - w_old));
+      else if (op > 0 && dj > 0)
+        alpha = w_new / (Wj + w_new);
+      else if (op < 0 && dj > 1)
+        alpha = -w_old / (Wj - w_old);
+    }
+    r = lowrank_block(ctx, 0, op, {i}, j, n, stats, nullptr, nullptr, alpha, reweight, w_new);
   } else if (case_id == 1) {
     ctx->g.n = n_new;
-    r = c1_block(ctx, {i}, j, n);
+    r = c1_block(ctx, {i}, j, n, nullptr, nullptr, w_new);
     ctx->last_r = 0;
   } else if (case_id == 2) {
     ctx->g.n = n_new;
+    const double alpha = ctx->weighted ? w_new / (ctx->Wsum[j] + w_new) : 0.0;
     r = set_diags(ctx, {{i, 1.0 - C}});
-    if (r == SR_OK) r = lowrank_block(ctx, 2, +1, {i}, j, n_new, stats);
+    if (r == SR_OK)
+      r = lowrank_block(ctx, 2, +1, {i}, j, n_new, stats, nullptr, nullptr, alpha, false, w_new);
   } else {
     ctx->g.n = n_new;
-    r = c3_block(ctx, {i}, j);
+    r = c3_block(ctx, {i}, j, w_new);
     ctx->last_r = 0;
   }
   if (r != SR_OK) return r;
@@ -1534,6 +1649,48 @@ sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
     }
   }
   return SR_OK;
+}
+
+extern "C" {
+
+sr_status apply_edge_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op,
+                            sr_update_stats* stats) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (op != 1 && op != -1) return SR_EINVAL;
+  double w_old = 0.0;
+  if (op < 0 && ctx->weighted && i >= 0 && j >= 0 && i < ctx->g.n && j < ctx->g.n) {
+    const int32_t p = ctx->g.in.find(j, i);
+    if (p >= 0) w_old = ctx->g.in.w[ctx->g.in.start[j] + p];
+  }
+  return unit_update(ctx, i, j, op, w_old, op > 0 ? 1.0 : 0.0, false, stats);
+}
+
+sr_status apply_weight_update(sr_ctx* ctx, int32_t i, int32_t j, double w,
+                              sr_update_stats* stats) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (!ctx->weighted) return SR_EMODE;
+  if (!(w >= 0.0) || !std::isfinite(w)) return SR_EINVAL;
+  const int64_t n = ctx->g.n;
+  if (i < 0 || j < 0) return SR_ERANGE;
+  if (i == j) return SR_ESELF;
+  double w_old = 0.0;
+  if (i < n && j < n) {
+    const int32_t p = ctx->g.in.find(j, i);
+    if (p >= 0) w_old = ctx->g.in.w[ctx->g.in.start[j] + p];
+  }
+  if (w_old == 0.0 && w == 0.0) return SR_ENOENT;
+  if (w == w_old) {
+    if (stats) {
+      memset(stats, 0, sizeof(*stats));
+      stats->n_after = n;
+    }
+    return SR_OK;
+  }
+  if (w_old == 0.0) return unit_update(ctx, i, j, +1, 0.0, w, false, stats);
+  if (w == 0.0) return unit_update(ctx, i, j, -1, w_old, 0.0, false, stats);
+  return unit_update(ctx, i, j, +1, w_old, w, true, stats);
 }
 
 // ------------------------------------------------------------------------------ batches
@@ -2212,6 +2369,31 @@ sr_status sr_get_aff(sr_ctx* ctx, int32_t level, int32_t* A_dev, int64_t* nA, in
   return SR_OK;
 }
 
+sr_status sr_edges(sr_ctx* ctx, int32_t* src, int32_t* dst, double* w, int64_t cap,
+                   int64_t* m) {
+  if (!valid_ctx(ctx) || !m) return SR_EINVAL;
+  *m = ctx->g.m;
+  if (cap < *m) return SR_OK;  // size query
+  if (!ctx->updated) {
+    for (int64_t e = 0; e < *m; ++e) {
+      if (src) src[e] = ctx->src0[e];
+      if (dst) dst[e] = ctx->dst0[e];
+      if (w) w[e] = ctx->weighted ? ctx->w0[e] : 1.0;
+    }
+    return SR_OK;
+  }
+  const SlotList& L = ctx->g.in;
+  int64_t k = 0;
+  for (int64_t j = 0; j < ctx->g.n; ++j)
+    for (int32_t p = 0; p < L.len[j]; ++p, ++k) {
+      const int64_t slot = L.start[j] + p;
+      if (src) src[k] = L.idx[slot];
+      if (dst) dst[k] = (int32_t)j;
+      if (w) w[k] = ctx->weighted ? L.w[slot] : 1.0;
+    }
+  return SR_OK;
+}
+
 sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m) {
   if (!valid_ctx(ctx)) return SR_EINVAL;
   if (n) *n = ctx->g.n;
@@ -2233,13 +2415,13 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   if (!valid_ctx(ctx) || npairs < 0 || !dw_dev || (npairs > 0 && (!a_dev || !b_dev || !g_dev)))
     return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
-  if (ctx->cfg.mode != SR_DENSE || ctx->updated) return SR_EMODE;
+  if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
   {
     const sr_status rs = check_pair_ids(ctx, npairs, a_dev, b_dev);
     if (rs != SR_OK) return rs;
   }
   const int64_t n = ctx->g.n;
-  const int64_t m = (int64_t)ctx->src0.size();
+  const int64_t m = ctx->g.m;
   const double C = ctx->cfg.C;
   hipStream_t s = ctx->stream;
   const int64_t ldi = (n + 63) / 64 * 64;
@@ -2262,8 +2444,10 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   }
   const DevQ q = devq(ctx);
   const DevAdj out = devout(ctx);
-  hipError_t e = hipMemcpy(se, ctx->slot_edge0.data(), ctx->slot_edge0.size() * 4,
-                           hipMemcpyHostToDevice);
+  // in-list slot -> output position: the caller's edge order until the first update, then
+  // the order of sr_edges (sinks ascending, slots in order)
+  const std::vector<int32_t> se_host = ctx->updated ? slot_edges(ctx) : ctx->slot_edge0;
+  hipError_t e = hipMemcpy(se, se_host.data(), se_host.size() * 4, hipMemcpyHostToDevice);
   // Gs = G + G^T: Sig = Lam + Lam^T solves Sig = Gs + C Q^T Sig Q (Lam = G + C Q^T Lam Q).
   if (e == hipSuccess) e = hipMemsetAsync(G, 0, (size_t)n * ldi * 8, s);
   if (e == hipSuccess) e = launch_scatter_pairs_sym(G, n, npairs, a_dev, b_dev, g_dev, s);

@@ -160,12 +160,24 @@ __global__ __launch_bounds__(kB) void gamma_kernel(GammaArgs g, int64_t n,
         uj = (g.dj == g.delta) ? 1.0 : d / (dj - d);
       }
       gam = uj * (Qz[a] + (isj ? 0.5 * vz * uj : 0.0));
-    } else {
-      // Eq (60) and Table 2 row (C2): the z vector is eta_0.
+    } else if (g.kind == 2) {
+      // Eq (60) and Table 2 row (C2): the z vector is eta_0. A weighted new source of weight
+      // w takes a = w / (W_j + w) in place of 1 / (d_j + 1) (delta = 1).
       const double sjj = Sj[g.j];
-      gam = (isj ? (d * sjj - (d - C) * (1.0 - C)) / (2.0 * C * (dj + d)) + (1.0 - C) / C
-                 : 0.0) -
-            Sj[a] / C;
+      const double diag = g.alpha > 0.0
+                              ? g.alpha * (sjj - (1.0 - C) * (1.0 - C)) / (2.0 * C)
+                              : (d * sjj - (d - C) * (1.0 - C)) / (2.0 * C * (dj + d));
+      gam = (isj ? diag + (1.0 - C) / C : 0.0) - Sj[a] / C;
+    } else {
+      // A weighted edge change i -> j by dw, Delta Q = e_j a (e_i - Q[j, :])^T with
+      // a = dw / (W_j + dw): Theorem 3's closed form with a in place of 1 / (d_j + 1)
+      // (it rests only on the fixed-point identity of eq (33)),
+      //   gamma = a (Q S e_i - S e_j / C) + (a (1 - C) / C + a^2 lambda / 2) e_j.
+      const double al = g.alpha;
+      const double Sii = sum_at(SI, g.I);
+      const double lam = Sii + Sj[g.j] / C - 2.0 * QSI[g.j] - 1.0 / C + 1.0;
+      gam = al * (QSI[a] - Sj[a] / C) +
+            (isj ? al * (1.0 - C) / C + 0.5 * al * al * lam : 0.0);
     }
     *reinterpret_cast<double2*>(P + a * pld) = make_double2(isj ? g.xi0 : 0.0, gam);
   }

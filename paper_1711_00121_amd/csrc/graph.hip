@@ -31,6 +31,11 @@ __global__ __launch_bounds__(64) void patch_kernel(AdjPtrs t, Patch p) {
   if (i < p.count) t.p[p.array[i]][p.index[i]] = p.value[i];
 }
 
+__global__ __launch_bounds__(64) void patch_w_kernel(WPtrs t, WPatch p) {
+  int i = threadIdx.x;
+  if (i < p.count) t.p[p.array[i]][p.index[i]] = p.value[i];
+}
+
 // What one traversal computes. Values per entry: NV = 1 (x) or 2 (xi, eta pair).
 struct Op {
   int kind;             // 0: y = post*(base + scale*Q x); 1: series step; 2: y = scale*Q^T x;
@@ -468,6 +473,12 @@ Op blank() {
 hipError_t launch_patch(const AdjPtrs& t, const Patch& p, hipStream_t s) {
   if (p.count <= 0) return hipSuccess;
   patch_kernel<<<1, 64, 0, s>>>(t, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_w(const WPtrs& t, const WPatch& p, hipStream_t s) {
+  if (p.count <= 0) return hipSuccess;
+  patch_w_kernel<<<1, 64, 0, s>>>(t, p);
   return hipGetLastError();
 }
 

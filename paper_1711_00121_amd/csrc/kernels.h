@@ -22,6 +22,19 @@ struct AdjPtrs {
   int32_t* p[6];
 };
 hipError_t launch_patch(const AdjPtrs& t, const Patch& p, hipStream_t s);
+// Weight patches of a weighted graph: slot weights of the in- and out-lists and the in-weight
+// sums W, passed by value.
+struct WPatch {
+  static constexpr int MAX = 24;
+  int32_t count;
+  int32_t array[MAX];  // 0 in-list slot weights, 1 out-list slot weights, 2 W
+  int32_t index[MAX];
+  double value[MAX];
+};
+struct WPtrs {
+  double* p[3];
+};
+hipError_t launch_patch_w(const WPtrs& t, const WPatch& p, hipStream_t s);
 
 // A list of node ids (the sources I of a block). Up to MAX ids travel by value in the
 // kernel arguments; a longer list lives in device memory (dev, count entries), so a block of
@@ -121,13 +134,17 @@ hipError_t launch_gather_inrows(SView S, int64_t n, const DevQ& q, int32_t j, do
 
 // Scalars and coefficients of one block update, shared by the gamma kernels.
 struct GammaArgs {
-  int32_t kind;     // 0 closed form (C0), 1 direct form (C0), 2 C2 z of eq (60) / Table 2
+  int32_t kind;     // 0 closed form (C0), 1 direct form (C0), 2 C2 z of eq (60) / Table 2,
+                    // 3 closed form of a weighted edge change (one source, scale alpha)
   int32_t op;       // +1 insert, -1 delete
   int32_t j;
   int32_t delta;
   int64_t dj;       // in-degree of j before the block
   double C;
   double xi0;       // xi_0 = xi0 * e_j
+  double alpha;     // weighted graphs: kind 3's scale a = dw / (W_j + dw) of
+                    // Delta Q = e_j a (e_i - Q[j, :])^T; kind 2 with alpha > 0 uses it for
+                    // 1 / (d_j + 1) (a new source of weight w: a = w / (W_j + w))
   IdList I;         // sources (for S_II and the direct form's v)
   // When set, the sum over I of the closed form's S[:, I] (kind 0: S_II) or of the direct
   // form's z (kind 1), precomputed by launch_sum_at; long lists use it so that no thread

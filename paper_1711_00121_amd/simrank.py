@@ -138,6 +138,17 @@ class Context:
             return None
         return {f: getattr(s, f) for f, _ in L.sr_update_stats._fields_}
 
+    def apply_weight_update(self, i, j, w, stats=False):
+        """Weighted graphs: sets the weight of edge i -> j to w (0 deletes, a missing edge
+        is inserted)."""
+        s = L.sr_update_stats() if stats else None
+        st = self.lib.apply_weight_update(self.h, int(i), int(j), float(w),
+                                          C.byref(s) if s is not None else None)
+        L.check(st, "apply_weight_update")
+        if s is None:
+            return None
+        return {f: getattr(s, f) for f, _ in L.sr_update_stats._fields_}
+
     def apply_batch(self, src, dst, op, stats=False):
         src = _i32(src)
         dst = _i32(dst)
@@ -181,6 +192,17 @@ class Context:
         m = C.c_int64()
         L.check(self.lib.sr_sizes(self.h, C.byref(n), C.byref(m)), "sr_sizes")
         return n.value, m.value
+
+    def edges(self):
+        """The current edges ``(src, dst, w)`` in the order backward reports dL/dw."""
+        m = C.c_int64()
+        L.check(self.lib.sr_edges(self.h, None, None, None, 0, C.byref(m)), "sr_edges")
+        src = np.empty(m.value, dtype=np.int32)
+        dst = np.empty(m.value, dtype=np.int32)
+        w = np.empty(m.value, dtype=np.float64)
+        L.check(self.lib.sr_edges(self.h, _ptr(src, C.c_int32), _ptr(dst, C.c_int32),
+                                  _ptr(w, C.c_double), m.value, C.byref(m)), "sr_edges")
+        return src, dst, w
 
     def query_column(self, x, what="S"):
         n, _ = self.sizes()
@@ -254,7 +276,7 @@ class Context:
         a = torch.as_tensor(a, dtype=torch.int32, device="cuda").contiguous()
         b = torch.as_tensor(b, dtype=torch.int32, device="cuda").contiguous()
         g = torch.as_tensor(g, dtype=torch.float64, device="cuda").contiguous()
-        dw = torch.empty(self.m0, dtype=torch.float64, device="cuda")
+        dw = torch.empty(self.sizes()[1], dtype=torch.float64, device="cuda")
         L.check(self.lib.backward(self.h, a.numel(), _dev(a), _dev(b), _dev(g), _dev(dw)),
                 "backward")
         return dw
@@ -288,16 +310,18 @@ class SimRankPairs(torch.autograd.Function):
     """``S[a, b]`` for the context's graph as a function of its edge weights.
 
     ``forward(weights, context, a, b)`` returns the pair values; ``weights`` must equal the
-    (m,) weights the context was built from (all ones for an unweighted context), else
-    ValueError. ``backward`` calls the library's adjoint and
+    context's current (m,) weights in the order of ``Context.edges`` (those it was built
+    with until its first update; all ones for an unweighted context), else ValueError. ``backward`` calls the library's adjoint and
     returns dL/dweights.
     """
 
     @staticmethod
     def forward(ctx, weights, context, a, b):
-        # the context holds S of the weights it was built with: any other weights would get
-        # stale values and gradients, so they are refused
-        ref = getattr(context, "weights", None)
+        # the context holds S of its current weights (those it was built with, or as updates
+        # left them, in the order of Context.edges): any other weights would get stale values
+        # and gradients, so they are refused
+        ref = context.edges()[2] if hasattr(context, "edges") else getattr(context, "weights",
+                                                                            None)
         if ref is None:
             ref = np.ones(context.m0)
         w = weights.detach().to(device="cpu", dtype=torch.float64).numpy()
