@@ -62,7 +62,11 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--max-batch", type=int, default=4096)
-    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="low-rank blocks per fused pass (0: the autotuner picks it, and the "
+                         "GEMM tile variant, at the size after the warm-up)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="plain launches instead of replaying captured series chains")
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--split-rows", type=int, default=0,
                     help="graph rows above this many entries are traversed in chunks "
@@ -149,7 +153,8 @@ def run_batch(args):
     ctx = Context(n, s, d, C=C, K=K, s_prec="hilo", node_cap=counts[-1] + 64,
                   split_rows=args.split_rows,
                   edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
-                  fused_batch=not args.no_fused, batch_chunk=args.chunk)
+                  fused_batch=not args.no_fused, batch_chunk=args.chunk or 64,
+                  graphs=not args.no_graphs)
     torch.cuda.synchronize()
     log(f"bench: init (S by fixed point on device) {time.perf_counter() - t0:.1f}s")
 
@@ -159,10 +164,18 @@ def run_batch(args):
         torch.cuda.synchronize()
         log(f"bench: warmup batch {w} ({len(bi)} edges) done")
 
+    tuning = None
+    if args.chunk == 0 and not args.no_fused:
+        t1 = time.perf_counter()
+        tuning = ctx.tune()
+        tuning["seconds"] = round(time.perf_counter() - t1, 2)
+        log(f"bench: autotuned batch_chunk={tuning['batch_chunk']} "
+            f"variant={tuning['variant']} ({'cached' if tuning['cached'] else 'measured'})")
+    chunk = ctx.cfg.batch_chunk
     n_first = ctx.sizes()[0]
     ctx.profile(True)
     ctx.profile_read(reset=True)
-    edges_in = edges_net = pairs = lowrank = passes = 0
+    edges_in = edges_net = pairs = lowrank = passes = replays = 0
     flops = 0.0
     # net edges per Table 2 case (C0 insertions and deletions apart), from the batch plans
     mix = {"C0+": 0, "C0-": 0, "C1": 0, "C2": 0, "C3": 0}
@@ -182,6 +195,7 @@ def run_batch(args):
         pairs += st["pairs"]
         lowrank += st["lowrank_blocks"]
         passes += st["fused_passes"]
+        replays += st["series_replays"]
         nt = float(st["n_after"])
         # Delta S is symmetric: a low-rank block's work is its n (n + 1) / 2 distinct entries
         # at 2 (K + 1) multiply-adds each, n the node count of the batch that applies it
@@ -229,7 +243,9 @@ def run_batch(args):
         ref = Context(n, s, d, C=C, K=K, s_prec="fp64", node_cap=counts[-1] + 64,
                       split_rows=args.split_rows,
                       edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
-                      fused_batch=not args.no_fused, batch_chunk=args.chunk)
+                      fused_batch=not args.no_fused, batch_chunk=chunk,
+                      graphs=not args.no_graphs)
+        ref.set_tuning(chunk, tuning["variant"] if tuning else 0)
         for t in range(args.warmup + args.steps):
             ref.apply_batch(*batches[t])
             log(f"bench: float64-store replay, batch {t} done")
@@ -311,13 +327,16 @@ def run_batch(args):
                                    "the graph after the timed batches")
     out = common(args, cfg, pairs / dt, "pair-updates/s", dt, args.steps,
                  extra_cfg={"s_store": "f32 value + f32 compensation",
-                            "max_batch": args.max_batch, "batch_chunk": args.chunk,
+                            "max_batch": args.max_batch, "batch_chunk": chunk,
+                            "gemm_variant": tuning["variant"] if tuning else 0,
+                            "graphs": not args.no_graphs,
                             "fused": not args.no_fused, "n_first": n_first, "n_last": n_last,
                             "m_last": m_last})
     out.update({
         "edge_updates_per_s": edge_rate, "edges_net": edges_net, "edges_in": edges_in,
         "edges_in_per_s": edges_in / dt, "net_edges_by_case": mix,
-        "lowrank_blocks": lowrank, "fused_passes": passes,
+        "lowrank_blocks": lowrank, "fused_passes": passes, "series_graph_replays": replays,
+        "tuning": tuning,
         "plain_gpu": {"ms_per_edge_by_case": per_case,
                       "edges_timed_by_case": {c: len(v) for c, v in times.items()},
                       "ms_per_edge_at_batch_mix": weighted,
@@ -549,7 +568,7 @@ def run_forest(args):
     n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
     log(f"bench: generating Chung-Lu n={n} m={m}")
     s, d = W.chung_lu(n, m, seed=1002)
-    common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk,
+    common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk or 64,
                       split_rows=args.split_rows)
 
     def seeded(profile=False):
@@ -586,7 +605,7 @@ def run_forest(args):
     ref.close()
     out = common(args, cfg, float(n) * n * args.steps / dt, "S entries/s", dt, args.steps,
                  extra_cfg={"workload": "forest_seeded_n20k", "s_store": "f32 value + f32 "
-                            "compensation", "batch_chunk": args.chunk})
+                            "compensation", "batch_chunk": args.chunk or 64})
     out["metric"] = "all-pairs SimRank seeded from a spanning forest (Example 1.2), S entries/s"
     out["seconds_per_all_pairs"] = dt / args.steps
     out["forest"] = {"tree_edges": m - st["edges_in"], "batch_edges": st["edges_in"],
@@ -625,7 +644,7 @@ def run_partitioned(args, parts=16, p_cross=0.01):
     n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
     log(f"bench: generating {parts} planted communities n={n} m={m}")
     s, d, _ = W.communities(n, m, parts, p_cross, seed=1102)
-    common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk,
+    common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk or 64,
                       split_rows=args.split_rows)
 
     def build(profile=False):
@@ -663,7 +682,7 @@ def run_partitioned(args, parts=16, p_cross=0.01):
                  extra_cfg={"workload": "partitioned_n20k", "parts": parts,
                             "planted_cross_fraction": p_cross,
                             "s_store": "f32 value + f32 compensation",
-                            "batch_chunk": args.chunk})
+                            "batch_chunk": args.chunk or 64})
     out["metric"] = ("all-pairs SimRank over a partitioned graph (Example 1.1), S entries/s")
     out["seconds_per_all_pairs"] = dt / args.steps
     out["partition"] = {"cross_edges": st["edges_in"], "blocks": st["blocks"],
@@ -704,7 +723,7 @@ def run_topk(args, nq=4096, k=100):
     s, d = W.chung_lu(n, m, seed=1003)
     batches, counts = W.batch_stream(n, s, d, 1, args.max_batch, seed=2003)
     ctx = Context(n, s, d, C=C, K=K, s_prec="hilo", node_cap=counts[-1] + 64,
-                  edge_cap=m + len(batches[0][0]) + 1024, batch_chunk=args.chunk,
+                  edge_cap=m + len(batches[0][0]) + 1024, batch_chunk=args.chunk or 64,
                   split_rows=args.split_rows)
     ctx.apply_batch(*batches[0])
     n_now = ctx.sizes()[0]

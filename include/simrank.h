@@ -86,7 +86,9 @@ typedef struct sr_config {
                             one workgroup. 0 means 65536; otherwise at least 2048            */
   int32_t profile;       /* 1: time the S-update launches from creation on (as sr_profile(1)),
                             so that those inside init_simrank_tree are counted too          */
-  int32_t reserved;      /* set to 0                                                        */
+  int32_t graphs;        /* 1: fused batches capture each block's K-step series chain as a HIP
+                            graph (one per panel slot of a chunk, kept while the node count
+                            and the graph's row tiers stay) and replay it; 0: plain launches */
 } sr_config;
 
 /* Per-update statistics (filled when a non-null pointer is passed; the call then
@@ -113,12 +115,12 @@ typedef struct sr_batch_stats {
   int64_t pairs;          /* S entries updated, summed over low-rank blocks, plus border
                              and diagonal writes of C1 / C2 / C3 blocks                    */
   int32_t fused_passes;   /* passes over S made by the fused apply                         */
-  int32_t reserved;
+  int32_t series_replays; /* K-step series chains replayed from captured HIP graphs        */
 } sr_batch_stats;
 
 /* Fills *cfg with defaults: C = 0.6, K = 15, K_ps = 30, SR_S_FP64, SR_DENSE,
  * SR_GAMMA_CLOSED, prune = 1, capacities 0 (derived), init_tol = 1e-15, init_max_iter = 400,
- * batch_chunk = 64, fused_batch = 1. */
+ * batch_chunk = 64, fused_batch = 1, graphs = 1. */
 sr_status sr_default_config(sr_config* cfg);
 
 /* Creates a context for the digraph with n nodes and m edges src[e] -> dst[e] (host arrays,
@@ -322,6 +324,21 @@ sr_status sr_profile(sr_ctx* ctx, int32_t enable);
 /* Synchronises, then returns the summed elapsed milliseconds of the recorded launches (*ms)
  * and their count (*launches); reset = 1 clears the record. */
 sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
+
+/* Tuning: times the fused pass of apply_batch at the context's current node count with the
+ * GEMM tile variant `variant` (0 .. 3: panel columns per LDS chunk and LDS pitch in doubles,
+ * (16, 18), (16, 20), (32, 34), (32, 36)) over `blocks` deferred blocks, and the incremental
+ * corrections one deferred block makes for blocks / 2 later slots of its chunk: *gemm_ms and
+ * *corr_ms are the mean of `reps` launches after one warm-up. The pass runs on a zero panel,
+ * so S keeps its values. Dense mode; allocates a zero panel of n x blocks 2(K+1) (rounded up
+ * to 32) doubles for the call; synchronises. */
+sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t reps,
+                        double* gemm_ms, double* corr_ms);
+
+/* Tuning: sets the context's batch_chunk (blocks per fused pass) and the fused GEMM's tile
+ * variant (as sr_time_fused). A new chunk frees the batch panel and correction buffers, which
+ * the next batch allocates again (synchronises). SR_ERANGE for an unknown variant. */
+sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant);
 
 /* Diagnostics: runs one v_mfma_f64_16x16x4_f64 on a single wave with lane l supplying
  * a_dev[l] and b_dev[l] (64 device doubles each) and writes the four accumulator values held

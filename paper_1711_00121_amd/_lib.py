@@ -37,7 +37,7 @@ class sr_config(C.Structure):
         ("fused_batch", C.c_int32),
         ("split_rows", C.c_int32),
         ("profile", C.c_int32),
-        ("reserved", C.c_int32),
+        ("graphs", C.c_int32),
     ]
 
 
@@ -65,7 +65,7 @@ class sr_batch_stats(C.Structure):
         ("n_after", C.c_int64),
         ("pairs", C.c_int64),
         ("fused_passes", C.c_int32),
-        ("reserved", C.c_int32),
+        ("series_replays", C.c_int32),
     ]
 
 
@@ -108,6 +108,9 @@ SIGNATURES = {
     "sr_strerror": (C.c_char_p, [C.c_int]),
     "sr_mfma_layout_probe": (C.c_int, [P, P, P, P]),
     "sr_profile": (C.c_int, [P, C.c_int32]),
+    "sr_time_fused": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
+    "sr_set_tuning": (C.c_int, [P, C.c_int32, C.c_int32]),
     "sr_profile_read": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
 }
 

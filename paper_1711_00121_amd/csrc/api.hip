@@ -32,6 +32,7 @@ struct HeavySet {
   std::vector<int32_t> med, heavy, huge, hfirst;
   std::vector<int2> chunk;           // (row, first entry) per chunk of the huge rows
   bool dirty = true;
+  uint64_t version = 0;              // bumped at every upload (captured graphs depend on it)
   int32_t* d_med = nullptr;
   int32_t* d_heavy = nullptr;
   int32_t* d_huge = nullptr;
@@ -106,6 +107,20 @@ struct sr_ctx {
   int64_t corr_tab_cap = 0;
 
   HeavySet hin, hout;      // heavy in-rows (Q) and out-rows (Q^T)
+
+  int gemm_variant = 0;    // fused GEMM tile variant (launch_lowrank), set by sr_set_tuning
+  // Captured K-step series chains of fused batches, one per panel slot of a chunk; a graph
+  // holds its panel segment, node count and the in-row tiers' version by value, so it is
+  // captured again when any of them changes.
+  struct SeriesGraph {
+    hipGraphExec_t exec = nullptr;
+    const double* P = nullptr;
+    int64_t n = -1;
+    uint64_t ver = ~0ull;
+  };
+  std::vector<SeriesGraph> sgraphs;
+  hipStream_t cap_stream = nullptr;  // capture only (the context's stream may be the null one)
+  int64_t graph_captures = 0, graph_replays = 0;
 
   bool profiling = false;  // bracket S-update launches with events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -270,6 +285,7 @@ sr_status heavy_sync(sr_ctx* ctx, HeavySet& H, const SlotList& L) {
   if (e == hipErrorOutOfMemory) return SR_ENOMEM;
   HC(e);
   H.dirty = false;
+  ++H.version;
   return SR_OK;
 }
 
@@ -574,6 +590,43 @@ struct FusedTarget {
   const double* cJ = nullptr;
 };
 
+// The K steps of eq (16a) of a deferred block that writes the panel segment P, replayed from
+// the captured graph of its chunk slot (captured on a private stream, launched on the
+// context's stream, so it runs in order with the block's other launches).
+sr_status series_replay(sr_ctx* ctx, int slot, double* P, int64_t n_work) {
+  if ((int)ctx->sgraphs.size() <= slot) ctx->sgraphs.resize(slot + 1);
+  sr_ctx::SeriesGraph& sg = ctx->sgraphs[slot];
+  const uint64_t ver = ctx->hin.version;
+  if (!sg.exec || sg.P != P || sg.n != n_work || sg.ver != ver) {
+    if (sg.exec) {
+      (void)hipGraphExecDestroy(sg.exec);
+      sg.exec = nullptr;
+    }
+    if (!ctx->cap_stream) HC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HC(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    const DevQ q = devq(ctx);
+    const HeavyArgs h = heavy_args(ctx->hin);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < ctx->cfg.K && e == hipSuccess; ++k)
+      e = launch_series_step(q, h, n_work, P, ctx->pld, k, ctx->cfg.C, 1.0, nullptr,
+                             ctx->cap_stream, ctx->pairs, ctx->node_cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (e == hipSuccess) e = ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) sg.exec = nullptr;
+    HC(e);
+    sg.P = P;
+    sg.n = n_work;
+    sg.ver = ver;
+    ++ctx->graph_captures;
+  }
+  HC(hipGraphLaunch(sg.exec, ctx->stream));
+  ++ctx->graph_replays;
+  return SR_OK;
+}
+
 // One low-rank block (Table 2 rows C0 insert/delete, or C2): gamma from the old S and graph,
 // affected areas, graph edit, K series steps on the new graph, and the S update.
 //   case_id 0: sources I exist; case_id 2: sources I are new nodes (isolated until now).
@@ -660,7 +713,10 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
   const HeavyArgs hin_new = heavy_args(ctx->hin);
 
   // K steps of eq (16a) on the new graph; level k+1 of the affected areas in the same pass:
-  // A_{k+1} = out_new(A_0 | A_k), B_{k+1} = out_new(B_0 | B_k).
+  // A_{k+1} = out_new(A_0 | A_k), B_{k+1} = out_new(B_0 | B_k). A deferred block of a fused
+  // batch (no affected areas) replays its chain from a captured graph.
+  if (ft && !prune && ctx->cfg.graphs && K > 0)
+    return series_replay(ctx, ft->r_prev / ft->pld, P, n_work);
   for (int k = 0; k < K; ++k) {
     AffLevel al;
     al.a0 = A;
@@ -923,12 +979,16 @@ sr_status sr_default_config(sr_config* cfg) {
   cfg->batch_chunk = 64;
   cfg->fused_batch = 1;
   cfg->split_rows = kSplitRows;
+  cfg->graphs = 1;
   return SR_OK;
 }
 
 sr_status sr_destroy(sr_ctx* ctx) {
   if (!ctx) return SR_OK;
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& g : ctx->sgraphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto& ev : ctx->prof_events) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
@@ -1845,6 +1905,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   }
   int q = 0;  // deferred blocks in the current chunk
   int passes = 0;
+  const int64_t replays0 = ctx->graph_replays;
   auto flush = [&]() -> sr_status {
     if (q == 0) return SR_OK;
     LowRankArgs la{};
@@ -1857,6 +1918,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     la.rows = nullptr;
     la.nrows = n_new;
     la.ncols = n_new;
+    la.variant = ctx->gemm_variant;
     HC(run_lowrank(ctx, la));
     ++passes;
     q = 0;
@@ -2008,6 +2070,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     stats->n_after = n_new;
     stats->pairs = pairs;
     stats->fused_passes = passes;
+    stats->series_replays = (int32_t)(ctx->graph_replays - replays0);
   }
   return SR_OK;
 }
@@ -2508,6 +2571,106 @@ sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t re
     ctx->prof_ms = 0.0;
     ctx->prof_launches = 0;
   }
+  return SR_OK;
+}
+
+sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t reps,
+                        double* gemm_ms, double* corr_ms) {
+  if (!valid_ctx(ctx) || !gemm_ms || !corr_ms || blocks < 1 || reps < 1) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+  if (variant < 0 || variant >= kGemmVariants) return SR_ERANGE;
+  const int64_t n = ctx->g.n;
+  const int pld = ctx->pld;
+  const int64_t cols = (int64_t)blocks * pld;
+  hipStream_t s = ctx->stream;
+  double* Z = nullptr;  // a zero panel: the timed passes add exact zeros to S
+  int32_t* tab = nullptr;
+  double *cv = nullptr, *cw = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int slots = std::max(1, blocks / 2);
+  auto done = [&](sr_status r) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(Z);
+    (void)hipFree(tab);
+    (void)hipFree(cv);
+    (void)hipFree(cw);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return r;
+  };
+  if (dalloc(&Z, ctx->p_rows * cols) != hipSuccess || dalloc(&tab, 2 * slots + 1) != hipSuccess ||
+      dalloc(&cv, 2 * (int64_t)slots * ctx->p_rows) != hipSuccess ||
+      dalloc(&cw, 2 * (int64_t)slots * pld) != hipSuccess)
+    return done(SR_ENOMEM);
+  if (hipMemsetAsync(Z, 0, (size_t)ctx->p_rows * cols * 8, s) != hipSuccess ||
+      hipMemsetAsync(tab, 0, (size_t)(2 * slots + 1) * 4, s) != hipSuccess ||
+      hipMemsetAsync(cv, 0, (size_t)2 * slots * ctx->p_rows * 8, s) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    ctx->poisoned = true;
+    return done(SR_EHIP);
+  }
+  LowRankArgs la{};
+  la.S = ctx->S;
+  la.P = Z;
+  la.pld = pld;
+  la.gstride = ctx->p_rows * pld;
+  la.p_rows = ctx->p_rows;
+  la.r = (int)cols;
+  la.nrows = n;
+  la.ncols = n;
+  la.variant = variant;
+  // one deferred block's corrections for `slots` later slots of its chunk (zero weights)
+  CorrSlots cs{};
+  cs.rstart = tab;
+  cs.sink = tab + slots + 1;
+  cs.rows = tab;
+  cs.corr = cv;
+  cs.ldc = ctx->p_rows;
+  cs.base = 0;
+  cs.w = cw;
+  float t_gemm = 0.0f, t_corr = 0.0f;
+  hipError_t e = launch_lowrank(la, s);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_lowrank(la, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&t_gemm, e0, e1);
+  if (e == hipSuccess && (pld == 32 || pld == 64)) {
+    e = launch_corr_update(Z, pld, n, cs, 0, slots, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_corr_update(Z, pld, n, cs, 0, slots, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_corr, e0, e1);
+  }
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return done(SR_EHIP);
+  }
+  *gemm_ms = (double)t_gemm / reps;
+  *corr_ms = (double)t_corr / reps;
+  return done(SR_OK);
+}
+
+sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant) {
+  if (!valid_ctx(ctx) || batch_chunk < 1) return SR_EINVAL;
+  if (ctx->poisoned) return SR_EHIP;
+  if (variant < 0 || variant >= kGemmVariants) return SR_ERANGE;
+  if (batch_chunk != ctx->cfg.batch_chunk) {
+    // the batch panel and the correction slots are sized by the chunk: allocated again by
+    // the next batch (captured chains keep panel addresses, so they go too)
+    HC(hipStreamSynchronize(ctx->stream));
+    for (auto& g : ctx->sgraphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    ctx->sgraphs.clear();
+    double* bufs[] = {ctx->Pb, ctx->wts, ctx->corr, ctx->corr_w};
+    for (double* b : bufs) (void)hipFree(b);
+    ctx->Pb = ctx->wts = ctx->corr = ctx->corr_w = nullptr;
+    ctx->corr_slots = 0;
+    ctx->cfg.batch_chunk = batch_chunk;
+  }
+  ctx->gemm_variant = variant;
   return SR_OK;
 }
 

@@ -267,7 +267,10 @@ struct LowRankArgs {
   int64_t gstride;    // doubles between consecutive groups of pld columns (block-major
                       // batch panel); column c of row a is at (c / pld) gstride + a pld + c % pld
   double* acc_out;    // launch_lowrank_acc: float64 output, ld_out doubles per row
+  int32_t variant;    // fused GEMM: tile variant (0 .. kGemmVariants - 1): panel columns per
+                      // LDS chunk and LDS pitch, (16, 18), (16, 20), (32, 34), (32, 36)
 };
+constexpr int kGemmVariants = 4;
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
 // Column mode, batches: acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1] for list
 // positions p < nrows and nodes a < ncols (the deferred blocks' Delta S[a][rows[p]], eq (71)),

@@ -252,19 +252,20 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
 // buffered: the global loads of chunk c + 1 are issued before the MFMAs of chunk c and land
 // in LDS after them. The global panel loads are unconditional (the panel holds zero rows up
 // to a multiple of GT and zero columns up to a multiple of GC), so the loop has no branch.
-// Two workgroups share a CU (74 KB of LDS and at most 256 registers each), so one
-// workgroup's barrier and LDS staging overlap the other's MFMAs.
+// With GC = 16 two workgroups share a CU (74 KB of LDS and at most 256 registers each), so
+// one workgroup's barrier and LDS staging overlap the other's MFMAs; with GC = 32 a
+// workgroup takes a CU alone and waits at half as many barriers. The chunk width GC and the
+// LDS pitch GP are template parameters chosen at run time among the instantiated variants
+// (kGemmVariants; the autotuner times them).
 // Workgroups are dealt to the 8 XCDs round-robin; workgroup w takes triangle tile
 // (w % 8) * per + w / 8, so each XCD walks a contiguous run of tiles (mostly one tile row)
 // and shares that row's panel in its L2.
 constexpr int GT = 128;       // tile rows = tile cols
-constexpr int GC = 16;        // panel columns per chunk
+constexpr int GC = 16;        // panel columns per chunk of the default variant (and of RECT)
 // LDS pitch in doubles. A wave reads 16 rows x 4 columns per operand; with 64 four-byte banks
 // a half-wave (16 rows x 2 columns) touches 32 distinct doubles when 18 * row mod 32 spreads
 // the rows over the even double slots, so the reads are free of bank conflicts.
 constexpr int GP = 18;
-constexpr int GL = GT * (GC / 2) / NT;  // double2 loads per thread per side per chunk (4)
-constexpr int GR = NT / (GC / 2);       // rows staged per load round (32)
 constexpr int NXCD = 8;
 
 // Tile t of the upper triangle of a T x T tiling, row by row: row I holds (I, I..T-1) and
@@ -285,11 +286,14 @@ constexpr int64_t kRectGroup = 8;
 //     acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1]   (p < nrows, a < ncols),
 // over T row tiles (list positions) x TJ column tiles (nodes), without the symmetry; A rows
 // are gathered through the list (positions past it read its last entry, not stored).
-template <int PREC, bool RECT = false>
-__global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
-                                                          int64_t per, int64_t TJ = 0) {
-  __shared__ double As[2][GT * GP];
-  __shared__ double Bs[2][GT * GP];
+// GCt: panel columns per LDS chunk; GPt: LDS row pitch in doubles; WPC: workgroups per CU.
+template <int PREC, bool RECT = false, int GCt = GC, int GPt = GP, int WPC = 2>
+__global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
+                                                            int64_t per, int64_t TJ = 0) {
+  constexpr int GL = GT * (GCt / 2) / NT;  // double2 loads per thread per side per chunk
+  constexpr int GR = NT / (GCt / 2);       // rows staged per load round
+  __shared__ double As[2][GT * GPt];
+  __shared__ double Bs[2][GT * GPt];
   const int64_t w = blockIdx.x;
   const int64_t t = (w % NXCD) * per + w / NXCD;
   int64_t I, J;
@@ -314,10 +318,10 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
   const int l16 = lane & 15, lk = lane >> 4;
   const int64_t r0 = I * GT;
   const int64_t c0 = J * GT;
-  const int nch = g.r / GC;
+  const int nch = g.r / GCt;
 
   // This thread stages rows lrow + GR u, columns lcol + {0, 1} of each chunk.
-  const int lrow = tid / (GC / 2), lcol = 2 * (tid % (GC / 2));
+  const int lrow = tid / (GCt / 2), lcol = 2 * (tid % (GCt / 2));
   const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
   const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
   const int64_t ustep = GR * (int64_t)g.pld;
@@ -332,8 +336,8 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
   }
   double2 ra[GL], rb[GL];
   auto load = [&](int ch) {
-    // chunk ch: columns [ch GC, ch GC + GC) lie in column group (ch GC) / pld
-    const int64_t cb = (int64_t)((ch * GC) / g.pld) * g.gstride + (ch * GC) % g.pld;
+    // chunk ch: columns [ch GCt, ch GCt + GCt) lie in column group (ch GCt) / pld
+    const int64_t cb = (int64_t)((ch * GCt) / g.pld) * g.gstride + (ch * GCt) % g.pld;
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
       if constexpr (RECT)
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      const int o = (lrow + GR * u) * GP + lcol;
+      const int o = (lrow + GR * u) * GPt + lcol;
       As[buf][o] = ra[u].x;
       As[buf][o + 1] = ra[u].y;
       Bs[buf][o] = rb[u].x;
@@ -368,13 +372,13 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_kernel(LowRankArgs g, int6
     // the last chunk reloads itself (uniform, harmless) so the loop body has no branch
     load(ch + 1 < nch ? ch + 1 : ch);
 #pragma unroll
-    for (int k4 = 0; k4 < GC; k4 += 4) {
+    for (int k4 = 0; k4 < GCt; k4 += 4) {
       const int c = k4 + lk;
       double av[4], bv[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) av[s] = As[buf][(wr * 64 + s * 16 + l16) * GP + c];
+      for (int s = 0; s < 4; ++s) av[s] = As[buf][(wr * 64 + s * 16 + l16) * GPt + c];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = Bs[buf][(wc * 64 + q * 16 + l16) * GP + (c ^ 1)];
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[buf][(wc * 64 + q * 16 + l16) * GPt + (c ^ 1)];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -774,21 +778,31 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   }
   // Several blocks: the fused GEMM over the upper triangle of tiles (rows list and mask not
   // used; see lowrank_gemm_kernel for what the panel must hold).
+  if (a.variant < 0 || a.variant >= kGemmVariants) return hipErrorInvalidValue;
+  const int gc = a.variant < 2 ? 16 : 32;
   if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr ||
-      a.nrows != a.ncols || a.r % GC != 0 || a.pld % GC != 0)
+      a.nrows != a.ncols || a.r % gc != 0 || a.pld % gc != 0)
     return hipErrorInvalidValue;
   const int64_t T = (a.nrows + GT - 1) / GT;
   if (a.p_rows < T * GT) return hipErrorInvalidValue;
   const int64_t tiles = T * (T + 1) / 2;
   const int64_t per = (tiles + NXCD - 1) / NXCD;
   const unsigned grid = (unsigned)(per * NXCD);
-  if (a.S.prec == PREC_FP64) {
-    lowrank_gemm_kernel<PREC_FP64><<<grid, NT, 0, s>>>(a, T, per);
-  } else if (a.S.prec == PREC_HILO) {
-    lowrank_gemm_kernel<PREC_HILO><<<grid, NT, 0, s>>>(a, T, per);
-  } else {
-    lowrank_gemm_kernel<PREC_FP32><<<grid, NT, 0, s>>>(a, T, per);
-  }
+  auto go = [&](auto prec) {
+    constexpr int P = decltype(prec)::value;
+    switch (a.variant) {
+      case 0: lowrank_gemm_kernel<P, false, 16, 18, 2><<<grid, NT, 0, s>>>(a, T, per); break;
+      case 1: lowrank_gemm_kernel<P, false, 16, 20, 2><<<grid, NT, 0, s>>>(a, T, per); break;
+      case 2: lowrank_gemm_kernel<P, false, 32, 34, 1><<<grid, NT, 0, s>>>(a, T, per); break;
+      default: lowrank_gemm_kernel<P, false, 32, 36, 1><<<grid, NT, 0, s>>>(a, T, per); break;
+    }
+  };
+  if (a.S.prec == PREC_FP64)
+    go(std::integral_constant<int, PREC_FP64>{});
+  else if (a.S.prec == PREC_HILO)
+    go(std::integral_constant<int, PREC_HILO>{});
+  else
+    go(std::integral_constant<int, PREC_FP32>{});
   return hipGetLastError();
 }
 

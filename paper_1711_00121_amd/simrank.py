@@ -37,7 +37,7 @@ def default_config(**kw):
             v = _MODE[v] if isinstance(v, str) else v
         elif k == "gamma_form":
             v = _GAMMA[v] if isinstance(v, str) else v
-        elif k in ("prune", "fused_batch", "profile"):
+        elif k in ("prune", "fused_batch", "profile", "graphs"):
             v = int(bool(v))
         setattr(cfg, k, v)
     return cfg
@@ -280,6 +280,24 @@ class Context:
         L.check(self.lib.backward(self.h, a.numel(), _dev(a), _dev(b), _dev(g), _dev(dw)),
                 "backward")
         return dw
+
+    def time_fused(self, variant, blocks, reps=2):
+        """Milliseconds of one fused pass over ``blocks`` deferred blocks with GEMM variant
+        ``variant`` at the current size, and of one block's corrections (sr_time_fused)."""
+        g = C.c_double()
+        c = C.c_double()
+        L.check(self.lib.sr_time_fused(self.h, int(variant), int(blocks), int(reps), C.byref(g),
+                                       C.byref(c)), "sr_time_fused")
+        return g.value, c.value
+
+    def set_tuning(self, batch_chunk, variant):
+        L.check(self.lib.sr_set_tuning(self.h, int(batch_chunk), int(variant)), "sr_set_tuning")
+        self.cfg.batch_chunk = int(batch_chunk)
+
+    def tune(self, **kw):
+        """Autotunes the fused batch pass (see paper_1711_00121_amd.tune)."""
+        from .tune import tune
+        return tune(self, **kw)
 
     def profile(self, enable=True):
         L.check(self.lib.sr_profile(self.h, int(bool(enable))), "sr_profile")
