@@ -77,6 +77,7 @@ struct sr_ctx {
            *Ahat = nullptr, *Bhat = nullptr;
   int W = 0;
   int32_t* rowlist = nullptr;
+  int32_t* rowlist2 = nullptr;  // rows filled by the transpose copy (launch_aff_mirror)
   int32_t* d_ids = nullptr;  // staging for query ids (capacity ids_cap)
   int64_t ids_cap = 0;
   int64_t* d_cnt = nullptr;
@@ -730,7 +731,8 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
                           s, ctx->pairs, ctx->node_cap));
   }
   if (ft) return SR_OK;  // applied later by the batch's fused pass
-  if (prune) HC(launch_aff_compact(aa, ctx->Ahat, ctx->Bhat, ctx->rowlist, ctx->d_cnt, s));
+  if (prune)
+    HC(launch_aff_compact(aa, ctx->Ahat, ctx->Bhat, ctx->rowlist, ctx->rowlist2, ctx->d_cnt, s));
 
   LowRankArgs la{};
   la.S = ctx->S;
@@ -754,6 +756,7 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
     if (la.r > 32) la.r = ctx->pld;
   }
   HC(run_lowrank(ctx, la));
+  if (prune) HC(launch_aff_mirror(ctx->S, ctx->rowlist, ctx->rowlist2, ctx->d_cnt, s));
   ctx->last_r = 2 * (K + 1);
   ctx->last_aff = prune;
 
@@ -1006,6 +1009,7 @@ sr_status sr_destroy(sr_ctx* ctx) {
   uint32_t* bb[] = {ctx->suppI, ctx->suppJ, ctx->Abits, ctx->Bbits, ctx->Ahat, ctx->Bhat};
   for (uint32_t* p : bb) (void)hipFree(p);
   (void)hipFree(ctx->rowlist);
+  (void)hipFree(ctx->rowlist2);
   (void)hipFree(ctx->d_ids);
   (void)hipFree(ctx->corr_tab);
   heavy_free(ctx->hin);
@@ -1156,6 +1160,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   IC(dalloc(&ctx->Ahat, ctx->W));
   IC(dalloc(&ctx->Bhat, ctx->W));
   IC(dalloc(&ctx->rowlist, node_cap));
+  IC(dalloc(&ctx->rowlist2, node_cap));
   IC(dalloc(&ctx->d_cnt, 8));
   IC(dalloc(&ctx->d_max, 1));
   IC(dalloc(&ctx->d_sum, 4));

@@ -225,11 +225,17 @@ struct AffArgs {
 // B_0 |= supp S[j, :] when f2, and j joins A_0 and B_0.
 hipError_t launch_aff_level0(const AffArgs& a, const uint32_t* suppJ, int f2, int32_t j,
                              hipStream_t s);
-// A_hat = A_0 | A_K, B_hat = B_0 | B_K into Ahat/Bhat; rows = ascending list of
-// A_hat | B_hat, entry (node << 2) | (in A_hat << 1) | (in B_hat);
-// cnt[0..3] = |A_hat|, |B_hat|, |A_hat & B_hat|, |rows|.
+// A_hat = A_0 | A_K, B_hat = B_0 | B_K into Ahat/Bhat; rows = ascending list of the rows the
+// streaming update takes, entry (node << 2) | (in A_hat << 1) | (in B_hat): A_hat | B_hat, or,
+// when the smaller set X of the two has at most n / 16 nodes, X alone, with the other set's
+// nodes outside X listed in mrows for launch_aff_mirror.
+// cnt[0..3] = |A_hat|, |B_hat|, |A_hat & B_hat|, |rows|; cnt[6] = |mrows| (0: none).
 hipError_t launch_aff_compact(const AffArgs& a, uint32_t* Ahat, uint32_t* Bhat,
-                              int32_t* rows, int64_t* cnt, hipStream_t s);
+                              int32_t* rows, int32_t* mrows, int64_t* cnt, hipStream_t s);
+// After the streaming update of the listed rows: S[y][x] = S[x][y] for the listed x and the
+// mirrored y (nothing when cnt[6] == 0).
+hipError_t launch_aff_mirror(SView S, const int32_t* rows, const int32_t* mrows,
+                             const int64_t* cnt, hipStream_t s);
 // Ascending list of the set bits of bm (n bits) into out; *cnt receives the count.
 hipError_t launch_bits_to_list(const uint32_t* bm, int64_t n, int32_t W, int32_t* out,
                                int64_t* cnt, hipStream_t s);

@@ -181,6 +181,37 @@ def test_aff_sets_bit_exact_mid_size():
         ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "hilo"])
+def test_small_affected_area_uses_the_transpose_copy(prec):
+    """Updates into sinks without out-edges have A_hat = {j}: only row j goes through the
+    streaming update and the pairs (y, j) are copied from (j, y). S matches the oracle's
+    Inc-uSR (K-matched) and the recompute, and stays exactly symmetric."""
+    n, K = 500, 15
+    s, d = W.chung_lu(n, 2500, seed=931)
+    outdeg = np.bincount(s, minlength=n)
+    indeg = np.bincount(d, minlength=n)
+    sinks = [x for x in range(n) if outdeg[x] == 0 and indeg[x] >= 2][:3]
+    assert len(sinks) == 3
+    es = set(zip(s.tolist(), d.tolist()))
+    ups = [(next(a for a in range(n) if a != j and (a, j) not in es), j, 1) for j in sinks[:2]]
+    ups.append((next(a for (a, b) in sorted(es) if b == sinks[2]), sinks[2], -1))
+    ctx = ctx_for(n, s, d, s_prec=prec, K=K)
+    tr = EdgeTracker(n, s, d)
+    S_or = O.fixed_point(tr.Q(), C)
+    for (i, j, op) in ups:
+        cs, cd = tr.arrays()
+        Qd = Gr.transition_matrix(n, cs, cd, dense=True)
+        S_or, _ = OI.inc_usr(Qd, S_or, np.bincount(cd, minlength=n), i, j, C, K, op=op)
+        st = ctx.apply_edge_update(i, j, op, stats=True)
+        tr.apply(i, j, op)
+        assert st["aff_A"] == 1 and st["pairs"] == 2 * st["aff_B"] - 1
+        S = ctx.S().cpu().numpy()
+        assert np.array_equal(S, S.T)
+        assert maxabs(S, S_or) < (1e-12 if prec == "fp64" else 1e-9)
+        assert maxabs(S, tr.exact(C)) < TOL
+    ctx.close()
+
+
 def test_node_insertion_cases_unit():
     n = 300
     s, d = W.chung_lu(n, 1200, seed=51)
