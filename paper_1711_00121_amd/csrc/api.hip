@@ -2493,7 +2493,7 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   const double C = ctx->cfg.C;
   hipStream_t s = ctx->stream;
   const int64_t ldi = (n + 63) / 64 * 64;
-  double *Sig = nullptr, *T = nullptr, *U = nullptr, *G = nullptr, *dq = nullptr;
+  double *Sig = nullptr, *T = nullptr, *U = nullptr, *G = nullptr, *dq = nullptr, *qv = nullptr;
   int32_t* se = nullptr;
   auto cleanup = [&]() {
     (void)hipFree(Sig);
@@ -2501,11 +2501,13 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
     (void)hipFree(U);
     (void)hipFree(G);
     (void)hipFree(dq);
+    (void)hipFree(qv);
     (void)hipFree(se);
   };
   if (dalloc(&Sig, n * ldi) != hipSuccess || dalloc(&T, n * ldi) != hipSuccess ||
       dalloc(&U, n * ldi) != hipSuccess || dalloc(&G, n * ldi) != hipSuccess ||
       dalloc(&dq, (int64_t)ctx->g.in.idx.size()) != hipSuccess ||
+      dalloc(&qv, (int64_t)ctx->g.out.idx.size()) != hipSuccess ||
       dalloc(&se, (int64_t)ctx->slot_edge0.size()) != hipSuccess) {
     cleanup();
     return SR_ENOMEM;
@@ -2517,6 +2519,7 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   const std::vector<int32_t> se_host = ctx->updated ? slot_edges(ctx) : ctx->slot_edge0;
   hipError_t e = hipMemcpy(se, se_host.data(), se_host.size() * 4, hipMemcpyHostToDevice);
   // Gs = G + G^T: Sig = Lam + Lam^T solves Sig = Gs + C Q^T Sig Q (Lam = G + C Q^T Lam Q).
+  if (e == hipSuccess) e = launch_qt_values(q, out, n, qv, s);
   if (e == hipSuccess) e = hipMemsetAsync(G, 0, (size_t)n * ldi * 8, s);
   if (e == hipSuccess) e = launch_scatter_pairs_sym(G, n, npairs, a_dev, b_dev, g_dev, s);
   if (e == hipSuccess) e = hipMemcpyAsync(Sig, G, (size_t)n * ldi * 8,
@@ -2525,11 +2528,11 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   for (int it = 0; it < ctx->cfg.init_max_iter && e == hipSuccess; ++it) {
     e = hipMemsetAsync(ctx->d_max, 0, 8, s);
     if (e == hipSuccess) e = profiled(ctx, [&]() {
-      return launch_spmm_qt_rows(q, out, n, Sig, U, 1.0, nullptr, nullptr, nullptr, s);
+      return launch_spmm_qt_rows(out, qv, n, Sig, U, 1.0, nullptr, nullptr, nullptr, s);
     });
     if (e == hipSuccess) e = launch_transpose(n, U, T, s);
     if (e == hipSuccess) e = profiled(ctx, [&]() {
-      return launch_spmm_qt_rows(q, out, n, T, U, C, G, Sig, ctx->d_max, s);
+      return launch_spmm_qt_rows(out, qv, n, T, U, C, G, Sig, ctx->d_max, s);
     });
     if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_max, ctx->d_max, 8, hipMemcpyDeviceToHost,
                                             s);

@@ -322,9 +322,13 @@ hipError_t launch_delta_col(const double* P, int pld, int r, int64_t n, int32_t 
 hipError_t launch_scatter_pairs_sym(double* G, int64_t n, int64_t np, const int32_t* a,
                                     const int32_t* b, const double* g, hipStream_t s);
 // Y[b][:] = scale * (Q^T X)[b][:] (+ Gadd[b][:] when Gadd != null); maxdiff vs prev as above.
-hipError_t launch_spmm_qt_rows(const DevQ& q, const DevAdj& out, int64_t n, const double* X,
+// qv: the values Q[a][b] of the out-list slots (launch_qt_values).
+hipError_t launch_spmm_qt_rows(const DevAdj& out, const double* qv, int64_t n, const double* X,
                                double* Y, double scale, const double* Gadd, const double* prev,
                                unsigned long long* maxdiff, hipStream_t s);
+// qv[p] = Q[a][b] for every out-list slot p of the rows b < n (a the slot's node).
+hipError_t launch_qt_values(const DevQ& q, const DevAdj& out, int64_t n, double* qv,
+                            hipStream_t s);
 // Per sink x and in-list slot p (source y): dq[p] = C * <Sig[x, :], T[y, :]>, then
 // dw[slot_edge[p]] = (dq[p] - sum_p' Q[x][y_p'] dq[p']) / W_x (W_x = in-degree unweighted).
 hipError_t launch_edge_grad(const DevQ& q, int64_t n, const double* Sig, const double* T,

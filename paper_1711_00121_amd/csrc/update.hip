@@ -76,6 +76,25 @@ __device__ __forceinline__ void sput(const SView& S, int64_t off, double t) {
   }
 }
 
+// Stores an entry back exactly as it was loaded.
+template <int PREC, bool NT = false>
+__device__ __forceinline__ void sraw(const SView& S, int64_t off, const Raw<PREC>& x) {
+  if constexpr (PREC == PREC_FP64) {
+    if constexpr (NT) __builtin_nontemporal_store(x.d, S.d + off);
+    else S.d[off] = x.d;
+  } else if constexpr (PREC == PREC_HILO) {
+    if constexpr (NT) {
+      const nt_float2 v = {x.hl.x, x.hl.y};
+      __builtin_nontemporal_store(v, reinterpret_cast<nt_float2*>(S.hl + off));
+    } else {
+      S.hl[off] = x.hl;
+    }
+  } else {
+    if constexpr (NT) __builtin_nontemporal_store(x.h, S.hi + off);
+    else S.hi[off] = x.h;
+  }
+}
+
 // Streaming update for one block (r <= RC panel columns). Workgroup = strip of SC columns whose
 // panel rows live in LDS for the whole strip; the workgroup walks row tiles of TR listed rows,
 // wave w taking rows [16 w, 16 w + 16) of each tile against the strip's SC columns (ST
@@ -94,7 +113,7 @@ constexpr int ST = SC / 16;
 // non-temporal loads of the same entries were 30-50% slower.
 constexpr bool kStripNTStore = true;
 
-template <int PREC, bool MASK, bool HASROWS>
+template <int PREC, bool MASK, bool HASROWS, bool FULL = false>
 __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
   __shared__ double lcol[SC * LP];
   const int tid = threadIdx.x;
@@ -221,11 +240,32 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
       const int rB = MASK ? (e0[1 + v] & 1) : 1;
       // pairs in A_hat x B_hat u B_hat x A_hat, as a bit per slice
       const int on = (rok ? cin : 0) & ((rA ? cB : 0) | (rB ? cA : 0));
+      if constexpr (FULL) {
+        // a slice with any pair of this row is written whole: its other entries go back
+        // exactly as loaded, so each row's line is written in full
+        int whole = 0;
 #pragma unroll
-      for (int t = 0; t < ST; ++t) {
-        if (!((on >> t) & 1)) continue;
-        const int64_t b = c0 + t * 16 + l16;
-        sput<PREC, kStripNTStore>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
+        for (int t = 0; t < ST; ++t) {
+          const uint64_t bal = __ballot((on >> t) & 1);
+          whole |= (((bal >> (16 * lk)) & 0xFFFFull) != 0 ? 1 : 0) << t;
+        }
+        whole &= (rok ? cin : 0);
+#pragma unroll
+        for (int t = 0; t < ST; ++t) {
+          if (!((whole >> t) & 1)) continue;
+          const int64_t off = row * g.S.ld + c0 + t * 16 + l16;
+          if ((on >> t) & 1)
+            sput<PREC, kStripNTStore>(g.S, off, sval<PREC>(x0[t][v]) + acc[t][v]);
+          else
+            sraw<PREC, kStripNTStore>(g.S, off, x0[t][v]);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < ST; ++t) {
+          if (!((on >> t) & 1)) continue;
+          const int64_t b = c0 + t * 16 + l16;
+          sput<PREC, kStripNTStore>(g.S, row * g.S.ld + b, sval<PREC>(x0[t][v]) + acc[t][v]);
+        }
       }
     }
 #pragma unroll
@@ -716,10 +756,12 @@ static void cols_launch(const LowRankArgs& a, dim3 grid, hipStream_t s) {
     lowrank_cols_kernel<KS, false><<<grid, NT, 0, s>>>(a);
 }
 
+// Listed rows store whole 16-column slices (measured at n = 92.5k, A_hat ~ B_hat ~ 0.64 n:
+// 17.6 ms instead of 18.4 ms with per-entry masked stores, although more bytes are written).
 template <int PREC, bool MASK>
 static void strip_launch(const LowRankArgs& a, dim3 grid, hipStream_t s) {
   if (a.rows)
-    lowrank_strip_kernel<PREC, MASK, true><<<grid, NT, 0, s>>>(a);
+    lowrank_strip_kernel<PREC, MASK, true, MASK><<<grid, NT, 0, s>>>(a);
   else
     lowrank_strip_kernel<PREC, MASK, false><<<grid, NT, 0, s>>>(a);
 }
