@@ -41,6 +41,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("ΔS pair-updates/s + edge updates/s at n=50k vs plain GPU path; % HBM peak")
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 C = 0.6
 # the oracle's all-core leg uses at most this many host threads (a GPU machine's CPU share)
 MAX_ORACLE_WORKERS = 16
@@ -65,6 +66,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0,
                     help="low-rank blocks per fused pass (0: the autotuner picks it, and the "
                          "GEMM tile variant, at the size after the warm-up)")
+    ap.add_argument("--update-prec", default="fp64", choices=["fp64", "fp32"],
+                    help="batch: arithmetic of the fused passes (fp32: float32 matrix cores, "
+                         "sums added to the store in float64)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="plain launches instead of replaying captured series chains")
     ap.add_argument("--no-fused", action="store_true")
@@ -154,7 +158,7 @@ def run_batch(args):
                   split_rows=args.split_rows,
                   edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
                   fused_batch=not args.no_fused, batch_chunk=args.chunk or 64,
-                  graphs=not args.no_graphs)
+                  graphs=not args.no_graphs, update_prec=args.update_prec)
     torch.cuda.synchronize()
     log(f"bench: init (S by fixed point on device) {time.perf_counter() - t0:.1f}s")
 
@@ -241,11 +245,12 @@ def run_batch(args):
                                   [int(x) for x in g.integers(n_last, size=56)]))
         got = torch.stack([ctx.query_column(x) for x in rows])
         ref = Context(n, s, d, C=C, K=K, s_prec="fp64", node_cap=counts[-1] + 64,
+                      update_prec="fp64",
                       split_rows=args.split_rows,
                       edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
                       fused_batch=not args.no_fused, batch_chunk=chunk,
                       graphs=not args.no_graphs)
-        ref.set_tuning(chunk, tuning["variant"] if tuning else 0)
+        ref.set_tuning(chunk, 0)
         for t in range(args.warmup + args.steps):
             ref.apply_batch(*batches[t])
             log(f"bench: float64-store replay, batch {t} done")
@@ -304,10 +309,12 @@ def run_batch(args):
 
     if passes:
         achieved = flops / (kern_ms / 1e3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+        peak = FP32_PEAK_TFLOPS if args.update_prec == "fp32" else FP64_PEAK_TFLOPS
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": traffic("lowrank_gemm_kernel", counters_for(args, cfg["name"])),
-                "kernel": "lowrank_gemm_kernel (fused batch pass)",
+                "kernel": "lowrank_gemm_kernel (fused batch pass)" if args.update_prec == "fp64"
+                          else "lowrank_gemm_f32_kernel (fused batch pass, float32 matrix cores)",
                 "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                 "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
                                "block, n the node count of its batch"}
@@ -326,10 +333,11 @@ def run_batch(args):
         cpu = cpu_baseline_columns(fn, fs, fd, args.cpu_seconds,
                                    "the graph after the timed batches")
     out = common(args, cfg, pairs / dt, "pair-updates/s", dt, args.steps,
+                 dtype="f64" if args.update_prec == "fp64" else "f32 fused passes, f64 series",
                  extra_cfg={"s_store": "f32 value + f32 compensation",
                             "max_batch": args.max_batch, "batch_chunk": chunk,
                             "gemm_variant": tuning["variant"] if tuning else 0,
-                            "graphs": not args.no_graphs,
+                            "graphs": not args.no_graphs, "update_prec": args.update_prec,
                             "fused": not args.no_fused, "n_first": n_first, "n_last": n_last,
                             "m_last": m_last})
     out.update({

@@ -62,6 +62,13 @@ enum {
   SR_GAMMA_CLOSED = 0, /* Theorem 3 / Theorem 9 / Table 2 closed form (2 columns of S)     */
   SR_GAMMA_DIRECT = 1  /* Theorem 2 direct form w = Q S v + (v^T S v / 2) u                */
 };
+/* Arithmetic of the fused batch passes (the low-rank update of S by many blocks at once). */
+enum {
+  SR_UPDATE_FP64 = 0, /* float64 matrix cores                                               */
+  SR_UPDATE_FP32 = 1  /* float32 matrix cores: the panel rounded to float, products and sums
+                         in float, added to S in float64 (the value + compensation store
+                         keeps the sum); the series vectors and gamma stay float64          */
+};
 /* What query_column returns. */
 enum { SR_COL_S = 0, SR_COL_DELTA = 1 };
 
@@ -89,6 +96,8 @@ typedef struct sr_config {
   int32_t graphs;        /* 1: fused batches capture each block's K-step series chain as a HIP
                             graph (one per panel slot of a chunk, kept while the node count
                             and the graph's row tiers stay) and replay it; 0: plain launches */
+  int32_t update_prec;   /* SR_UPDATE_FP64 | SR_UPDATE_FP32: the fused passes' arithmetic    */
+  int32_t reserved;      /* set to 0                                                        */
 } sr_config;
 
 /* Per-update statistics (filled when a non-null pointer is passed; the call then
@@ -326,8 +335,9 @@ sr_status sr_profile(sr_ctx* ctx, int32_t enable);
 sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
 
 /* Tuning: times the fused pass of apply_batch at the context's current node count with the
- * GEMM tile variant `variant` (0 .. 3: panel columns per LDS chunk and LDS pitch in doubles,
- * (16, 18), (16, 20), (32, 34), (32, 36)) over `blocks` deferred blocks, and the incremental
+ * GEMM tile variant `variant` (0 .. 3: float64 matrix cores with panel columns per LDS chunk
+ * and LDS pitch in doubles, (16, 18), (16, 20), (32, 34), (32, 36); 4: float32 matrix cores,
+ * as SR_UPDATE_FP32) over `blocks` deferred blocks, and the incremental
  * corrections one deferred block makes for blocks / 2 later slots of its chunk: *gemm_ms and
  * *corr_ms are the mean of `reps` launches after one warm-up. The pass runs on a zero panel,
  * so S keeps its values. Dense mode; allocates a zero panel of n x blocks 2(K+1) (rounded up
@@ -346,6 +356,11 @@ sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant);
  * operand and accumulator lane layout the update kernel assumes. Asynchronous on hip_stream. */
 sr_status sr_mfma_layout_probe(const double* a_dev, const double* b_dev, double* out_dev,
                                void* hip_stream);
+
+/* Diagnostics: the same for v_mfma_f32_16x16x4f32 with float operands and accumulators (the
+ * float32 fused pass relies on its layout). */
+sr_status sr_mfma_layout_probe_f32(const float* a_dev, const float* b_dev, float* out_dev,
+                                   void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,7 @@ SR_S_FP64, SR_S_FP32_HILO, SR_S_FP32 = 0, 1, 2
 SR_DENSE, SR_COLUMN = 0, 1
 SR_GAMMA_CLOSED, SR_GAMMA_DIRECT = 0, 1
 SR_COL_S, SR_COL_DELTA = 0, 1
+SR_UPDATE_FP64, SR_UPDATE_FP32 = 0, 1
 
 
 class sr_config(C.Structure):
@@ -38,6 +39,8 @@ class sr_config(C.Structure):
         ("split_rows", C.c_int32),
         ("profile", C.c_int32),
         ("graphs", C.c_int32),
+        ("update_prec", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -107,6 +110,7 @@ SIGNATURES = {
     "sr_destroy": (C.c_int, [P]),
     "sr_strerror": (C.c_char_p, [C.c_int]),
     "sr_mfma_layout_probe": (C.c_int, [P, P, P, P]),
+    "sr_mfma_layout_probe_f32": (C.c_int, [P, P, P, P]),
     "sr_profile": (C.c_int, [P, C.c_int32]),
     "sr_time_fused": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)]),

@@ -1044,6 +1044,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   if (!(cfg.C > 0.0 && cfg.C < 1.0) || cfg.K < 0 || cfg.K > 200 || cfg.K_ps < 0 ||
       cfg.s_prec < 0 || cfg.s_prec > 2 || (cfg.mode != SR_DENSE && cfg.mode != SR_COLUMN) ||
       cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0 ||
+      cfg.update_prec < 0 || cfg.update_prec > 1 ||
       (cfg.split_rows != 0 && cfg.split_rows < kMedium))
     return SR_EINVAL;
   if (cfg.split_rows == 0) cfg.split_rows = kSplitRows;
@@ -1067,6 +1068,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   sr_ctx* ctx = new (std::nothrow) sr_ctx();
   if (!ctx) return SR_ENOMEM;
   ctx->cfg = cfg;
+  ctx->gemm_variant = cfg.update_prec == SR_UPDATE_FP32 ? kGemmF32 : 0;
   ctx->hin.split = ctx->hout.split = cfg.split_rows;
   ctx->profiling = cfg.profile != 0;
   ctx->stream = (hipStream_t)hip_stream;
@@ -1923,6 +1925,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     la.rows = nullptr;
     la.nrows = n_new;
     la.ncols = n_new;
+    la.fused = 1;
     la.variant = ctx->gemm_variant;
     HC(run_lowrank(ctx, la));
     ++passes;
@@ -2627,6 +2630,7 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
   la.r = (int)cols;
   la.nrows = n;
   la.ncols = n;
+  la.fused = 1;
   la.variant = variant;
   // one deferred block's corrections for `slots` later slots of its chunk (zero weights)
   CorrSlots cs{};
@@ -2680,6 +2684,14 @@ sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant) {
   }
   ctx->gemm_variant = variant;
   return SR_OK;
+}
+
+sr_status sr_mfma_layout_probe_f32(const float* a_dev, const float* b_dev, float* out_dev,
+                                   void* hip_stream) {
+  if (!a_dev || !b_dev || !out_dev) return SR_EINVAL;
+  return launch_mfma_probe_f32(a_dev, b_dev, out_dev, (hipStream_t)hip_stream) == hipSuccess
+             ? SR_OK
+             : SR_EHIP;
 }
 
 sr_status sr_mfma_layout_probe(const double* a_dev, const double* b_dev, double* out_dev,

@@ -251,8 +251,8 @@ hipError_t launch_bits_or(const uint32_t* a, const uint32_t* b, uint32_t* dst, i
 //       S[a][b] += sum_{c < r} P[a][c] * P[b][c ^ 1]
 // P rows hold (xi_k, eta_k) pairs, so the sum is sum_k xi_k[a] eta_k[b] + eta_k[a] xi_k[b].
 // For several blocks the panel holds their pairs side by side (r = 2 (K+1) * blocks).
-// With r > 32 and no row list or mask (fused passes) the update runs as a GEMM over the
-// upper triangle of 128 x 128 tiles; it then needs nrows == ncols, r and pld multiples of 32,
+// Fused passes (fused = 1, no row list or mask) run as a GEMM over the upper triangle of
+// 128 x 128 tiles, whatever r; it then needs nrows == ncols, r and pld multiples of 32,
 // p_rows >= nrows rounded up to 128, with panel rows [nrows, p_rows) zero.
 // Column-output form (out != null): out[t][b] = sum_c P[rows[t]][c] * P[b][c ^ 1] as float32
 // (row t of out at out + t * ld_out), no mask; S is not touched.
@@ -273,10 +273,13 @@ struct LowRankArgs {
   int64_t gstride;    // doubles between consecutive groups of pld columns (block-major
                       // batch panel); column c of row a is at (c / pld) gstride + a pld + c % pld
   double* acc_out;    // launch_lowrank_acc: float64 output, ld_out doubles per row
-  int32_t variant;    // fused GEMM: tile variant (0 .. kGemmVariants - 1): panel columns per
-                      // LDS chunk and LDS pitch, (16, 18), (16, 20), (32, 34), (32, 36)
+  int32_t fused;      // 1: a fused batch pass, always the symmetric GEMM (even at r = 32)
+  int32_t variant;    // fused GEMM: tile variant (0 .. kGemmVariants - 1): float64 matrix
+                      // cores with panel columns per LDS chunk and LDS pitch (16, 18),
+                      // (16, 20), (32, 34), (32, 36); kGemmF32: float32 matrix cores
 };
-constexpr int kGemmVariants = 4;
+constexpr int kGemmF32 = 4;
+constexpr int kGemmVariants = 5;
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
 // Column mode, batches: acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1] for list
 // positions p < nrows and nodes a < ncols (the deferred blocks' Delta S[a][rows[p]], eq (71)),
@@ -358,5 +361,6 @@ hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int
 hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
 hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);
+hipError_t launch_mfma_probe_f32(const float* a, const float* b, float* out, hipStream_t s);
 
 }  // namespace sr

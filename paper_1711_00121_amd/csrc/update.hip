@@ -496,6 +496,122 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
   }
 }
 
+// Fused batch pass on the FP32 matrix cores (tile variant kGemmF32): the same tiling and
+// symmetric epilogue as lowrank_gemm_kernel, with the panel rounded to float when it is
+// staged (32 columns per chunk, LDS pitch 33 floats: a half-wave's 16 rows x 2 columns fall on
+// 32 distinct banks) and v_mfma_f32_16x16x4f32, whose accumulator slot v of lane l holds row
+// 4 (l / 16) + v of the 16 x 16 block (the float64 instruction's is 4 v + l / 16). The float
+// sum is added to the stored value in float64 and stored as the store's precision keeps it
+// (value + compensation re-split), so long streams accumulate without loss, but each pass
+// carries the rounding of float products and sums.
+constexpr int GCF = 32;
+constexpr int GPF = GCF + 1;
+typedef float fl4 __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+__global__ __launch_bounds__(NT, 2) void lowrank_gemm_f32_kernel(LowRankArgs g, int64_t T,
+                                                              int64_t per) {
+  constexpr int GL = GT * (GCF / 2) / NT;  // double2 loads per thread per side per chunk (8)
+  constexpr int GR = NT / (GCF / 2);       // rows staged per load round (16)
+  __shared__ float As[2][GT * GPF];
+  __shared__ float Bs[2][GT * GPF];
+  const int64_t w = blockIdx.x;
+  const int64_t t = (w % NXCD) * per + w / NXCD;
+  if (t >= T * (T + 1) / 2) return;
+  int64_t I, J;
+  tri_tile(t, T, I, J);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int64_t r0 = I * GT;
+  const int64_t c0 = J * GT;
+  const int nch = g.r / GCF;
+  const int lrow = tid / (GCF / 2), lcol = 2 * (tid % (GCF / 2));
+  const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
+  const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
+  const int64_t ustep = GR * (int64_t)g.pld;
+  double2 ra[GL], rb[GL];
+  auto load = [&](int ch) {
+    const int64_t cb = (int64_t)((ch * GCF) / g.pld) * g.gstride + (ch * GCF) % g.pld;
+#pragma unroll
+    for (int u = 0; u < GL; ++u) {
+      ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
+      rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < GL; ++u) {
+      const int o = (lrow + GR * u) * GPF + lcol;
+      As[buf][o] = (float)ra[u].x;
+      As[buf][o + 1] = (float)ra[u].y;
+      Bs[buf][o] = (float)rb[u].x;
+      Bs[buf][o + 1] = (float)rb[u].y;
+    }
+  };
+  fl4 acc[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[s][q] = fl4{0.0f, 0.0f, 0.0f, 0.0f};
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    load(ch + 1 < nch ? ch + 1 : ch);
+#pragma unroll
+    for (int k4 = 0; k4 < GCF; k4 += 4) {
+      const int c = k4 + lk;
+      float av[4], bv[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) av[s] = As[buf][(wr * 64 + s * 16 + l16) * GPF + c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[buf][(wc * 64 + q * 16 + l16) * GPF + (c ^ 1)];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[q], acc[s][q], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    store(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue as lowrank_gemm_kernel's, rows 4 lk + v of each 16 x 16 block
+  const bool diag = I == J;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    Raw<PREC> x[4][4], y[4][4];
+    int on[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t a = r0 + wr * 64 + s * 16 + 4 * lk + v;
+        const int64_t b = c0 + wc * 64 + q * 16 + l16;
+        on[q][v] = a < g.nrows && b < g.ncols;
+        const int64_t da = on[q][v] ? a * g.S.ld + b : 0;
+        const int64_t ma = on[q][v] ? b * g.S.ld + a : 0;
+        sload<PREC>(g.S, da, x[q][v]);
+        sload<PREC>(g.S, ma, y[q][v]);
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (!on[q][v]) continue;
+        const int64_t a = r0 + wr * 64 + s * 16 + 4 * lk + v;
+        const int64_t b = c0 + wc * 64 + q * 16 + l16;
+        const double d = (double)acc[s][q][v];
+        if (!diag || a <= b) sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + d);
+        if (!diag || a < b) sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(y[q][v]) + d);
+      }
+  }
+}
+
 __global__ __launch_bounds__(256) void delta_col_kernel(const double* __restrict__ P, int pld,
                                                        int r, int64_t n, int32_t x,
                                                        double* __restrict__ out) {
@@ -769,7 +885,7 @@ static void strip_launch(const LowRankArgs& a, dim3 grid, hipStream_t s) {
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   if (a.ncols <= 0 || (a.nrows_dev == nullptr && a.nrows <= 0)) return hipSuccess;
   const int64_t nrows_bound = a.nrows_dev ? (a.rows ? a.ncols : a.nrows) : a.nrows;
-  if (a.r > RC && (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr)) {
+  if (!a.fused && a.r > RC && (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr)) {
     // one streaming pass per 32 panel columns (pairs never straddle a pass)
     if (a.out) return hipErrorInvalidValue;
     for (int c = 0; c < a.r; c += RC) {
@@ -781,7 +897,7 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     }
     return hipSuccess;
   }
-  if (a.r <= RC) {
+  if (a.r <= RC && !a.fused) {
     const int64_t strips = (a.ncols + SC - 1) / SC;
     const int64_t rtiles = (nrows_bound + TR - 1) / TR;
     int64_t gy = (4096 + strips - 1) / strips;
@@ -818,10 +934,11 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     }
     return hipGetLastError();
   }
-  // Several blocks: the fused GEMM over the upper triangle of tiles (rows list and mask not
-  // used; see lowrank_gemm_kernel for what the panel must hold).
+  // Fused passes, and several blocks without a row list: the GEMM over the upper triangle of
+  // tiles, which writes (a, b) and (b, a) from one sum so S stays exactly symmetric (rows
+  // list and mask not used; see lowrank_gemm_kernel for what the panel must hold).
   if (a.variant < 0 || a.variant >= kGemmVariants) return hipErrorInvalidValue;
-  const int gc = a.variant < 2 ? 16 : 32;
+  const int gc = a.variant < 2 ? 16 : 32;  // the float32 variant stages 32 columns too
   if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr ||
       a.nrows != a.ncols || a.r % gc != 0 || a.pld % gc != 0)
     return hipErrorInvalidValue;
@@ -833,6 +950,7 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   auto go = [&](auto prec) {
     constexpr int P = decltype(prec)::value;
     switch (a.variant) {
+      case kGemmF32: lowrank_gemm_f32_kernel<P><<<grid, NT, 0, s>>>(a, T, per); break;
       case 0: lowrank_gemm_kernel<P, false, 16, 18, 2><<<grid, NT, 0, s>>>(a, T, per); break;
       case 1: lowrank_gemm_kernel<P, false, 16, 20, 2><<<grid, NT, 0, s>>>(a, T, per); break;
       case 2: lowrank_gemm_kernel<P, false, 32, 34, 1><<<grid, NT, 0, s>>>(a, T, per); break;
@@ -878,6 +996,21 @@ __global__ __launch_bounds__(64) void mfma_probe_kernel(const double* a_in, cons
 
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s) {
   mfma_probe_kernel<<<1, 64, 0, s>>>(a, b, out);
+  return hipGetLastError();
+}
+
+// The same check for v_mfma_f32_16x16x4f32 (float operands and accumulators).
+typedef float f32x4_acc __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(64) void mfma_probe_f32_kernel(const float* a_in, const float* b_in,
+                                                            float* out) {
+  const int lane = threadIdx.x;
+  f32x4_acc c = {0.0f, 0.0f, 0.0f, 0.0f};
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a_in[lane], b_in[lane], c, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) out[lane * 4 + v] = c[v];
+}
+
+hipError_t launch_mfma_probe_f32(const float* a, const float* b, float* out, hipStream_t s) {
+  mfma_probe_f32_kernel<<<1, 64, 0, s>>>(a, b, out);
   return hipGetLastError();
 }
 

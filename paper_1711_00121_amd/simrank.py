@@ -12,6 +12,7 @@ from . import _lib as L
 _PREC = {"fp64": L.SR_S_FP64, "hilo": L.SR_S_FP32_HILO, "fp32": L.SR_S_FP32}
 _MODE = {"dense": L.SR_DENSE, "column": L.SR_COLUMN}
 _GAMMA = {"closed": L.SR_GAMMA_CLOSED, "direct": L.SR_GAMMA_DIRECT}
+_UPDATE = {"fp64": L.SR_UPDATE_FP64, "fp32": L.SR_UPDATE_FP32}
 
 
 def _i32(a):
@@ -37,6 +38,8 @@ def default_config(**kw):
             v = _MODE[v] if isinstance(v, str) else v
         elif k == "gamma_form":
             v = _GAMMA[v] if isinstance(v, str) else v
+        elif k == "update_prec":
+            v = _UPDATE[v] if isinstance(v, str) else v
         elif k in ("prune", "fused_batch", "profile", "graphs"):
             v = int(bool(v))
         setattr(cfg, k, v)
@@ -61,7 +64,7 @@ class Context:
     S (fixed point of eq (03a) on the device unless ``S0`` is given). Config keys follow
     ``sr_config``: C, K, K_ps, s_prec ('fp64' | 'hilo' | 'fp32'), mode ('dense' | 'column'),
     gamma_form ('closed' | 'direct'), prune, node_cap, edge_cap, init_tol, init_max_iter,
-    batch_chunk, fused_batch, split_rows, profile.
+    batch_chunk, fused_batch, split_rows, profile, graphs, update_prec ('fp64' | 'fp32').
     """
 
     def __init__(self, n, src, dst, weight=None, S0=None, stream=None, init="fixed_point",

@@ -16,8 +16,11 @@ import json
 import os
 import tempfile
 
-# tile variants of the fused GEMM: (panel columns per LDS chunk, LDS pitch in doubles)
+# tile variants of the fused GEMM: (panel columns per LDS chunk, LDS pitch) on the float64
+# matrix cores, and the float32 matrix cores' variant (SR_UPDATE_FP32; pitch in floats)
 VARIANTS = {0: (16, 18), 1: (16, 20), 2: (32, 34), 3: (32, 36)}
+F32_VARIANT = 4
+F32_TILE = (32, 33)
 CHUNKS = (32, 48, 64, 96, 128)
 BUCKET = 8192
 
@@ -50,14 +53,18 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def tune(ctx, chunks=CHUNKS, variants=tuple(VARIANTS), reps=2, path=None, force=False):
+def tune(ctx, chunks=CHUNKS, variants=None, reps=2, path=None, force=False):
     """Chooses batch_chunk and the GEMM variant for ``ctx`` (a dense-mode Context), applies
-    them, and returns a record of the choice (and of the timings when it measured)."""
+    them, and returns a record of the choice (and of the timings when it measured). A context
+    whose fused passes run on the float32 matrix cores tunes the chunk of that variant."""
     from . import _lib as L
     path = path or cache_path()
     n, _ = ctx.sizes()
     prec = {L.SR_S_FP64: "fp64", L.SR_S_FP32_HILO: "hilo", L.SR_S_FP32: "fp32"}[ctx.cfg.s_prec]
-    key = key_for(n, ctx.cfg.K, prec)
+    f32 = ctx.cfg.update_prec == L.SR_UPDATE_FP32
+    if variants is None:
+        variants = (F32_VARIANT,) if f32 else tuple(VARIANTS)
+    key = key_for(n, ctx.cfg.K, prec) + ("_f32update" if f32 else "")
     data = _load(path)
     if key in data and not force:
         c = data[key]
@@ -70,9 +77,9 @@ def tune(ctx, chunks=CHUNKS, variants=tuple(VARIANTS), reps=2, path=None, force=
             table.append({"variant": v, "chunk": b, "gemm_ms": round(g, 4),
                           "corr_ms": round(c, 5), "ms_per_block": g / b + c})
     best = min(table, key=lambda t: t["ms_per_block"])
+    tile = VARIANTS.get(best["variant"], F32_TILE)
     choice = {"batch_chunk": best["chunk"], "variant": best["variant"],
-              "lds_chunk": VARIANTS[best["variant"]][0],
-              "lds_pitch": VARIANTS[best["variant"]][1],
+              "lds_chunk": tile[0], "lds_pitch": tile[1],
               "ms_per_block": best["ms_per_block"], "n_timed": n}
     data = _load(path)
     data[key] = choice

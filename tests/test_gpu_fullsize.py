@@ -84,10 +84,10 @@ def _bench_stream():
     return n, m, s, d, batches, counts
 
 
-def _replay(prec, n, m, s, d, batches, counts):
+def _replay(prec, n, m, s, d, batches, counts, update_prec="fp64"):
     ctx = _ctx(n, s, d, C=C, K=15, s_prec=prec, node_cap=counts[-1] + 64,
                edge_cap=m + sum(len(b[0]) for b in batches) + 1024, fused_batch=True,
-               batch_chunk=64)
+               batch_chunk=64, update_prec=update_prec)
     for t in range(BENCH_WARMUP + BENCH_STEPS):
         st = ctx.apply_batch(*batches[t], stats=True)
         _say(f"{prec} replay: batch {t} ({len(batches[t][0])} edges, {st['blocks']} blocks), "
@@ -155,6 +155,24 @@ def test_bench_state_store_gap_vs_fp64(bench_state):
          f"float64 store vs S* {maxabs(rows64, st['exact']):.3e}")
     assert gap < 1e-12
     assert maxabs(rows64, st["exact"]) < 1e-6
+
+
+@pytest.mark.gpu
+def test_bench_state_float32_update(bench_state):
+    """The benchmark's 25 batches with the fused passes on the float32 matrix cores (the
+    spec precision form: float32 low-rank update, value + compensation store, float64
+    series): the sampled rows stay within 1e-6 of S*, and their gap to the float64 passes is
+    stated."""
+    st = bench_state
+    n, m, s, d, batches, counts = _bench_stream()
+    ctx = _replay("hilo", n, m, s, d, batches, counts, update_prec="fp32")
+    rows32 = np.stack([ctx.query_column(int(x)).cpu().numpy() for x in st["nodes"]])
+    ctx.close()
+    torch.cuda.empty_cache()
+    gap = maxabs(rows32, st["rows"])
+    err = maxabs(rows32, st["exact"])
+    _say(f"bench state, float32 passes: vs float64 passes {gap:.3e}; vs S* {err:.3e}")
+    assert err < 1e-6
 
 
 @pytest.mark.gpu

@@ -587,7 +587,7 @@ def test_fused_batches_match_oracle(prec, chunk):
     This stream's K = 15 truncation error (2.5e-6, the oracle's own Inc-bSR at K = 15 shows
     the same) exceeds 1e-6, so parity is checked twice: at K = 15 against the oracle's
     K-truncated Inc-bSR (same method, tight tolerance), and at K = 40 against the converged
-    recompute at 1e-6."""
+    recompute at 1e-6. Chunk 1 makes every pass a single block."""
     n = 300
     s, d = W.chung_lu(n, 1500, seed=63)
     batches, counts = W.batch_stream(n, s, d, 3, 150, 64)
@@ -609,5 +609,8 @@ def test_fused_batches_match_oracle(prec, chunk):
             tr.apply(i, j, 1)
         tr.n = nn
         assert st["fused_passes"] == -(-st["lowrank_blocks"] // chunk)
-        assert maxabs(ctx15.S().cpu().numpy(), S_or) < (1e-12 if prec == "fp64" else 1e-9)
+        S15 = ctx15.S().cpu().numpy()
+        # every fused pass, one block or many, writes (a, b) and (b, a) from one sum
+        assert np.array_equal(S15, S15.T)
+        assert maxabs(S15, S_or) < (1e-12 if prec == "fp64" else 1e-9)
         assert maxabs(ctx40.S().cpu().numpy(), tr.exact(C)) < TOL

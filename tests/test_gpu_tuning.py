@@ -125,3 +125,61 @@ def test_autotuner_keeps_S_and_caches(tmp_path):
     tr.n = counts[0]
     assert maxabs(ctx.S().cpu().numpy(), tr.exact(C)) < 1e-6
     ctx.close()
+
+
+def test_mfma_f32_lane_layout():
+    """v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l//16] and B[l//16][l%16]; slot v of lane
+    l holds D[4*(l//16) + v][l%16]. The float32 fused pass relies on this layout."""
+    import ctypes as Cc
+    import torch
+    from paper_1711_00121_amd import _lib as L
+    a = torch.arange(64, dtype=torch.float32, device="cuda") * 0.5 + 1.0
+    b = torch.arange(64, dtype=torch.float32, device="cuda") * 0.25 - 3.0
+    out = torch.empty(256, dtype=torch.float32, device="cuda")
+    assert L.load().sr_mfma_layout_probe_f32(Cc.c_void_p(a.data_ptr()), Cc.c_void_p(b.data_ptr()),
+                                             Cc.c_void_p(out.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    A = np.zeros((16, 4))
+    B = np.zeros((4, 16))
+    for l in range(64):
+        A[l % 16, l // 16] = a[l].item()
+        B[l // 16, l % 16] = b[l].item()
+    D = A @ B
+    got = out.cpu().numpy()
+    for l in range(64):
+        for v in range(4):
+            assert got[4 * l + v] == D[4 * (l // 16) + v, l % 16]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "hilo"])
+def test_float32_update_passes(prec):
+    """Fused passes on the float32 matrix cores: within 1e-6 of the oracle's Inc-bSR at the
+    same K and of the converged recompute (K = 40), exactly symmetric; the gap to the float64
+    passes is reported."""
+    n = 400
+    s, d, batches, counts = stream(n, 2400, 1207)
+    kw = dict(C=C, s_prec=prec, node_cap=counts[-1] + 4, batch_chunk=6)
+    f32 = ctx_for(n, s, d, K=15, update_prec="fp32", **kw)
+    f64 = ctx_for(n, s, d, K=15, **kw)
+    deep = ctx_for(n, s, d, K=40, update_prec="fp32", **kw)
+    tr = EdgeTracker(n, s, d)
+    S_or = O.fixed_point(Gr.transition_matrix(n, s, d), C)
+    gap = 0.0
+    for (bi, bj, bo), nn in zip(batches, counts):
+        cs, cd = tr.arrays()
+        S_or, _ = OI.inc_bsr(tr.n, cs, cd, S_or, bi, bj, bo, C, 15)
+        for c in (f32, f64, deep):
+            c.apply_batch(bi, bj, bo)
+        plus, minus = OI.net_update(bi, bj, bo)
+        for (i, j) in minus:
+            tr.apply(i, j, -1)
+        for (i, j) in plus:
+            tr.apply(i, j, 1)
+        tr.n = nn
+        S = f32.S().cpu().numpy()
+        assert np.array_equal(S, S.T)
+        assert maxabs(S, S_or) < 1e-6
+        gap = max(gap, maxabs(S, f64.S().cpu().numpy()))
+        assert maxabs(deep.S().cpu().numpy(), tr.exact(C)) < 1e-6
+    print(f"float32 passes ({prec} store): max gap to float64 passes {gap:.2e}")
+    assert gap < 1e-6
