@@ -65,7 +65,8 @@ def main():
     ap.add_argument("--max-batch", type=int, default=4096)
     ap.add_argument("--chunk", type=int, default=0,
                     help="low-rank blocks per fused pass (0: the autotuner picks it, and the "
-                         "GEMM tile variant, at the size after the warm-up)")
+                         "GEMM tile variant, at the size after the warm-up; in column mode "
+                         "the library's memory-bounded default)")
     ap.add_argument("--update-prec", default="fp64", choices=["fp64", "fp32"],
                     help="batch: arithmetic of the fused passes (fp32: float32 matrix cores, "
                          "sums added to the store in float64)")
@@ -513,9 +514,13 @@ def run_columns_batch(args):
     s, d = W.chung_lu(n, m, seed=1004)
     batches = W.existing_batches(n, s, d, args.warmup + steps, n_ins, n_del, shared, seed=2204)
     cols = W.column_sample(n, cfg["block"], seed=3004)[:cfg["block"]]
+    from paper_1711_00121_amd import device_bytes
+    held_before, _ = device_bytes()
     ctx = Context(n, s, d, C=C, K=K, K_ps=Kps, mode="column",
                   edge_cap=m + (args.warmup + steps) * n_ins + 1024,
-                  split_rows=args.split_rows)
+                  split_rows=args.split_rows, batch_chunk=args.chunk)
+    chunk = ctx.config().batch_chunk
+    held_ctx, _ = device_bytes(reset_peak=True)
     out_buf = torch.empty((len(cols), n), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     for t in range(args.warmup):
@@ -534,13 +539,25 @@ def run_columns_batch(args):
     dt = time.perf_counter() - t0
     kern_ms, launches = ctx.profile_read(reset=True)
     ctx.profile(False)
+    _, peak = device_bytes()
     values = float(n) * len(cols) * steps
     edges = (n_ins + n_del) * steps
     out = common(args, cfg, values / dt, "pair-values/s", dt, steps,
                  extra_cfg={"workload": "column_batch_n1m", "K_ps": Kps,
                             "columns": len(cols), "batch": {"insert": n_ins, "delete": n_del,
                                                             "shared_sink": shared},
-                            "output": "float64"})
+                            "output": "float64", "batch_chunk": chunk})
+    # memory: what the library holds (graph, series and PartialSim buffers, the panel), not
+    # the caller's output; an n x n store would be n^2 x 8 bytes
+    w = 2 * (K + 1)
+    out["memory"] = {"library_bytes_after_init": held_ctx - held_before,
+                     "library_bytes_peak": peak - held_before,
+                     "panel_bytes": -(-chunk * w // 16) * 16 * (-(-n // 128) * 128) * 8,
+                     "series_bytes_Kn": 2 * (K + 1) * n * 8,
+                     "output_bytes": len(cols) * n * 8,
+                     "dense_S_bytes": n * n * 8}
+    out["accuracy"] = {"note": "float64 arithmetic and output throughout; parity against the "
+                               "oracle's column method is in the GPU tests (1e-12 relative)"}
     out["metric"] = "batch Delta S column values/s, column-by-column mode (no stored S)"
     out["edges_per_s"] = edges / dt
     out["blocks_per_batch"] = blocks / steps

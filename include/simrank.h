@@ -84,7 +84,11 @@ typedef struct sr_config {
   int64_t edge_cap;      /* maximum edge count (>= m); 0 means 2 m + 1024                   */
   double init_tol;       /* fixed-point step tolerance of the initial S (max-abs)           */
   int32_t init_max_iter; /* iteration cap of the initial fixed point                        */
-  int32_t batch_chunk;   /* low-rank blocks applied per fused pass of apply_batch (>= 1)   */
+  int32_t batch_chunk;   /* low-rank blocks per fused pass of apply_batch, or per
+                            accumulate pass of apply_batch_columns; 0: the mode's default,
+                            64 in dense mode, ceil(512 / (2 (K + 1))) in column mode
+                            (passes bounded by arithmetic, not by the output's traffic, with
+                            a panel of at most 512 + 2 (K + 1) columns of n doubles)                  */
   int32_t fused_batch;   /* 1: apply_batch defers low-rank blocks into fused passes;
                             0: each block updates S on its own                              */
   int32_t split_rows;    /* graph rows (in- or out-lists) with more entries are traversed in
@@ -129,7 +133,7 @@ typedef struct sr_batch_stats {
 
 /* Fills *cfg with defaults: C = 0.6, K = 15, K_ps = 30, SR_S_FP64, SR_DENSE,
  * SR_GAMMA_CLOSED, prune = 1, capacities 0 (derived), init_tol = 1e-15, init_max_iter = 400,
- * batch_chunk = 64, fused_batch = 1, graphs = 1. */
+ * batch_chunk = 0 (the mode's default), fused_batch = 1, graphs = 1. */
 sr_status sr_default_config(sr_config* cfg);
 
 /* Creates a context for the digraph with n nodes and m edges src[e] -> dst[e] (host arrays,
@@ -224,9 +228,10 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* src, const int32_
  * series of eq (16a)), and eq (71) summed over the blocks:
  *   out_dev[t * ld_out + a] = Delta S[a][cols[t]]   (float64, t < ncols, a < n).
  * cols: host array of node ids (< n); out_dev: device, ncols x ld_out float64, ld_out >= n,
- * overwritten (entries past n of a row are set to zero). Memory: batch_chunk deferred
- * panels of n x 2(K+1) doubles (rounded up to 32), then one FP64 matrix-core pass over them
- * per chunk. SR_EMODE outside column mode, for a weighted graph, or when an edge would create
+ * overwritten (entries past n of a row are set to zero). Memory: O(K n + m) besides the output: batch_chunk
+ * deferred blocks of n x 2(K+1) doubles each (packed in slabs of 16 columns; at most
+ * 512 + 2(K+1) columns at the default chunk), then one FP64 matrix-core pass over them per
+ * chunk. SR_EMODE outside column mode, for a weighted graph, or when an edge would create
  * a node; SR_ERANGE for a column id out of range; otherwise as apply_batch (validation errors
  * change nothing). stats: NULL, or filled after synchronising. */
 sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* src,
@@ -309,6 +314,16 @@ sr_status sr_edges(sr_ctx* ctx, int32_t* src, int32_t* dst, double* w, int64_t c
 
 /* Current node and edge counts. */
 sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m);
+
+/* The context's configuration as resolved at init (defaults filled in: capacities,
+ * batch_chunk) and as changed since by sr_set_tuning. SR_EINVAL for a NULL argument. */
+sr_status sr_get_config(sr_ctx* ctx, sr_config* out);
+
+/* Device memory the library holds now, over all contexts of the process (S, panels, graph
+ * arrays, work buffers; not the caller's buffers, not the static no-allocation scratch), and
+ * the peak since the last reset: held, peak: NULL or filled, in bytes; reset_peak != 0 sets
+ * the peak to the bytes held now after reading it. Always SR_OK. */
+sr_status sr_device_bytes(int64_t* held, int64_t* peak, int32_t reset_peak);
 
 /* The block plan of the last apply_batch, as int32 records
  * [case, op, j, d_j, delta, i_1, ..., i_delta] concatenated, into out (host, capacity cap).

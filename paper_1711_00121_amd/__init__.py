@@ -5,8 +5,8 @@ The library (csrc/, built in-tree into libsimrank.so) implements Yu, Lin, Zhang,
 K sparse matrix-vector products, affected-area pruning, node insertions, similar-sink
 batches, a column-by-column mode, and an edge-weight adjoint.
 """
-from .simrank import (Context, SimRankPairs, default_config, mfma_layout_probe, partition,
-                      simrank_pairs)
+from .simrank import (Context, SimRankPairs, default_config, device_bytes, mfma_layout_probe,
+                      partition, simrank_pairs)
 
-__all__ = ["Context", "SimRankPairs", "default_config", "mfma_layout_probe", "partition",
-           "simrank_pairs"]
+__all__ = ["Context", "SimRankPairs", "default_config", "device_bytes", "mfma_layout_probe",
+           "partition", "simrank_pairs"]

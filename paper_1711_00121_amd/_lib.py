@@ -104,6 +104,8 @@ SIGNATURES = {
                              C.POINTER(C.c_int64)]),
     "sr_copy_S": (C.c_int, [P, P, C.c_int64]),
     "sr_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sr_get_config": (C.c_int, [P, C.POINTER(sr_config)]),
+    "sr_device_bytes": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32]),
     "sr_edges": (C.c_int, [P, I32P, I32P, F64P, C.c_int64, C.POINTER(C.c_int64)]),
     "sr_last_plan": (C.c_int, [P, I32P, C.c_int64, C.POINTER(C.c_int64)]),
     "sr_synchronize": (C.c_int, [P]),

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <set>
+#include <unordered_map>
 #include <vector>
 
 #include "hostgraph.h"
@@ -22,6 +23,9 @@ using namespace sr;
 // the address hipGetSymbolAddress returns for the device (scratch_ptr below).
 constexpr int64_t kScratchIds = 65536;  // 256 KiB per GPU
 static __device__ __align__(256) int32_t scratch[kScratchIds];
+
+// Panel columns one column-mode accumulate pass covers by default (see init_impl).
+constexpr int kColumnPanelCols = 512;
 
 // Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
 // process them in chunks (see graph.hip).
@@ -170,13 +174,37 @@ AdjPtrs adjptrs(const sr_ctx* c) {
 // hipMalloc that leaves no sticky error behind on failure: HIP keeps the last error for
 // hipGetLastError, which the kernel launchers read after every launch, so a failed
 // allocation would otherwise be reported by the next, unrelated launch.
+// Every device allocation of the library goes through dmalloc / dfree, which keep the bytes
+// held (all contexts of the process) and their peak for sr_device_bytes.
+std::mutex g_mem_mu;
+std::unordered_map<void*, size_t> g_mem_live;
+int64_t g_mem_now = 0, g_mem_peak = 0;
+
 hipError_t dmalloc(void** p, size_t bytes) {
   const hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
+    return e;
   }
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_mem_live[*p] = bytes;
+  g_mem_now += (int64_t)bytes;
+  g_mem_peak = std::max(g_mem_peak, g_mem_now);
   return e;
+}
+
+hipError_t dfree(void* p) {
+  if (!p) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_mem_live.find(p);
+    if (it != g_mem_live.end()) {
+      g_mem_now -= (int64_t)it->second;
+      g_mem_live.erase(it);
+    }
+  }
+  return hipFree(p);
 }
 
 template <typename T>
@@ -211,13 +239,13 @@ void heavy_touch(HeavySet& H, const SlotList& L, int32_t r) {
 }
 
 void heavy_free(HeavySet& H) {
-  (void)hipFree(H.d_med);
-  (void)hipFree(H.d_heavy);
-  (void)hipFree(H.d_huge);
-  (void)hipFree(H.d_hfirst);
-  (void)hipFree(H.d_chunk);
-  (void)hipFree(H.d_part);
-  (void)hipFree(H.d_pflag);
+  (void)dfree(H.d_med);
+  (void)dfree(H.d_heavy);
+  (void)dfree(H.d_huge);
+  (void)dfree(H.d_hfirst);
+  (void)dfree(H.d_chunk);
+  (void)dfree(H.d_part);
+  (void)dfree(H.d_pflag);
   H.d_med = H.d_heavy = H.d_huge = H.d_hfirst = nullptr;
   H.d_chunk = nullptr;
   H.d_part = nullptr;
@@ -229,7 +257,7 @@ template <typename T>
 hipError_t upload_list(const std::vector<T>& v, T** d, int64_t* cap) {
   const int64_t cnt = (int64_t)v.size();
   if (cnt > *cap) {
-    (void)hipFree(*d);
+    (void)dfree(*d);
     *d = nullptr;
     const int64_t c = std::max<int64_t>(64, 2 * cnt);
     hipError_t e = dmalloc((void**)d, (size_t)c * sizeof(T));
@@ -274,8 +302,8 @@ sr_status heavy_sync(sr_ctx* ctx, HeavySet& H, const SlotList& L) {
     const int64_t old_cap = H.cap_chunk;
     e = upload_list(H.chunk, &H.d_chunk, &H.cap_chunk);
     if (e == hipSuccess && (H.cap_chunk != old_cap || H.d_part == nullptr)) {
-      (void)hipFree(H.d_part);
-      (void)hipFree(H.d_pflag);
+      (void)dfree(H.d_part);
+      (void)dfree(H.d_pflag);
       H.d_part = nullptr;
       H.d_pflag = nullptr;
       e = dmalloc((void**)&H.d_part, (size_t)std::max<int64_t>(H.cap_chunk, 1) * 16);
@@ -551,7 +579,7 @@ sr_status stage_long_lists(sr_ctx* ctx, const std::vector<BlockT>& plan,
   // earlier work may still read the previous lists
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail_hip(ctx);
   if ((int64_t)ids.size() > ctx->blk_cap) {
-    (void)hipFree(ctx->d_blk);
+    (void)dfree(ctx->d_blk);
     ctx->d_blk = nullptr;
     ctx->blk_cap = 0;
     const int64_t c = std::max<int64_t>(4096, 2 * (int64_t)ids.size());
@@ -979,7 +1007,7 @@ sr_status sr_default_config(sr_config* cfg) {
   cfg->edge_cap = 0;
   cfg->init_tol = 1e-15;
   cfg->init_max_iter = 400;
-  cfg->batch_chunk = 64;
+  cfg->batch_chunk = 0;  // mode default, resolved by init_simrank
   cfg->fused_batch = 1;
   cfg->split_rows = kSplitRows;
   cfg->graphs = 1;
@@ -996,29 +1024,29 @@ sr_status sr_destroy(sr_ctx* ctx) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
-  for (int k = 0; k < 6; ++k) (void)hipFree(ctx->d_adj[k]);
-  (void)hipFree(ctx->d_in_w);
-  (void)hipFree(ctx->d_out_w);
-  (void)hipFree(ctx->d_W);
-  (void)hipFree(ctx->S_mem[0]);
-  (void)hipFree(ctx->S_mem[1]);
+  for (int k = 0; k < 6; ++k) (void)dfree(ctx->d_adj[k]);
+  (void)dfree(ctx->d_in_w);
+  (void)dfree(ctx->d_out_w);
+  (void)dfree(ctx->d_W);
+  (void)dfree(ctx->S_mem[0]);
+  (void)dfree(ctx->S_mem[1]);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp, ctx->ylast,
                   ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd, ctx->corr,
                   ctx->corr_w};
-  for (double* p : dd) (void)hipFree(p);
+  for (double* p : dd) (void)dfree(p);
   uint32_t* bb[] = {ctx->suppI, ctx->suppJ, ctx->Abits, ctx->Bbits, ctx->Ahat, ctx->Bhat};
-  for (uint32_t* p : bb) (void)hipFree(p);
-  (void)hipFree(ctx->rowlist);
-  (void)hipFree(ctx->rowlist2);
-  (void)hipFree(ctx->d_ids);
-  (void)hipFree(ctx->corr_tab);
+  for (uint32_t* p : bb) (void)dfree(p);
+  (void)dfree(ctx->rowlist);
+  (void)dfree(ctx->rowlist2);
+  (void)dfree(ctx->d_ids);
+  (void)dfree(ctx->corr_tab);
   heavy_free(ctx->hin);
   heavy_free(ctx->hout);
-  (void)hipFree(ctx->d_cnt);
-  (void)hipFree(ctx->d_max);
-  (void)hipFree(ctx->d_sum);
-  (void)hipFree(ctx->d_mm);
-  (void)hipFree(ctx->d_blk);
+  (void)dfree(ctx->d_cnt);
+  (void)dfree(ctx->d_max);
+  (void)dfree(ctx->d_sum);
+  (void)dfree(ctx->d_mm);
+  (void)dfree(ctx->d_blk);
   (void)hipHostFree(ctx->h_cnt);
   (void)hipHostFree(ctx->h_max);
   delete ctx;
@@ -1048,7 +1076,17 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
       (cfg.split_rows != 0 && cfg.split_rows < kMedium))
     return SR_EINVAL;
   if (cfg.split_rows == 0) cfg.split_rows = kSplitRows;
-  if (cfg.batch_chunk == 0) cfg.batch_chunk = 64;
+  // Column mode's default chunk keeps the accumulate passes bounded by matrix-core
+  // arithmetic rather than by their read-modify-write of the output: a pass of chunk blocks
+  // does chunk 2 (K + 1) / 8 flop per output byte moved, against the ~15 flop per byte where
+  // FP64 matrix cores and HBM balance. Measured at n = 1M, K = 10, 8,192 columns, relative
+  // to chunk 64 (11.3 GB panel): chunk 24 from 512 columns 0.96 (4.2 GB), chunk 12 0.91
+  // (2.2 GB), chunk 1 0.41 (0.26 GB). The panel holds at most 512 + 2 (K + 1) columns of n
+  // doubles, a constant multiple of the O(K n) series storage whatever n.
+  if (cfg.batch_chunk == 0)
+    cfg.batch_chunk = cfg.mode == SR_COLUMN ? std::max(1, (kColumnPanelCols + 2 * cfg.K + 1) /
+                                                              (2 * (cfg.K + 1)))
+                                            : 64;
   if (cfg.init_max_iter <= 0) cfg.init_max_iter = 400;
   if (cfg.mode == SR_COLUMN && S0) return SR_EINVAL;
   const int64_t node_cap = cfg.node_cap > 0 ? cfg.node_cap : n;
@@ -1068,6 +1106,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   sr_ctx* ctx = new (std::nothrow) sr_ctx();
   if (!ctx) return SR_ENOMEM;
   ctx->cfg = cfg;
+  ctx->cfg.node_cap = node_cap;
+  ctx->cfg.edge_cap = edge_cap;
   ctx->gemm_variant = cfg.update_prec == SR_UPDATE_FP32 ? kGemmF32 : 0;
   ctx->hin.split = ctx->hout.split = cfg.split_rows;
   ctx->profiling = cfg.profile != 0;
@@ -1254,7 +1294,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
       if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
       sr_destroy(b);
     }
-    (void)hipFree(dg);
+    (void)dfree(dg);
     if (bst != SR_OK || e != hipSuccess) {
       sr_destroy(ctx);
       return bst != SR_OK ? bst : SR_EHIP;
@@ -1273,8 +1313,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
     if (e == hipSuccess) e = hipMemcpy(dd, tree_depth, (size_t)n * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_tree_init(ctx->S, n, dp, dd, cfg.C, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    (void)hipFree(dp);
-    (void)hipFree(dd);
+    (void)dfree(dp);
+    (void)dfree(dd);
     if (e != hipSuccess) {
       sr_destroy(ctx);
       return SR_EHIP;
@@ -1292,7 +1332,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   if (S0) {
     // S0 has leading dimension n; re-pitch into ldi
     if (hipMemcpy2D(A, ldi * 8, S0, n * 8, n * 8, n, hipMemcpyDeviceToDevice) != hipSuccess) {
-      (void)hipFree(A);
+      (void)dfree(A);
       sr_destroy(ctx);
       return SR_EHIP;
     }
@@ -1317,9 +1357,9 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
       if (step <= cfg.init_tol) break;
     }
     if (e != hipSuccess) {
-      (void)hipFree(A);
-      (void)hipFree(B);
-      (void)hipFree(T);
+      (void)dfree(A);
+      (void)dfree(B);
+      (void)dfree(T);
       sr_destroy(ctx);
       return SR_EHIP;
     }
@@ -1330,9 +1370,9 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   if (B) e = launch_transpose(n, A, B, ctx->stream);
   if (e == hipSuccess) e = launch_to_store(ctx->S, n, A, ctx->stream, B);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  (void)hipFree(A);
-  (void)hipFree(B);
-  (void)hipFree(T);
+  (void)dfree(A);
+  (void)dfree(B);
+  (void)dfree(T);
   if (e != hipSuccess) {
     sr_destroy(ctx);
     return SR_EHIP;
@@ -1985,7 +2025,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     tab.insert(tab.end(), rows.begin(), rows.end());
     HC(hipStreamSynchronize(ctx->stream));
     if ((int64_t)tab.size() > ctx->corr_tab_cap) {
-      (void)hipFree(ctx->corr_tab);
+      (void)dfree(ctx->corr_tab);
       ctx->corr_tab = nullptr;
       ctx->corr_tab_cap = 0;
       const int64_t c = std::max<int64_t>(1024, 2 * (int64_t)tab.size());
@@ -2107,24 +2147,23 @@ sr_status apply_batch_columns(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const
   hipStream_t s = ctx->stream;
   const double C = ctx->cfg.C;
   const int K = ctx->cfg.K;
-  const int pld = ctx->pld;
   const int chunk = ctx->cfg.batch_chunk > 0 ? ctx->cfg.batch_chunk : 1;
-  const int64_t gstride = ctx->p_rows * pld;
   // Deferred blocks share one packed panel: block q's 2(K+1) columns are global columns
   // q 2(K+1) .. (q + 1) 2(K+1) - 1, stored in slabs of 16 columns (node-major inside a slab),
   // so the matrix-core pass runs over no padding but the last slab's tail. Rows past n stay
-  // zero. The slabs of `chunk` blocks fit in the chunk x pld columns allocated.
+  // zero. The panel holds the slabs of `chunk` blocks, chunk 2(K+1) columns rounded up to 16.
   const int w = 2 * (K + 1);
   const int64_t slab = ctx->p_rows * 16;
+  const int64_t slabs = ((int64_t)chunk * w + 15) / 16;
   auto at = [&](int64_t col) { return ctx->Pb + (col / 16) * slab + col % 16; };
   if (!ctx->Pb) {
-    if (dalloc(&ctx->Pb, gstride * chunk) != hipSuccess) return SR_ENOMEM;
-    HC(hipMemsetAsync(ctx->Pb, 0, (size_t)gstride * chunk * 8, s));
+    if (dalloc(&ctx->Pb, slabs * slab) != hipSuccess) return SR_ENOMEM;
+    HC(hipMemsetAsync(ctx->Pb, 0, (size_t)(slabs * slab) * 8, s));
   }
   if (ncols > 0) {
     if (ctx->ids_cap < ncols) {
       HC(hipStreamSynchronize(s));
-      (void)hipFree(ctx->d_ids);
+      (void)dfree(ctx->d_ids);
       ctx->d_ids = nullptr;
       ctx->ids_cap = 0;
       if (dalloc(&ctx->d_ids, ncols) != hipSuccess) return SR_ENOMEM;
@@ -2302,7 +2341,7 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
   if (ncols == 0) return SR_OK;
   if (ctx->ids_cap < ncols) {
     HC(hipStreamSynchronize(ctx->stream));
-    (void)hipFree(ctx->d_ids);
+    (void)dfree(ctx->d_ids);
     ctx->d_ids = nullptr;
     ctx->ids_cap = 0;
     if (dalloc(&ctx->d_ids, ncols) != hipSuccess) return SR_ENOMEM;
@@ -2328,7 +2367,7 @@ sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
   if (nq == 0) return SR_OK;
   if (ctx->ids_cap < nq) {
     HC(hipStreamSynchronize(ctx->stream));
-    (void)hipFree(ctx->d_ids);
+    (void)dfree(ctx->d_ids);
     ctx->d_ids = nullptr;
     ctx->ids_cap = 0;
     if (dalloc(&ctx->d_ids, nq) != hipSuccess) return SR_ENOMEM;
@@ -2472,6 +2511,20 @@ sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m) {
   return SR_OK;
 }
 
+sr_status sr_get_config(sr_ctx* ctx, sr_config* out) {
+  if (!valid_ctx(ctx) || !out) return SR_EINVAL;
+  *out = ctx->cfg;
+  return SR_OK;
+}
+
+sr_status sr_device_bytes(int64_t* held, int64_t* peak, int32_t reset_peak) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  if (held) *held = g_mem_now;
+  if (peak) *peak = g_mem_peak;
+  if (reset_peak) g_mem_peak = g_mem_now;
+  return SR_OK;
+}
+
 sr_status sr_synchronize(sr_ctx* ctx) {
   if (!valid_ctx(ctx)) return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
@@ -2499,13 +2552,13 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   double *Sig = nullptr, *T = nullptr, *U = nullptr, *G = nullptr, *dq = nullptr, *qv = nullptr;
   int32_t* se = nullptr;
   auto cleanup = [&]() {
-    (void)hipFree(Sig);
-    (void)hipFree(T);
-    (void)hipFree(U);
-    (void)hipFree(G);
-    (void)hipFree(dq);
-    (void)hipFree(qv);
-    (void)hipFree(se);
+    (void)dfree(Sig);
+    (void)dfree(T);
+    (void)dfree(U);
+    (void)dfree(G);
+    (void)dfree(dq);
+    (void)dfree(qv);
+    (void)dfree(se);
   };
   if (dalloc(&Sig, n * ldi) != hipSuccess || dalloc(&T, n * ldi) != hipSuccess ||
       dalloc(&U, n * ldi) != hipSuccess || dalloc(&G, n * ldi) != hipSuccess ||
@@ -2602,10 +2655,10 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
   const int slots = std::max(1, blocks / 2);
   auto done = [&](sr_status r) {
     (void)hipStreamSynchronize(s);
-    (void)hipFree(Z);
-    (void)hipFree(tab);
-    (void)hipFree(cv);
-    (void)hipFree(cw);
+    (void)dfree(Z);
+    (void)dfree(tab);
+    (void)dfree(cv);
+    (void)dfree(cw);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return r;
@@ -2677,7 +2730,7 @@ sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant) {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
     ctx->sgraphs.clear();
     double* bufs[] = {ctx->Pb, ctx->wts, ctx->corr, ctx->corr_w};
-    for (double* b : bufs) (void)hipFree(b);
+    for (double* b : bufs) (void)dfree(b);
     ctx->Pb = ctx->wts = ctx->corr = ctx->corr_w = nullptr;
     ctx->corr_slots = 0;
     ctx->cfg.batch_chunk = batch_chunk;

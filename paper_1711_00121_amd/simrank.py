@@ -46,6 +46,15 @@ def default_config(**kw):
     return cfg
 
 
+def device_bytes(reset_peak=False):
+    """(held, peak): device bytes the library holds now over all contexts, and the peak since
+    the last reset (``reset_peak`` starts a new peak from what is held now)."""
+    held, peak = C.c_int64(), C.c_int64()
+    L.check(L.load().sr_device_bytes(C.byref(held), C.byref(peak), int(bool(reset_peak))),
+            "sr_device_bytes")
+    return held.value, peak.value
+
+
 def partition(n, src, dst, parts):
     """Block labels from the library's breadth-first partitioner (host only)."""
     src = _i32(src)
@@ -292,6 +301,13 @@ class Context:
         L.check(self.lib.sr_time_fused(self.h, int(variant), int(blocks), int(reps), C.byref(g),
                                        C.byref(c)), "sr_time_fused")
         return g.value, c.value
+
+    def config(self):
+        """The configuration as resolved at init (capacities, batch_chunk filled in) and as
+        changed since by ``set_tuning``: an ``sr_config``."""
+        out = L.sr_config()
+        L.check(self.lib.sr_get_config(self.h, C.byref(out)), "sr_get_config")
+        return out
 
     def set_tuning(self, batch_chunk, variant):
         L.check(self.lib.sr_set_tuning(self.h, int(batch_chunk), int(variant)), "sr_set_tuning")

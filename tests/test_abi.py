@@ -48,7 +48,7 @@ def test_default_config_and_strerror():
     cfg = _lib.sr_config()
     assert L.sr_default_config(ctypes.byref(cfg)) == 0
     assert cfg.C == 0.6 and cfg.K == 15 and cfg.K_ps == 30 and cfg.prune == 1
-    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 64 and cfg.split_rows == 65536
+    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 0 and cfg.split_rows == 65536
     assert cfg.profile == 0 and cfg.graphs == 1
     assert L.sr_strerror(-3) == b"edge exists"
     assert L.sr_default_config(None) == _lib.SR_EINVAL
@@ -61,6 +61,14 @@ def test_null_context_arguments_are_rejected_without_gpu():
     assert L.sr_destroy(None) == _lib.SR_OK
     assert L.init_simrank(None, 10, 0, None, None, None, None, None, None) == _lib.SR_EINVAL
     assert L.init_simrank_tree(None, 10, 0, None, None, None, None, None) == _lib.SR_EINVAL
+    assert L.sr_get_config(None, None) == _lib.SR_EINVAL
+
+
+def test_device_bytes_without_contexts():
+    """No context allocates on a host without a GPU: the library holds nothing."""
+    from paper_1711_00121_amd import device_bytes
+    assert device_bytes() == (0, 0)
+    assert device_bytes(reset_peak=True) == (0, 0)
 
 
 def test_struct_layout_matches_header():

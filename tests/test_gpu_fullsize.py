@@ -267,10 +267,23 @@ def test_fullsize_column_batch_n1m():
     bi, bj, bo = W.existing_batch(n, s, d, n_ins=12, n_del=4, shared=6, seed=2104)
     block = W.column_sample(n, cfg["block"] - 2, seed=3004,
                             extra=[int(bi[0]), int(bj[0])])[:cfg["block"]]
+    from paper_1711_00121_amd import device_bytes
     ctx = _ctx(n, s, d, C=C, K=K, K_ps=Kps, mode="column")
+    chunk = ctx.config().batch_chunk
+    held0, _ = device_bytes(reset_peak=True)
     out, st = ctx.apply_batch_columns(bi, bj, bo, block, stats=True)
     torch.cuda.synchronize()
-    _say(f"batch of {len(bi)} edges: {st['blocks']} blocks, {st['fused_passes']} passes")
+    _, peak = device_bytes()
+    # the default chunk keeps the call's own memory to its packed panel (chunk 2(K+1)
+    # columns rounded up to 16, of n + padding rows) plus the column ids: O(K n), no n x n
+    w = 2 * (K + 1)
+    panel = -(-chunk * w // 16) * 16 * (n + 256) * 8
+    _say(f"batch of {len(bi)} edges: {st['blocks']} blocks, {st['fused_passes']} passes, "
+         f"chunk {chunk}; library bytes held {held0 / 2**30:.2f} GiB before, peak "
+         f"{peak / 2**30:.2f} GiB during the call (panel bound {panel / 2**30:.2f} GiB)")
+    assert chunk == -(-512 // w)
+    assert st["fused_passes"] == -(-st["lowrank_blocks"] // chunk)
+    assert peak - held0 <= panel + 4 * len(block) + (16 << 20)
     pick = np.unique(np.concatenate([[0, len(block) - 1],
                                      W.rng(6104).choice(len(block), 6, replace=False),
                                      np.nonzero((block == bi[0]) | (block == bj[0]))[0]]))

@@ -413,17 +413,21 @@ def _existing_batch(n, s, d, seed, n_ins, n_del, shared):
     return bi, bj, bo
 
 
-@pytest.mark.parametrize("chunk", [1, 64])
+@pytest.mark.parametrize("chunk", [1, 5, 64, 0])
 def test_column_batch_matches_oracle(chunk):
     """Column mode, a batch between existing nodes: Algorithm 6's blocks with the column
     method inside, summed over the blocks on FP64 matrix cores, against the oracle's same
     computation (same K and PartialSim depth) on a ragged shape (n = 1500 nodes, 70 columns);
-    chunk 1 runs one pass per block, chunk 64 one pass for the batch."""
+    chunk 1 runs one pass per block, chunk 64 one pass for the batch, 0 the column-mode
+    default, ceil(512 / 2(K+1)) = 24 blocks per pass at K = 10."""
     n, K, Kps = 1500, 10, 30
     s, d = W.chung_lu(n, 9000, seed=91)
     bi, bj, bo = _existing_batch(n, s, d, seed=92, n_ins=14, n_del=6, shared=4)
     cols = W.column_sample(n, 66, seed=93, extra=[bj[0], bi[0], 0, n - 1])[:70]
     ctx = ctx_for(n, s, d, mode="column", K=K, K_ps=Kps, batch_chunk=chunk)
+    if chunk == 0:
+        chunk = ctx.config().batch_chunk
+        assert chunk == 24
     out, st = ctx.apply_batch_columns(bi, bj, bo, cols, stats=True)
     got = out.cpu().numpy().T
     ref = OI.delta_columns_batch(n, s.astype(np.int64), d.astype(np.int64), bi, bj, bo, cols, C,
