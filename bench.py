@@ -474,10 +474,22 @@ def run_columns(args):
     dt = time.perf_counter() - t0
     kern_ms, launches = ctx.profile_read(reset=True)
     ctx.profile(False)
+    # precision of the float32 output: the last block's first columns against the float64
+    # Delta S columns of the same (last) insertion
+    last = blocks[-1][:8]
+    got = out_buf[:len(last)].double()
+    ref64 = torch.stack([ctx.query_column(int(x), what="delta") for x in last])
+    out32_gap = float((got - ref64).abs().max())
+    out32_scale = float(ref64.abs().max())
+    del got, ref64
     values = float(n) * len(cols) * steps
     out = common(args, cfg, values / dt, "pair-values/s", dt, steps,
                  extra_cfg={"K_ps": Kps, "columns": len(cols), "block": cfg["block"],
                             "output": "float32"})
+    out["accuracy"] = {"vs": "float64 Delta S columns of the same insertion (query_column)",
+                       "columns": len(last), "max_abs_float32_output_vs_fp64": out32_gap,
+                       "max_abs_delta": out32_scale,
+                       "note": "float64 arithmetic; only the output is rounded to float32"}
     out["metric"] = "ΔS column values/s, column-by-column mode (no stored S)"
     out["columns_per_s"] = len(cols) * steps / dt
     # each output value is a 2 (K + 1)-term dot product (4 (K + 1) flop) written as 4 bytes;
@@ -628,9 +640,11 @@ def run_forest(args):
     t_fixed = time.perf_counter() - t1
     diff = float((ctx.S() - ref.S()).abs().max())
     ref.close()
+    accuracy = oracle_accuracy(ctx, n, s, d, "the graph")
     out = common(args, cfg, float(n) * n * args.steps / dt, "S entries/s", dt, args.steps,
                  extra_cfg={"workload": "forest_seeded_n20k", "s_store": "f32 value + f32 "
                             "compensation", "batch_chunk": args.chunk or 64})
+    out["accuracy"] = accuracy
     out["metric"] = "all-pairs SimRank seeded from a spanning forest (Example 1.2), S entries/s"
     out["seconds_per_all_pairs"] = dt / args.steps
     out["forest"] = {"tree_edges": m - st["edges_in"], "batch_edges": st["edges_in"],
@@ -703,12 +717,14 @@ def run_partitioned(args, parts=16, p_cross=0.01):
     t_fixed = time.perf_counter() - t1
     diff = float((ctx.S() - ref.S()).abs().max())
     ref.close()
+    accuracy = oracle_accuracy(ctx, n, s, d, "the graph")
     out = common(args, cfg, float(n) * n * args.steps / dt, "S entries/s", dt, args.steps,
                  extra_cfg={"workload": "partitioned_n20k", "parts": parts,
                             "planted_cross_fraction": p_cross,
                             "s_store": "f32 value + f32 compensation",
                             "batch_chunk": args.chunk or 64})
     out["metric"] = ("all-pairs SimRank over a partitioned graph (Example 1.1), S entries/s")
+    out["accuracy"] = accuracy
     out["seconds_per_all_pairs"] = dt / args.steps
     out["partition"] = {"cross_edges": st["edges_in"], "blocks": st["blocks"],
                         "lowrank_blocks": st["lowrank_blocks"],
@@ -779,6 +795,26 @@ def run_topk(args, nq=4096, k=100):
     res["roofline"] = hbm_roof(8.0 * n_now * nq * args.steps, kern_ms, "topk_kernel",
                                launches, "one row of the store per query (8 B per entry)",
                                counters_for(args, "topk_serving_n50k"))
+    res["accuracy"] = None
+    if ORACLE_POOL is not None:
+        # served lists against the oracle's converged columns of the graph after the batch:
+        # precision@k of the sets and the largest error of a served value
+        fn, fs, fd = graph_after(n, s, d, [(batches[0], counts[0])])
+        qx = [int(x) for x in qs[-1][:8]]
+        exact = oracle_columns(fn, fs, fd, qx)
+        idx, val = ctx.query_topk(np.asarray(qx, np.int32), k)
+        idx, val = idx.cpu().numpy(), val.cpu().numpy()
+        prec, err = [], 0.0
+        for t, x in enumerate(qx):
+            col = exact[t].copy()
+            col[x] = -np.inf  # the query itself is excluded
+            best = np.argsort(-col, kind="stable")[:k]
+            prec.append(len(set(best.tolist()) & set(idx[t].tolist())) / k)
+            err = max(err, float(np.abs(val[t] - exact[t][idx[t]]).max()))
+        res["accuracy"] = {"vs": "oracle FP64 converged columns of the graph after the batch",
+                           "queries": qx, "precision_at_k_min": min(prec),
+                           "precision_at_k_mean": float(np.mean(prec)),
+                           "max_abs_served_value": err}
     res["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         rows = np.stack([ctx.query_column(int(x)).cpu().numpy() for x in qs[0][:256]])
@@ -844,8 +880,21 @@ def run_adjoint(args):
     out["roofline"] = hbm_roof(nbytes, kern_ms, "spmm_qt_rows_kernel", launches,
                                "n^2 x 8 B read + n^2 x 8 B written (+ 2 n^2 x 8 B read on "
                                "every second launch)", counters_for(args, cfg["name"]))
+    out["accuracy"] = None
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
+        import numpy as np
+        # dL/dw for unit upstream gradients at the pairs, on 16 edges, against the oracle's
+        # per-edge adjoint form (converged columns, no dense matrices)
+        edges = np.sort(W.rng(3305).choice(m, 16, replace=False))
+        dw = ctx.backward(at, bt, torch.ones(len(a), dtype=torch.float64,
+                                             device="cuda")).cpu().numpy()
+        path = ORACLE_POOL.stage(n=n, s=np.asarray(s, np.int64), d=np.asarray(d, np.int64),
+                                 w=w, a=a, b=b, C=C)
+        ref = np.asarray(ORACLE_POOL.map("gradient", path, [int(e) for e in edges]))
+        out["accuracy"] = {"vs": "oracle FP64 per-edge adjoint (converged columns)",
+                           "edges": len(edges), "max_abs": float(np.abs(dw[edges] - ref).max()),
+                           "max_abs_gradient": float(np.abs(ref).max())}
         out["cpu_baseline"] = cpu_baseline_gradient(n, s, d, w, a, b, args.cpu_seconds)
     return out
 
@@ -967,9 +1016,9 @@ def oracle_task(kind, path, arg):
             return None
         if kind == "gradient":
             from oracle import adjoint as OA
-            OA.grad_weight_edges(int(z["n"]), z["s"], z["d"], z["w"], z["a"], z["b"], None,
-                                 float(z["C"]), [int(arg)], g_pairs=np.ones(len(z["a"])))
-            return None
+            return float(OA.grad_weight_edges(int(z["n"]), z["s"], z["d"], z["w"], z["a"],
+                                              z["b"], None, float(z["C"]), [int(arg)],
+                                              g_pairs=np.ones(len(z["a"])))[0])
         if kind == "topk":
             from oracle import serving as Sv
             r = int(arg) % len(z["q"])
@@ -1101,6 +1150,21 @@ def oracle_columns(n, s, d, xs):
     import numpy as np
     path = ORACLE_POOL.stage(n=n, s=np.asarray(s, np.int64), d=np.asarray(d, np.int64), C=C)
     return np.stack(ORACLE_POOL.map("columns", path, [int(x) for x in xs]))
+
+
+def oracle_accuracy(ctx, n, s, d, what):
+    """Stored columns against the oracle's converged columns of the same graph (the hub and
+    five uniform nodes); None when the oracle pool is off."""
+    import numpy as np
+    if ORACLE_POOL is None:
+        return None
+    indeg = np.bincount(np.asarray(d, np.int64), minlength=n)
+    xs = list(dict.fromkeys([int(np.argmax(indeg))] +
+                            [int(x) for x in np.random.default_rng(14).integers(n, size=5)]))
+    exact = oracle_columns(n, s, d, xs)
+    got = np.stack([ctx.query_column(x).cpu().numpy() for x in xs])
+    return {"vs": f"oracle FP64 converged single-source columns of {what}", "nodes": xs,
+            "max_abs": float(np.abs(got - exact).max()), "bar": 1e-6}
 
 
 def cpu_baseline_delta_columns(n, s, d, i, j, cols, K, Kps, seconds):
