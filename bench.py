@@ -77,6 +77,15 @@ def main():
                     help="graph rows above this many entries are traversed in chunks "
                          "(0: the library default)")
     ap.add_argument("--plain-edges", type=int, default=24)
+    ap.add_argument("--store", default="blocks", choices=["blocks", "dense"],
+                    help="partitioned: S per pair of partition blocks (Example 1.1), or one "
+                         "dense n x n store")
+    ap.add_argument("--p-cross", type=float, default=0.01,
+                    help="partitioned: fraction of planted cross-community edges")
+    ap.add_argument("--parts", type=int, default=16, help="partitioned: blocks")
+    ap.add_argument("--partition", default="bfs", choices=["bfs", "planted"],
+                    help="partitioned: the library's breadth-first partitioner, or the "
+                         "planted communities (standing in for a partitioner that finds them)")
     ap.add_argument("--case-edges", type=int, default=4,
                     help="single edges timed per case C0-C3 on the plain path")
     ap.add_argument("--cb-edges", default="48,16,16",
@@ -675,7 +684,7 @@ def run_forest(args):
 
 
 # ------------------------------------------------------------------------------ partitioned
-def run_partitioned(args, parts=16, p_cross=0.01):
+def run_partitioned(args):
     import numpy as np
     import torch
 
@@ -684,14 +693,17 @@ def run_partitioned(args, parts=16, p_cross=0.01):
 
     cfg = W.WORKLOADS[2]
     n, m, K = args.n or cfg["n"], args.m or cfg["m"], cfg["K"]
+    p_cross, parts = args.p_cross, args.parts
     log(f"bench: generating {parts} planted communities n={n} m={m}")
-    s, d, _ = W.communities(n, m, parts, p_cross, seed=1102)
+    s, d, planted = W.communities(n, m, parts, p_cross, seed=1102)
     common_cfg = dict(C=C, K=K, s_prec="hilo", batch_chunk=args.chunk or 64,
                       split_rows=args.split_rows)
+    store_cfg = dict(block_store=True) if args.store == "blocks" else {}
 
     def build(profile=False):
-        lab = partition(n, s, d, parts)
-        return Context(n, s, d, init="partitioned", part=lab, profile=profile, **common_cfg)
+        lab = planted if args.partition == "planted" else partition(n, s, d, parts)
+        return Context(n, s, d, init="partitioned", part=lab, profile=profile, **common_cfg,
+                       **store_cfg)
 
     for w in range(args.warmup):
         build().close()
@@ -719,13 +731,22 @@ def run_partitioned(args, parts=16, p_cross=0.01):
     torch.cuda.synchronize()
     t_fixed = time.perf_counter() - t1
     diff = float((ctx.S() - ref.S()).abs().max())
+    dense_bytes = ref.store_bytes()[0]
     ref.close()
     accuracy = oracle_accuracy(ctx, n, s, d, "the graph")
+    store_bytes, store_pairs = ctx.store_bytes()
     out = common(args, cfg, float(n) * n * args.steps / dt, "S entries/s", dt, args.steps,
                  extra_cfg={"workload": "partitioned_n20k", "parts": parts,
                             "planted_cross_fraction": p_cross,
+                            "partition": args.partition,
                             "s_store": "f32 value + f32 compensation",
+                            "store": "block pairs" if args.store == "blocks" else "dense",
                             "batch_chunk": args.chunk or 64})
+    # memory of S: the store held against n^2 entries of 8 bytes (value + compensation)
+    out["store"] = {"bytes": store_bytes, "block_pairs_held": store_pairs,
+                    "block_pairs": parts * (parts + 1) // 2,
+                    "n2_bytes": 8 * n * n, "fraction_of_n2": store_bytes / (8.0 * n * n),
+                    "dense_store_bytes": dense_bytes}
     out["metric"] = ("all-pairs SimRank over a partitioned graph (Example 1.1), S entries/s")
     out["accuracy"] = accuracy
     out["seconds_per_all_pairs"] = dt / args.steps
@@ -735,13 +756,20 @@ def run_partitioned(args, parts=16, p_cross=0.01):
     out["fixed_point_init_s"] = t_fixed
     out["max_abs_vs_fixed_point"] = diff
     pld = 2 * (K + 1)
-    flops = float(n) * (n + 1.0) * pld * st["lowrank_blocks"] * args.steps
+    if args.store == "blocks":
+        # entries of the reached block pairs per deferred block (both triangles), each
+        # 2 (K + 1) multiply-adds for half of them (the pass writes mirrored entries once)
+        flops = float(st["pairs"]) * pld * args.steps
+    else:
+        flops = float(n) * (n + 1.0) * pld * st["lowrank_blocks"] * args.steps
     achieved = flops / (kern_ms / 1e3) / 1e12 if kern_ms > 0 else 0.0
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                       "traffic": traffic("lowrank_gemm_kernel", counters_for(args, "partitioned_n20k")),
-                       "kernel": "lowrank_gemm_kernel (fused batch pass)",
+                       "traffic": None if args.store == "blocks" else
+                       traffic("lowrank_gemm_kernel", counters_for(args, "partitioned_n20k")),
+                       "kernel": "lowrank_gemm_kernel (fused batch pass"
+                                 + (", block-store mode)" if args.store == "blocks" else ")"),
                        "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "share_of_step": round(kern_ms / (1e3 * dt), 3),
                        "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per "

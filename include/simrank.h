@@ -88,7 +88,7 @@ typedef struct sr_config {
                             accumulate pass of apply_batch_columns; 0: the mode's default,
                             64 in dense mode, ceil(512 / (2 (K + 1))) in column mode
                             (passes bounded by arithmetic, not by the output's traffic, with
-                            a panel of at most 512 + 2 (K + 1) columns of n doubles)                  */
+                            a panel of at most 512 + 2 (K + 1) columns of n doubles)       */
   int32_t fused_batch;   /* 1: apply_batch defers low-rank blocks into fused passes;
                             0: each block updates S on its own                              */
   int32_t split_rows;    /* graph rows (in- or out-lists) with more entries are traversed in
@@ -101,7 +101,16 @@ typedef struct sr_config {
                             graph (one per panel slot of a chunk, kept while the node count
                             and the graph's row tiers stay) and replay it; 0: plain launches */
   int32_t update_prec;   /* SR_UPDATE_FP64 | SR_UPDATE_FP32: the fused passes' arithmetic    */
-  int32_t reserved;      /* set to 0                                                        */
+  int32_t block_store;   /* 1 (init_simrank_partitioned only, dense mode): keep S as Example
+                            1.1 does, per pair of partition blocks: the diagonal blocks S_Gi
+                            of the blocks' own edges, and for the cross-block edges only the
+                            block pairs their Delta S reaches, each a dense sub-matrix
+                            allocated when first reached; no n x n store. Such a context
+                            serves query_column (SR_COL_S), query_columns, query_topk,
+                            sr_gather_pairs and sr_copy_S, and takes apply_batch batches of
+                            insertions and deletions between existing nodes (fused passes
+                            into the reached pairs); other updates, backward and
+                            query_topk_noalloc return SR_EMODE. 0: one dense store          */
 } sr_config;
 
 /* Per-update statistics (filled when a non-null pointer is passed; the call then
@@ -126,7 +135,9 @@ typedef struct sr_batch_stats {
   int64_t lowrank_blocks; /* blocks that produced a low-rank Delta S (C0 and C2)           */
   int64_t n_after;        /* node count after the batch                                    */
   int64_t pairs;          /* S entries updated, summed over low-rank blocks, plus border
-                             and diagonal writes of C1 / C2 / C3 blocks                    */
+                             and diagonal writes of C1 / C2 / C3 blocks; with block_store,
+                             the entries of the block pairs a fused pass reaches, per
+                             deferred block of the pass                                   */
   int32_t fused_passes;   /* passes over S made by the fused apply                         */
   int32_t series_replays; /* K-step series chains replayed from captured HIP graphs        */
 } sr_batch_stats;
@@ -318,6 +329,11 @@ sr_status sr_sizes(sr_ctx* ctx, int64_t* n, int64_t* m);
 /* The context's configuration as resolved at init (defaults filled in: capacities,
  * batch_chunk) and as changed since by sr_set_tuning. SR_EINVAL for a NULL argument. */
 sr_status sr_get_config(sr_ctx* ctx, sr_config* out);
+
+/* Bytes of the context's store of S: the dense n x n store (node_cap rows of its leading
+ * dimension), or with block_store the sub-matrices of the block pairs held (pairs: their
+ * count; 0 for a dense store); 0 in column mode. bytes, pairs: NULL or filled. */
+sr_status sr_store_bytes(sr_ctx* ctx, int64_t* bytes, int64_t* pairs);
 
 /* Device memory the library holds now, over all contexts of the process (S, panels, graph
  * arrays, work buffers; not the caller's buffers, not the static no-allocation scratch), and

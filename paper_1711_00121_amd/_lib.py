@@ -40,7 +40,7 @@ class sr_config(C.Structure):
         ("profile", C.c_int32),
         ("graphs", C.c_int32),
         ("update_prec", C.c_int32),
-        ("reserved", C.c_int32),
+        ("block_store", C.c_int32),
     ]
 
 
@@ -105,6 +105,7 @@ SIGNATURES = {
     "sr_copy_S": (C.c_int, [P, P, C.c_int64]),
     "sr_sizes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sr_get_config": (C.c_int, [P, C.POINTER(sr_config)]),
+    "sr_store_bytes": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sr_device_bytes": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32]),
     "sr_edges": (C.c_int, [P, I32P, I32P, F64P, C.c_int64, C.POINTER(C.c_int64)]),
     "sr_last_plan": (C.c_int, [P, I32P, C.c_int64, C.POINTER(C.c_int64)]),

@@ -70,6 +70,21 @@ struct sr_ctx {
   SView S{};
   void* S_mem[2] = {nullptr, nullptr};
 
+  // Block store (Example 1.1; cfg.block_store with init_simrank_partitioned): S kept per
+  // pair of partition blocks (see BlockStore); the dense S above is then not allocated.
+  bool bstore = false;
+  int32_t bs_np = 0;
+  std::vector<int32_t> bs_n;           // members per block
+  std::vector<SView> bs_pairs;         // host copy of the pair table (np x np)
+  int32_t *d_bs_part = nullptr, *d_bs_loc = nullptr, *d_bs_mem = nullptr, *d_bs_n = nullptr;
+  int64_t* d_bs_off = nullptr;
+  SView* d_bs_pairs = nullptr;
+  uint32_t* d_bs_flags = nullptr;      // per pass: deferred block x block x {xi, eta}
+  int64_t bs_flags_cap = 0;
+  BsItem* d_bs_items = nullptr;
+  int64_t bs_items_cap = 0;
+  int64_t bs_bytes = 0;                // bytes of the pairs' sub-matrices
+
   double *SI = nullptr, *Sj = nullptr, *QSI = nullptr, *zbuf = nullptr, *Qz = nullptr,
          *zsum = nullptr, *ytmp = nullptr;
   double* P = nullptr;
@@ -145,6 +160,19 @@ sr_status fail_hip(sr_ctx* c) {
     hipError_t e__ = (expr);                     \
     if (e__ != hipSuccess) return fail_hip(ctx); \
   } while (0)
+
+// The device view of the block store (Example 1.1).
+BlockStore bs_view(const sr_ctx* c) {
+  BlockStore b{};
+  b.pairs = c->d_bs_pairs;
+  b.np = c->bs_np;
+  b.part = c->d_bs_part;
+  b.loc = c->d_bs_loc;
+  b.mem = c->d_bs_mem;
+  b.mem_off = c->d_bs_off;
+  b.mem_n = c->d_bs_n;
+  return b;
+}
 
 DevQ devq(const sr_ctx* c) {
   DevQ q;
@@ -693,8 +721,12 @@ sr_status lowrank_block(sr_ctx* ctx, int case_id, int op, const std::vector<int3
 
   // S[:, I] (with supports) and S[:, j] from the old S.
   const IdList src_rows = ga.I;
-  HC(launch_gather_rows(ctx->S, n_work, src_rows, 0, j, ctx->SI, ctx->Sj, ctx->suppI,
-                        ctx->suppJ, s, ft ? ft->cI : nullptr, ft ? ft->cJ : nullptr));
+  if (ctx->bstore)
+    HC(launch_bs_gather_rows(bs_view(ctx), n_work, src_rows, j, ctx->SI, ctx->Sj,
+                             ft ? ft->cI : nullptr, ft ? ft->cJ : nullptr, s));
+  else
+    HC(launch_gather_rows(ctx->S, n_work, src_rows, 0, j, ctx->SI, ctx->Sj, ctx->suppI,
+                          ctx->suppJ, s, ft ? ft->cI : nullptr, ft ? ft->cJ : nullptr));
   if (ft && !ft->incremental && ft->r_prev > 0)
     HC(launch_panel_correct(ft->P, ft->pld, ft->gstride, ft->r_prev, n_work, src_rows, j, ctx->wts,
                             ctx->SI, ctx->Sj, s));
@@ -1030,6 +1062,13 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)dfree(ctx->d_W);
   (void)dfree(ctx->S_mem[0]);
   (void)dfree(ctx->S_mem[1]);
+  for (SView& v : ctx->bs_pairs) (void)dfree(v.d);
+  int32_t* bsi[] = {ctx->d_bs_part, ctx->d_bs_loc, ctx->d_bs_mem, ctx->d_bs_n};
+  for (int32_t* p : bsi) (void)dfree(p);
+  (void)dfree(ctx->d_bs_off);
+  (void)dfree(ctx->d_bs_pairs);
+  (void)dfree(ctx->d_bs_flags);
+  (void)dfree(ctx->d_bs_items);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp, ctx->ylast,
                   ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd, ctx->corr,
                   ctx->corr_w};
@@ -1053,6 +1092,212 @@ sr_status sr_destroy(sr_ctx* ctx) {
   return SR_OK;
 }
 
+static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
+                           const int32_t* dst, const double* weight, const sr_config* cfg_in,
+                           const void* S0, void* hip_stream, const int32_t* tree_parent,
+                           const int32_t* tree_depth, const int32_t* block_part);
+
+namespace {
+
+// Block store (Example 1.1): pair allocation, initialisation and the fused pass.
+constexpr int32_t kMaxStoreBlocks = 4096;  // the pair table holds np^2 views
+constexpr int64_t kStoreTopkRows = 256;    // query rows staged at a time for top-k
+
+// Copies host ids into ctx->d_ids (grown as needed) once earlier work has read it.
+sr_status stage_ids(sr_ctx* ctx, const int32_t* ids, int64_t cnt) {
+  HC(hipStreamSynchronize(ctx->stream));
+  if (ctx->ids_cap < cnt) {
+    (void)dfree(ctx->d_ids);
+    ctx->d_ids = nullptr;
+    ctx->ids_cap = 0;
+    if (dalloc(&ctx->d_ids, cnt) != hipSuccess) return SR_ENOMEM;
+    ctx->ids_cap = cnt;
+  }
+  HC(hipMemcpy(ctx->d_ids, ids, (size_t)cnt * 4, hipMemcpyHostToDevice));
+  return SR_OK;
+}
+
+// Pair (p, q), p <= q: a zero-filled mem_n[p] x mem_n[q] sub-matrix in the store's precision.
+// The caller uploads the pair table afterwards.
+sr_status bs_alloc_pair(sr_ctx* ctx, int32_t p, int32_t q) {
+  SView& v = ctx->bs_pairs[(int64_t)p * ctx->bs_np + q];
+  if (v.d) return SR_OK;
+  const size_t es = ctx->cfg.s_prec == SR_S_FP32 ? 4 : 8;
+  const size_t bytes = (size_t)ctx->bs_n[p] * (size_t)ctx->bs_n[q] * es;
+  void* mem = nullptr;
+  if (dmalloc(&mem, bytes) != hipSuccess) return SR_ENOMEM;
+  v.prec = ctx->cfg.s_prec;
+  v.ld = ctx->bs_n[q];
+  v.d = (double*)mem;
+  v.hl = (float2*)mem;
+  v.hi = (float*)mem;
+  ctx->bs_bytes += (int64_t)bytes;
+  HC(hipMemsetAsync(mem, 0, bytes, ctx->stream));
+  return SR_OK;
+}
+
+sr_status bs_upload_pairs(sr_ctx* ctx) {
+  HC(hipStreamSynchronize(ctx->stream));  // earlier kernels read the old table
+  HC(hipMemcpy(ctx->d_bs_pairs, ctx->bs_pairs.data(), ctx->bs_pairs.size() * sizeof(SView),
+               hipMemcpyHostToDevice));
+  return SR_OK;
+}
+
+// S of the blocks' own edges into the diagonal pairs, block by block: each block's fixed
+// point on a context of its own nodes (float64), converted into the store's precision.
+sr_status block_store_init(sr_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
+                           const int32_t* dst, const int32_t* part, void* hip_stream) {
+  int32_t np = 0;
+  for (int64_t v = 0; v < n; ++v) np = std::max(np, part[v] + 1);
+  if (np > kMaxStoreBlocks) return SR_ECAPACITY;
+  ctx->bstore = true;
+  ctx->bs_np = np;
+  std::vector<std::vector<int32_t>> mem(np), bs(np), bd(np);
+  std::vector<int32_t> loc(n);
+  for (int32_t v = 0; v < n; ++v) {
+    loc[v] = (int32_t)mem[part[v]].size();
+    mem[part[v]].push_back(v);
+  }
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t p = part[dst[e]];
+    bs[p].push_back(loc[src[e]]);
+    bd[p].push_back(loc[dst[e]]);
+  }
+  ctx->bs_n.assign(np, 0);
+  std::vector<int64_t> off(np + 1, 0);
+  std::vector<int32_t> flat;
+  flat.reserve(n);
+  for (int32_t p = 0; p < np; ++p) {
+    ctx->bs_n[p] = (int32_t)mem[p].size();
+    off[p] = (int64_t)flat.size();
+    flat.insert(flat.end(), mem[p].begin(), mem[p].end());
+  }
+  off[np] = (int64_t)flat.size();
+  if (dalloc(&ctx->d_bs_part, n) != hipSuccess || dalloc(&ctx->d_bs_loc, n) != hipSuccess ||
+      dalloc(&ctx->d_bs_mem, n) != hipSuccess || dalloc(&ctx->d_bs_n, np) != hipSuccess ||
+      dalloc(&ctx->d_bs_off, np + 1) != hipSuccess ||
+      dalloc(&ctx->d_bs_pairs, (int64_t)np * np) != hipSuccess)
+    return SR_ENOMEM;
+  HC(hipMemcpy(ctx->d_bs_part, part, (size_t)n * 4, hipMemcpyHostToDevice));
+  HC(hipMemcpy(ctx->d_bs_loc, loc.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+  HC(hipMemcpy(ctx->d_bs_mem, flat.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+  HC(hipMemcpy(ctx->d_bs_n, ctx->bs_n.data(), (size_t)np * 4, hipMemcpyHostToDevice));
+  HC(hipMemcpy(ctx->d_bs_off, off.data(), (size_t)(np + 1) * 8, hipMemcpyHostToDevice));
+  ctx->bs_pairs.assign((size_t)np * np, SView{});
+  sr_config bc = ctx->cfg;
+  bc.mode = SR_DENSE;
+  bc.s_prec = SR_S_FP64;
+  bc.node_cap = 0;
+  bc.edge_cap = 0;
+  bc.profile = 0;
+  bc.block_store = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    const int64_t nb = (int64_t)mem[p].size();
+    if (nb == 0) continue;
+    sr_ctx* b = nullptr;
+    sr_status st = init_impl(&b, nb, (int64_t)bs[p].size(), bs[p].data(), bd[p].data(),
+                             nullptr, &bc, nullptr, hip_stream, nullptr, nullptr, nullptr);
+    if (st != SR_OK) return st;
+    st = bs_alloc_pair(ctx, p, p);
+    hipError_t e = hipSuccess;
+    if (st == SR_OK)
+      e = launch_bs_place(ctx->bs_pairs[(int64_t)p * np + p], b->S.d, b->S.ld, nb, ctx->stream);
+    if (st == SR_OK && e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    sr_destroy(b);
+    if (st != SR_OK) return st;
+    HC(e);
+  }
+  return bs_upload_pairs(ctx);
+}
+
+// The fused pass of q deferred blocks (panel ctx->Pb) into the block store: the pairs of
+// partition blocks that the blocks' xi and eta supports reach (a pair (p, p') is reached when
+// one deferred block has, for one k, a nonzero xi_k entry in p and a nonzero eta_k entry in
+// p', or the other way round: its Delta S is sum_k xi_k eta_k^T + eta_k xi_k^T) are
+// allocated when new, and the pass adds the chunk's product to every tile of the reached
+// pairs; the other deferred blocks' terms are exact zeros there.
+sr_status bs_flush(sr_ctx* ctx, int q, int64_t n, int64_t* covered) {
+  hipStream_t s = ctx->stream;
+  const int32_t np = ctx->bs_np;
+  const int nk = ctx->cfg.K + 1;
+  const int64_t nf = (int64_t)q * np * nk * 2;
+  if (ctx->bs_flags_cap < nf) {
+    HC(hipStreamSynchronize(s));
+    (void)dfree(ctx->d_bs_flags);
+    ctx->d_bs_flags = nullptr;
+    ctx->bs_flags_cap = 0;
+    if (dalloc(&ctx->d_bs_flags, nf) != hipSuccess) return SR_ENOMEM;
+    ctx->bs_flags_cap = nf;
+  }
+  HC(hipMemsetAsync(ctx->d_bs_flags, 0, (size_t)nf * 4, s));
+  HC(launch_bs_touch(ctx->Pb, ctx->pld, ctx->p_rows * ctx->pld, q, nk, n, ctx->d_bs_part, np,
+                     ctx->d_bs_flags, s));
+  std::vector<uint32_t> f((size_t)nf);
+  HC(hipMemcpyAsync(f.data(), ctx->d_bs_flags, (size_t)nf * 4, hipMemcpyDeviceToHost, s));
+  HC(hipStreamSynchronize(s));
+  std::vector<char> hit((size_t)np * np, 0);
+  std::vector<int32_t> xs, es;
+  for (int d = 0; d < q; ++d)
+    for (int k = 0; k < nk; ++k) {
+      xs.clear();
+      es.clear();
+      for (int32_t p = 0; p < np; ++p) {
+        const size_t at = (((size_t)d * np + p) * nk + k) * 2;
+        if (f[at]) xs.push_back(p);
+        if (f[at + 1]) es.push_back(p);
+      }
+      for (int32_t a : xs)
+        for (int32_t b : es) hit[(size_t)std::min(a, b) * np + std::max(a, b)] = 1;
+    }
+  bool grew = false;
+  std::vector<BsItem> items;
+  *covered = 0;
+  for (int32_t p = 0; p < np; ++p)
+    for (int32_t p2 = p; p2 < np; ++p2) {
+      if (!hit[(size_t)p * np + p2] || ctx->bs_n[p] == 0 || ctx->bs_n[p2] == 0) continue;
+      // entries of S the pair stands for (both triangles)
+      *covered += (int64_t)ctx->bs_n[p] * ctx->bs_n[p2] * (p == p2 ? 1 : 2);
+      if (!ctx->bs_pairs[(size_t)p * np + p2].d) {
+        const sr_status r = bs_alloc_pair(ctx, p, p2);
+        if (r != SR_OK) return r;
+        grew = true;
+      }
+      const int32_t T1 = (ctx->bs_n[p] + 127) / 128, T2 = (ctx->bs_n[p2] + 127) / 128;
+      for (int32_t ti = 0; ti < T1; ++ti)
+        for (int32_t tj = p == p2 ? ti : 0; tj < T2; ++tj) items.push_back({p, p2, ti, tj});
+    }
+  if (grew) {
+    const sr_status r = bs_upload_pairs(ctx);
+    if (r != SR_OK) return r;
+  }
+  if (items.empty()) return SR_OK;
+  const int64_t ni = (int64_t)items.size();
+  HC(hipStreamSynchronize(s));  // the previous pass has read the old item list
+  if (ctx->bs_items_cap < ni) {
+    (void)dfree(ctx->d_bs_items);
+    ctx->d_bs_items = nullptr;
+    ctx->bs_items_cap = 0;
+    const int64_t c = std::max<int64_t>(1024, 2 * ni);
+    if (dmalloc((void**)&ctx->d_bs_items, (size_t)c * sizeof(BsItem)) != hipSuccess)
+      return SR_ENOMEM;
+    ctx->bs_items_cap = c;
+  }
+  HC(hipMemcpy(ctx->d_bs_items, items.data(), (size_t)ni * sizeof(BsItem),
+               hipMemcpyHostToDevice));
+  LowRankArgs la{};
+  la.S.prec = ctx->cfg.s_prec;
+  la.P = ctx->Pb;
+  la.pld = ctx->pld;
+  la.gstride = ctx->p_rows * ctx->pld;
+  la.p_rows = ctx->p_rows;
+  la.r = q * ctx->pld;
+  const BlockStore bv = bs_view(ctx);
+  HC(profiled(ctx, [&]() { return launch_bs_gemm(la, bv, ctx->d_bs_items, ni, s); }));
+  return SR_OK;
+}
+
+}  // namespace
+
 // Context set-up shared by init_simrank, init_simrank_tree and init_simrank_partitioned. With
 // tree_parent, the graph is a spanning forest (tree_parent / tree_depth per node) and S is its
 // closed form; with block_part, every edge lies inside a block (block_part per node) and S is
@@ -1072,9 +1317,10 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   if (!(cfg.C > 0.0 && cfg.C < 1.0) || cfg.K < 0 || cfg.K > 200 || cfg.K_ps < 0 ||
       cfg.s_prec < 0 || cfg.s_prec > 2 || (cfg.mode != SR_DENSE && cfg.mode != SR_COLUMN) ||
       cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0 ||
-      cfg.update_prec < 0 || cfg.update_prec > 1 ||
-      (cfg.split_rows != 0 && cfg.split_rows < kMedium))
+      cfg.update_prec < 0 || cfg.update_prec > 1 || cfg.block_store < 0 ||
+      cfg.block_store > 1 || (cfg.split_rows != 0 && cfg.split_rows < kMedium))
     return SR_EINVAL;
+  if (cfg.block_store && (!block_part || cfg.mode != SR_DENSE)) return SR_EMODE;
   if (cfg.split_rows == 0) cfg.split_rows = kSplitRows;
   // Column mode's default chunk keeps the accumulate passes bounded by matrix-core
   // arithmetic rather than by their read-modify-write of the output: a pass of chunk blocks
@@ -1243,7 +1489,9 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   ctx->S.prec = cfg.s_prec;
   ctx->S.ld = ld;
   const size_t cells = (size_t)node_cap * (size_t)ld;
-  if (cfg.s_prec == SR_S_FP64) {
+  if (cfg.block_store) {
+    // no dense store: S lives in the block pairs (block_store_init below)
+  } else if (cfg.s_prec == SR_S_FP64) {
     IC(dmalloc((void**)&ctx->S_mem[0], cells * 8));
     ctx->S.d = (double*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 8));
@@ -1255,6 +1503,17 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
     IC(dmalloc((void**)&ctx->S_mem[0], cells * 4));
     ctx->S.hi = (float*)ctx->S_mem[0];
     IC(hipMemset(ctx->S_mem[0], 0, cells * 4));
+  }
+
+  if (block_part && cfg.block_store) {
+    const sr_status bst = block_store_init(ctx, n, m, src, dst, block_part, hip_stream);
+    if (bst != SR_OK) {
+      sr_destroy(ctx);
+      return bst;
+    }
+    ctx->updated = false;
+    *out = ctx;
+    return SR_OK;
   }
 
   if (block_part) {
@@ -1604,6 +1863,7 @@ static sr_status unit_update(sr_ctx* ctx, int32_t i, int32_t j, int32_t op, doub
     return SR_ERANGE;
   }
   if (op < 0 && case_id != 0) return SR_ENOENT;
+  if (ctx->bstore) return SR_EMODE;  // the block store takes batches (apply_batch) only
   if (case_id == 0) {
     const bool has = ctx->g.has(i, j);
     if (op > 0 && has && !reweight) return SR_EEXIST;
@@ -1932,6 +2192,13 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   sr_status r = plan_batch(ctx, cnt, bi, bj, bo, plan, n_new, net_edges);
   if (r != SR_OK) return r;
   const int64_t n_old = ctx->g.n;
+  if (ctx->bstore) {
+    // the block store takes fused passes of blocks between existing nodes only
+    if (n_new != n_old || !ctx->cfg.fused_batch || ctx->cfg.gamma_form != SR_GAMMA_CLOSED)
+      return SR_EMODE;
+    for (const Block& b : plan)
+      if (b.case_id != 0) return SR_EMODE;
+  }
   const double C = ctx->cfg.C;
   // New nodes start as isolated nodes (SimRank 1 - C on the diagonal, 0 elsewhere); a block
   // that creates one then writes its case's values.
@@ -1955,6 +2222,15 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   const int64_t replays0 = ctx->graph_replays;
   auto flush = [&]() -> sr_status {
     if (q == 0) return SR_OK;
+    if (ctx->bstore) {
+      int64_t covered = 0;
+      const sr_status rb = bs_flush(ctx, q, n_new, &covered);
+      if (rb != SR_OK) return rb;
+      pairs += covered * q;  // the pass updates these entries once per deferred block
+      ++passes;
+      q = 0;
+      return SR_OK;
+    }
     LowRankArgs la{};
     la.S = ctx->S;
     la.P = ctx->Pb;
@@ -2082,7 +2358,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
         r = lowrank_block(ctx, b.case_id, b.op, b.I, b.j, n_new, nullptr, fused ? &ft : nullptr,
                           dev_of[bi]);
         ++lowrank;
-        pairs += n_new * n_new;
+        if (!ctx->bstore) pairs += n_new * n_new;
         if (r == SR_OK && incremental) {
           // this block's terms for the chunk's later slots
           const int s0 = slot_of[bi] + 1, s1 = chunk_base[chunk_of[bi] + 1];
@@ -2323,6 +2599,12 @@ sr_status query_column(sr_ctx* ctx, int32_t x, int32_t what, double* out_dev) {
   if (x < 0 || x >= n) return SR_ERANGE;
   if (what == SR_COL_S) {
     if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+    if (ctx->bstore) {
+      const sr_status r = stage_ids(ctx, &x, 1);
+      if (r != SR_OK) return r;
+      HC(launch_bs_rows(bs_view(ctx), n, ctx->d_ids, 1, out_dev, nullptr, n, ctx->stream));
+      return SR_OK;
+    }
     HC(launch_copy_row(ctx->S, n, x, out_dev, ctx->stream));
     return SR_OK;
   }
@@ -2349,6 +2631,11 @@ sr_status query_columns(sr_ctx* ctx, const int32_t* cols, int32_t ncols, float* 
   }
   HC(hipStreamSynchronize(ctx->stream));  // d_ids may be read by earlier work
   HC(hipMemcpy(ctx->d_ids, cols, (size_t)ncols * 4, hipMemcpyHostToDevice));
+  if (ctx->cfg.mode == SR_DENSE && ctx->bstore) {
+    HC(launch_bs_rows(bs_view(ctx), n, ctx->d_ids, ncols, nullptr, out_dev, ld_out,
+                      ctx->stream));
+    return SR_OK;
+  }
   if (ctx->cfg.mode == SR_DENSE) {
     HC(launch_rows_to_f32(ctx->S, n, ctx->d_ids, ncols, out_dev, ld_out, ctx->stream));
     return SR_OK;
@@ -2377,6 +2664,27 @@ sr_status query_topk(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t k,
   HC(hipMemcpy(ctx->d_ids, q, (size_t)nq * 4, hipMemcpyHostToDevice));
   hipStream_t s = ctx->stream;
   const int ex = exclude_self ? 1 : 0;
+  if (ctx->cfg.mode == SR_DENSE && ctx->bstore) {
+    // the queries' rows of S gathered from the block pairs, then selected as vectors
+    const int64_t chunk = std::min<int64_t>(nq, kStoreTopkRows);
+    double* rows = nullptr;
+    if (dalloc(&rows, chunk * n) != hipSuccess) return SR_ENOMEM;
+    hipError_t e = hipSuccess;
+    for (int64_t t = 0; t < nq && e == hipSuccess; t += chunk) {
+      const int c = (int)std::min<int64_t>(chunk, nq - t);
+      e = launch_bs_rows(bs_view(ctx), n, ctx->d_ids + t, c, rows, nullptr, n, s);
+      if (e == hipSuccess)
+        e = profiled(ctx, [&]() {
+          return launch_topk(ctx->S, rows, n, ctx->d_ids + t, c, n, k, ex, idx_dev + t * k,
+                             val_dev + t * k, s);
+        });
+    }
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)dfree(rows);
+    HC(e);
+    HC(e2);
+    return SR_OK;
+  }
   if (ctx->cfg.mode == SR_DENSE) {
     HC(profiled(ctx, [&]() {
       return launch_topk(ctx->S, nullptr, 0, ctx->d_ids, nq, n, k, ex, idx_dev, val_dev, s);
@@ -2411,6 +2719,7 @@ sr_status query_topk_noalloc(sr_ctx* ctx, const int32_t* q, int32_t nq, int32_t 
   const int64_t n = ctx->g.n;
   if (k < 1 || k > kTopkMax || k > n - (exclude_self ? 1 : 0)) return SR_EINVAL;
   if (nq > kScratchIds) return SR_ECAPACITY;
+  if (ctx->bstore) return SR_EMODE;  // the block store's selection stages rows
   for (int32_t t = 0; t < nq; ++t)
     if (q[t] < 0 || q[t] >= n) return SR_ERANGE;
   if (nq == 0) return SR_OK;
@@ -2448,6 +2757,10 @@ sr_status sr_gather_pairs(sr_ctx* ctx, int64_t np, const int32_t* a, const int32
   if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
   const sr_status rs = check_pair_ids(ctx, np, a, b);
   if (rs != SR_OK) return rs;
+  if (ctx->bstore) {
+    HC(launch_bs_pairs(bs_view(ctx), np, a, b, out, ctx->stream));
+    return SR_OK;
+  }
   HC(launch_gather_pairs(ctx->S, np, a, b, out, ctx->stream));
   return SR_OK;
 }
@@ -2457,6 +2770,15 @@ sr_status sr_copy_S(sr_ctx* ctx, double* out_dev, int64_t ld) {
   if (ctx->poisoned) return SR_EHIP;
   if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
   if (ld < ctx->g.n) return SR_EINVAL;
+  if (ctx->bstore) {
+    const int64_t n = ctx->g.n;
+    std::vector<int32_t> all(n);
+    for (int64_t v = 0; v < n; ++v) all[v] = (int32_t)v;
+    const sr_status r = stage_ids(ctx, all.data(), n);
+    if (r != SR_OK) return r;
+    HC(launch_bs_rows(bs_view(ctx), n, ctx->d_ids, n, out_dev, nullptr, ld, ctx->stream));
+    return SR_OK;
+  }
   HC(launch_from_store(ctx->S, ctx->g.n, out_dev, ld, ctx->stream));
   return SR_OK;
 }
@@ -2517,6 +2839,20 @@ sr_status sr_get_config(sr_ctx* ctx, sr_config* out) {
   return SR_OK;
 }
 
+sr_status sr_store_bytes(sr_ctx* ctx, int64_t* bytes, int64_t* pairs) {
+  if (!valid_ctx(ctx)) return SR_EINVAL;
+  int64_t b = 0, np = 0;
+  if (ctx->bstore) {
+    b = ctx->bs_bytes;
+    for (const SView& v : ctx->bs_pairs) np += v.d != nullptr;
+  } else if (ctx->cfg.mode == SR_DENSE) {
+    b = ctx->node_cap * ctx->S.ld * (ctx->cfg.s_prec == SR_S_FP32 ? 4 : 8);
+  }
+  if (bytes) *bytes = b;
+  if (pairs) *pairs = np;
+  return SR_OK;
+}
+
 sr_status sr_device_bytes(int64_t* held, int64_t* peak, int32_t reset_peak) {
   std::lock_guard<std::mutex> lk(g_mem_mu);
   if (held) *held = g_mem_now;
@@ -2539,7 +2875,7 @@ sr_status backward(sr_ctx* ctx, int64_t npairs, const int32_t* a_dev, const int3
   if (!valid_ctx(ctx) || npairs < 0 || !dw_dev || (npairs > 0 && (!a_dev || !b_dev || !g_dev)))
     return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
-  if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+  if (ctx->cfg.mode != SR_DENSE || ctx->bstore) return SR_EMODE;
   {
     const sr_status rs = check_pair_ids(ctx, npairs, a_dev, b_dev);
     if (rs != SR_OK) return rs;
@@ -2642,7 +2978,7 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
                         double* gemm_ms, double* corr_ms) {
   if (!valid_ctx(ctx) || !gemm_ms || !corr_ms || blocks < 1 || reps < 1) return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
-  if (ctx->cfg.mode != SR_DENSE) return SR_EMODE;
+  if (ctx->cfg.mode != SR_DENSE || ctx->bstore) return SR_EMODE;
   if (variant < 0 || variant >= kGemmVariants) return SR_ERANGE;
   const int64_t n = ctx->g.n;
   const int pld = ctx->pld;

@@ -358,6 +358,54 @@ hipError_t launch_place_block(SView S, const int32_t* gid, int64_t nb, const dou
 // n x n block of the store by Example 1.2's closed form.
 hipError_t launch_tree_init(SView S, int64_t n, const int32_t* parent, const int32_t* depth,
                             double C, hipStream_t s);
+// ---------------------------------------------------------------------------------------
+// Block store (Example 1.1): S kept per pair of partition blocks instead of as one n x n
+// matrix. Block p holds the nodes mem[mem_off[p] .. mem_off[p] + mem_n[p]) (ascending ids);
+// part[a] is a's block and loc[a] its position there. pairs[p * np + q] (p <= q) is the
+// dense mem_n[p] x mem_n[q] sub-matrix S[mem_p][mem_q] (row-major, ld = mem_n[q], the
+// store's precision), or a view with null pointers when the pair holds no nonzero entry;
+// entries with p > q are read from pair (q, p), transposed. The diagonal pairs hold S_old's
+// blocks S_Gi; the others only the Delta S of cross-block updates.
+struct BlockStore {
+  const SView* pairs;
+  int32_t np;
+  const int32_t* part;
+  const int32_t* loc;
+  const int32_t* mem;
+  const int64_t* mem_off;
+  const int32_t* mem_n;
+};
+// One 128 x 128 tile (ti, tj) of pair (p, q), p <= q (ti <= tj when p == q).
+struct BsItem {
+  int32_t p, q, ti, tj;
+};
+// SI[a] = sum over I of S[i][a] (+ cI[a]), Sj[a] = S[j][a] (+ cJ[a]), a < n (j < 0: none).
+hipError_t launch_bs_gather_rows(const BlockStore& B, int64_t n, const IdList& I, int32_t j,
+                                 double* SI, double* Sj, const double* cI, const double* cJ,
+                                 hipStream_t s);
+// Rows of S as dense vectors: out[t * ld_out + a] = S[rows[t]][a] (float64, or float32 when
+// out32 is set), t < nrows, a < n.
+hipError_t launch_bs_rows(const BlockStore& B, int64_t n, const int32_t* rows, int64_t nrows,
+                          double* out, float* out32, int64_t ld_out, hipStream_t s);
+// out[t] = S[a[t]][b[t]], t < cnt.
+hipError_t launch_bs_pairs(const BlockStore& B, int64_t cnt, const int32_t* a,
+                           const int32_t* b, double* out, hipStream_t s);
+// Which blocks the deferred blocks of a fused pass reach: for deferred block d < q (panel
+// segment d, gstride doubles apart, pld doubles per row, columns 2k = xi_k, 2k + 1 = eta_k,
+// k < nk) and node a < n with a nonzero xi_k (eta_k) entry,
+// flags[((d * np + part[a]) * nk + k) * 2] ([... + 1]) is set to 1. flags must hold
+// q * np * nk * 2 words, zeroed by the caller.
+hipError_t launch_bs_touch(const double* P, int pld, int64_t gstride, int q, int nk, int64_t n,
+                           const int32_t* part, int32_t np, uint32_t* flags, hipStream_t s);
+// Writes a block's float64 S (nb x nb, ld ldb) into its diagonal pair view.
+hipError_t launch_bs_place(SView dst, const double* Sb, int64_t ldb, int64_t nb,
+                           hipStream_t s);
+// Fused pass into the block store: for every listed tile, S[mem_p rows][mem_q cols] +=
+// sum_{c < r} P[a][c] P[b][c ^ 1] over the panel a.P (block-major, a.pld, a.gstride; r a
+// multiple of 16), mirrored inside diagonal pairs so that they stay exactly symmetric.
+hipError_t launch_bs_gemm(const LowRankArgs& a, const BlockStore& B, const BsItem* items,
+                          int64_t nitems, hipStream_t s);
+
 hipError_t launch_fill_diag(double* A, int64_t n, int64_t ld, double v, hipStream_t s);
 hipError_t launch_diag_range(SView S, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_mfma_probe(const double* a, const double* b, double* out, hipStream_t s);

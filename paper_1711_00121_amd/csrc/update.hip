@@ -305,7 +305,7 @@ __global__ __launch_bounds__(NT) void lowrank_strip_kernel(LowRankArgs g) {
 // the panel slices per XCD from ~65 to 16, measured 2.4% slower: the pass is bound by the
 // matrix cores, not by these re-reads.
 constexpr int GT = 128;       // tile rows = tile cols
-constexpr int GC = 16;        // panel columns per chunk of the default variant (and of RECT)
+constexpr int GC = 16;        // panel columns per chunk of the default variant (and of kRect, kBlk)
 // LDS pitch in doubles. A wave reads 16 rows x 4 columns per operand; with 64 four-byte banks
 // a half-wave (16 rows x 2 columns) touches 32 distinct doubles when 18 * row mod 32 spreads
 // the rows over the even double slots, so the reads are free of bank conflicts.
@@ -326,14 +326,26 @@ __device__ __forceinline__ void tri_tile(int64_t t, int64_t T, int64_t& I, int64
 
 constexpr int64_t kRectGroup = 8;
 
-// RECT (column mode, batches): a rectangular product accumulated into a float64 output,
+// Modes of lowrank_gemm_kernel.
+constexpr int kSym = 0;   // fused pass into the dense S (upper triangle of tiles, mirrored)
+constexpr int kRect = 1;  // column-mode batches: accumulate into a float64 output
+constexpr int kBlk = 2;   // fused pass into the block store
+
+// kRect (column mode, batches): a rectangular product accumulated into a float64 output,
 //     acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1]   (p < nrows, a < ncols),
 // over T row tiles (list positions) x TJ column tiles (nodes), without the symmetry; A rows
 // are gathered through the list (positions past it read its last entry, not stored).
+// kBlk: one workgroup per listed tile (ti, tj) of a block pair (p, q); A rows are the members
+// of block p from 128 ti on, B rows those of block q from 128 tj on (positions past a
+// block read its last member and are not stored), and the product is added to the pair's
+// sub-matrix; inside a diagonal pair (p == q, ti <= tj) the mirrored entry is written from
+// the same sum, and a diagonal tile stores a <= b only, as the symmetric mode does.
 // GCt: panel columns per LDS chunk; GPt: LDS row pitch in doubles; WPC: workgroups per CU.
-template <int PREC, bool RECT = false, int GCt = GC, int GPt = GP, int WPC = 2>
+template <int PREC, int MODE = kSym, int GCt = GC, int GPt = GP, int WPC = 2>
 __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, int64_t T,
-                                                            int64_t per, int64_t TJ = 0) {
+                                                            int64_t per, int64_t TJ = 0,
+                                                            BlockStore bs = {},
+                                                            const BsItem* items = nullptr) {
   constexpr int GL = GT * (GCt / 2) / NT;  // double2 loads per thread per side per chunk
   constexpr int GR = NT / (GCt / 2);       // rows staged per load round
   __shared__ double As[2][GT * GPt];
@@ -341,7 +353,15 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
   const int64_t w = blockIdx.x;
   const int64_t t = (w % NXCD) * per + w / NXCD;
   int64_t I, J;
-  if constexpr (RECT) {
+  [[maybe_unused]] int32_t bp = 0, bq = 0;
+  if constexpr (MODE == kBlk) {
+    if (t >= T) return;  // T: the number of listed tiles
+    const BsItem it = items[t];
+    bp = it.p;
+    bq = it.q;
+    I = it.ti;
+    J = it.tj;
+  } else if constexpr (MODE == kRect) {
     // Tiles in groups of kRectGroup row tiles, column-major inside a group: the workgroups
     // running together on one XCD share one column tile (a slice of the panel, read from HBM
     // once per group) and the group's row tiles (gathered rows, small enough to stay cached).
@@ -369,13 +389,28 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
   const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
   const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
   const int64_t ustep = GR * (int64_t)g.pld;
-  // RECT: the A rows of this thread, gathered through the list
-  int64_t arow[RECT ? GL : 1];
-  if constexpr (RECT) {
+  // kRect: the A rows of this thread, gathered through the list; kBlk: the A and B rows,
+  // gathered through the two blocks' member lists
+  constexpr bool GA = MODE != kSym;
+  constexpr bool GB = MODE == kBlk;
+  int64_t arow[GA ? GL : 1], brow[GB ? GL : 1];
+  [[maybe_unused]] int64_t na = 0, nb = 0;
+  if constexpr (MODE == kRect) {
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
       const int64_t p = r0 + lrow + GR * u;
       arow[u] = (int64_t)g.rows[p < g.nrows ? p : g.nrows - 1] * g.pld + lcol;
+    }
+  } else if constexpr (MODE == kBlk) {
+    const int32_t* ma = bs.mem + bs.mem_off[bp];
+    const int32_t* mb = bs.mem + bs.mem_off[bq];
+    na = bs.mem_n[bp];
+    nb = bs.mem_n[bq];
+#pragma unroll
+    for (int u = 0; u < GL; ++u) {
+      const int64_t p = r0 + lrow + GR * u, q = c0 + lrow + GR * u;
+      arow[u] = (int64_t)ma[p < na ? p : na - 1] * g.pld + lcol;
+      brow[u] = (int64_t)mb[q < nb ? q : nb - 1] * g.pld + lcol;
     }
   }
   double2 ra[GL], rb[GL];
@@ -384,11 +419,14 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
     const int64_t cb = (int64_t)((ch * GCt) / g.pld) * g.gstride + (ch * GCt) % g.pld;
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      if constexpr (RECT)
+      if constexpr (GA)
         ra[u] = *reinterpret_cast<const double2*>(g.P + arow[u] + cb);
       else
         ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
-      rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
+      if constexpr (GB)
+        rb[u] = *reinterpret_cast<const double2*>(g.P + brow[u] + cb);
+      else
+        rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
     }
   };
   auto store = [&](int buf) {
@@ -435,7 +473,42 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
     __syncthreads();
   }
 
-  if constexpr (RECT) {
+  if constexpr (MODE == kBlk) {
+    // the pair's sub-matrix += acc, one row sub-tile at a time (loads first, then stores);
+    // inside a diagonal pair the mirrored entry goes with it
+    const SView o = bs.pairs[(int64_t)bp * bs.np + bq];
+    const bool mir = bp == bq;
+    const bool diag = mir && I == J;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      Raw<PREC> x[4][4], y[4][4];
+      int on[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
+          const int64_t b = c0 + wc * 64 + q * 16 + l16;
+          on[q][v] = a < na && b < nb;
+          sload<PREC>(o, on[q][v] ? a * o.ld + b : 0, x[q][v]);
+          if (mir) sload<PREC>(o, on[q][v] ? b * o.ld + a : 0, y[q][v]);
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (!on[q][v]) continue;
+          const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
+          const int64_t b = c0 + wc * 64 + q * 16 + l16;
+          const double d = acc[s][q][v];
+          if (!diag || a <= b) sput<PREC>(o, a * o.ld + b, sval<PREC>(x[q][v]) + d);
+          if (mir && (!diag || a < b)) sput<PREC>(o, b * o.ld + a, sval<PREC>(y[q][v]) + d);
+        }
+    }
+    return;
+  }
+
+  if constexpr (MODE == kRect) {
     // acc_out[p][a] += acc, one row sub-tile at a time (loads first, then the stores)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -955,10 +1028,10 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     constexpr int P = decltype(prec)::value;
     switch (a.variant) {
       case kGemmF32: lowrank_gemm_f32_kernel<P><<<grid, NT, 0, s>>>(a, T, per); break;
-      case 0: lowrank_gemm_kernel<P, false, 16, 18, 2><<<grid, NT, 0, s>>>(a, T, per); break;
-      case 1: lowrank_gemm_kernel<P, false, 16, 20, 2><<<grid, NT, 0, s>>>(a, T, per); break;
-      case 2: lowrank_gemm_kernel<P, false, 32, 34, 1><<<grid, NT, 0, s>>>(a, T, per); break;
-      default: lowrank_gemm_kernel<P, false, 32, 36, 1><<<grid, NT, 0, s>>>(a, T, per); break;
+      case 0: lowrank_gemm_kernel<P, kSym, 16, 18, 2><<<grid, NT, 0, s>>>(a, T, per); break;
+      case 1: lowrank_gemm_kernel<P, kSym, 16, 20, 2><<<grid, NT, 0, s>>>(a, T, per); break;
+      case 2: lowrank_gemm_kernel<P, kSym, 32, 34, 1><<<grid, NT, 0, s>>>(a, T, per); break;
+      default: lowrank_gemm_kernel<P, kSym, 32, 36, 1><<<grid, NT, 0, s>>>(a, T, per); break;
     }
   };
   if (a.S.prec == PREC_FP64)
@@ -967,6 +1040,21 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     go(std::integral_constant<int, PREC_HILO>{});
   else
     go(std::integral_constant<int, PREC_FP32>{});
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_gemm(const LowRankArgs& a, const BlockStore& B, const BsItem* items,
+                          int64_t nitems, hipStream_t s) {
+  if (nitems <= 0 || a.r <= 0) return hipSuccess;
+  if (a.r % GC != 0 || a.pld % GC != 0 || !items) return hipErrorInvalidValue;
+  const int64_t per = (nitems + NXCD - 1) / NXCD;
+  const unsigned grid = (unsigned)(per * NXCD);
+  if (a.S.prec == PREC_FP64)
+    lowrank_gemm_kernel<PREC_FP64, kBlk><<<grid, NT, 0, s>>>(a, nitems, per, 0, B, items);
+  else if (a.S.prec == PREC_HILO)
+    lowrank_gemm_kernel<PREC_HILO, kBlk><<<grid, NT, 0, s>>>(a, nitems, per, 0, B, items);
+  else
+    lowrank_gemm_kernel<PREC_FP32, kBlk><<<grid, NT, 0, s>>>(a, nitems, per, 0, B, items);
   return hipGetLastError();
 }
 
@@ -980,7 +1068,7 @@ hipError_t launch_lowrank_acc(const LowRankArgs& a, hipStream_t s) {
   if (a.p_rows < TJ * GT) return hipErrorInvalidValue;
   const int64_t tiles = T * TJ;
   const int64_t per = (tiles + NXCD - 1) / NXCD;
-  lowrank_gemm_kernel<PREC_FP64, true><<<(unsigned)(per * NXCD), NT, 0, s>>>(a, T, per, TJ);
+  lowrank_gemm_kernel<PREC_FP64, kRect><<<(unsigned)(per * NXCD), NT, 0, s>>>(a, T, per, TJ);
   return hipGetLastError();
 }
 

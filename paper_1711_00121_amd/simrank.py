@@ -40,7 +40,7 @@ def default_config(**kw):
             v = _GAMMA[v] if isinstance(v, str) else v
         elif k == "update_prec":
             v = _UPDATE[v] if isinstance(v, str) else v
-        elif k in ("prune", "fused_batch", "profile", "graphs"):
+        elif k in ("prune", "fused_batch", "profile", "graphs", "block_store"):
             v = int(bool(v))
         setattr(cfg, k, v)
     return cfg
@@ -73,7 +73,8 @@ class Context:
     S (fixed point of eq (03a) on the device unless ``S0`` is given). Config keys follow
     ``sr_config``: C, K, K_ps, s_prec ('fp64' | 'hilo' | 'fp32'), mode ('dense' | 'column'),
     gamma_form ('closed' | 'direct'), prune, node_cap, edge_cap, init_tol, init_max_iter,
-    batch_chunk, fused_batch, split_rows, profile, graphs, update_prec ('fp64' | 'fp32').
+    batch_chunk, fused_batch, split_rows, profile, graphs, update_prec ('fp64' | 'fp32'),
+    block_store (partitioned contexts: S kept per pair of blocks, Example 1.1).
     """
 
     def __init__(self, n, src, dst, weight=None, S0=None, stream=None, init="fixed_point",
@@ -301,6 +302,12 @@ class Context:
         L.check(self.lib.sr_time_fused(self.h, int(variant), int(blocks), int(reps), C.byref(g),
                                        C.byref(c)), "sr_time_fused")
         return g.value, c.value
+
+    def store_bytes(self):
+        """(bytes, pairs): bytes of the store of S, and the block pairs held (block store)."""
+        b, np_ = C.c_int64(), C.c_int64()
+        L.check(self.lib.sr_store_bytes(self.h, C.byref(b), C.byref(np_)), "sr_store_bytes")
+        return b.value, np_.value
 
     def config(self):
         """The configuration as resolved at init (capacities, batch_chunk filled in) and as
