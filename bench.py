@@ -211,9 +211,13 @@ def run_batch(args):
         passes += st["fused_passes"]
         replays += st["series_replays"]
         nt = float(st["n_after"])
-        # Delta S is symmetric: a low-rank block's work is its n (n + 1) / 2 distinct entries
-        # at 2 (K + 1) multiply-adds each, n the node count of the batch that applies it
-        flops += nt * (nt + 1.0) * 2 * (K + 1) * st["lowrank_blocks"]
+        # Delta S is symmetric: a fused pass's work is, per low-rank block, the distinct
+        # entries (a <= b) over the nodes the pass reaches, at 2 (K + 1) multiply-adds each;
+        # without fused passes a block covers all n (n + 1) / 2
+        if st["fused_passes"]:
+            flops += float(st["pass_entries"]) * 4 * (K + 1)
+        else:
+            flops += nt * (nt + 1.0) * 2 * (K + 1) * st["lowrank_blocks"]
         log(f"bench: step {k}: {len(bi)} edges ({st['edges_net']} net), {st['blocks']} blocks "
             f"({st['lowrank_blocks']} low-rank), {st['fused_passes']} fused passes, "
             f"n = {st['n_after']}")
@@ -329,8 +333,9 @@ def run_batch(args):
                 "kernel": "lowrank_gemm_kernel (fused batch pass)" if args.update_prec == "fp64"
                           else "lowrank_gemm_f32_kernel (fused batch pass, float32 matrix cores)",
                 "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
-                "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
-                               "block, n the node count of its batch"}
+                "algorithmic": "r (r + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
+                               "block, r the nodes its fused pass reaches (nonzero panel "
+                               "rows)"}
     else:
         roof = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
                         "16 B per pair-update (S value + compensation, read + write)",
@@ -665,7 +670,7 @@ def run_forest(args):
     out["fixed_point_init_s"] = t_fixed
     out["max_abs_vs_fixed_point"] = diff
     pld = 2 * (K + 1)
-    flops = float(n) * (n + 1.0) * pld * st["lowrank_blocks"] * args.steps
+    flops = float(st["pass_entries"]) * 2 * pld * args.steps
     achieved = flops / (kern_ms / 1e3) / 1e12
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -674,8 +679,8 @@ def run_forest(args):
                        "kernel": "lowrank_gemm_kernel (fused batch pass)",
                        "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "share_of_step": round(kern_ms / (1e3 * dt), 3),
-                       "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per "
-                                      "low-rank block"}
+                       "algorithmic": "r (r + 1) / 2 distinct entries x 4 (K + 1) flop per "
+                                      "low-rank block, r the nodes its fused pass reaches"}
     ctx.close()
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
@@ -761,7 +766,7 @@ def run_partitioned(args):
         # 2 (K + 1) multiply-adds for half of them (the pass writes mirrored entries once)
         flops = float(st["pairs"]) * pld * args.steps
     else:
-        flops = float(n) * (n + 1.0) * pld * st["lowrank_blocks"] * args.steps
+        flops = float(st["pass_entries"]) * 2 * pld * args.steps
     achieved = flops / (kern_ms / 1e3) / 1e12 if kern_ms > 0 else 0.0
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -772,8 +777,8 @@ def run_partitioned(args):
                                  + (", block-store mode)" if args.store == "blocks" else ")"),
                        "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                        "share_of_step": round(kern_ms / (1e3 * dt), 3),
-                       "algorithmic": "n (n + 1) / 2 distinct entries x 4 (K + 1) flop per "
-                                      "low-rank block"}
+                       "algorithmic": "r (r + 1) / 2 distinct entries x 4 (K + 1) flop per "
+                                      "low-rank block, r the nodes its fused pass reaches"}
     ctx.close()
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:

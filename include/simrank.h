@@ -135,11 +135,15 @@ typedef struct sr_batch_stats {
   int64_t lowrank_blocks; /* blocks that produced a low-rank Delta S (C0 and C2)           */
   int64_t n_after;        /* node count after the batch                                    */
   int64_t pairs;          /* S entries updated, summed over low-rank blocks, plus border
-                             and diagonal writes of C1 / C2 / C3 blocks; with block_store,
-                             the entries of the block pairs a fused pass reaches, per
-                             deferred block of the pass                                   */
+                             and diagonal writes of C1 / C2 / C3 blocks; a fused pass counts
+                             the square of the nodes it reaches (those with a nonzero panel
+                             row), per deferred block; with block_store, the entries of the
+                             block pairs the pass reaches, per deferred block              */
   int32_t fused_passes;   /* passes over S made by the fused apply                         */
   int32_t series_replays; /* K-step series chains replayed from captured HIP graphs        */
+  int64_t pass_entries;   /* dense fused passes: distinct entries (a <= b) of S that their
+                             GEMMs computed, summed over the passes' low-rank blocks (a
+                             pass covers the square of the nodes its blocks reach)          */
 } sr_batch_stats;
 
 /* Fills *cfg with defaults: C = 0.6, K = 15, K_ps = 30, SR_S_FP64, SR_DENSE,

@@ -69,6 +69,7 @@ class sr_batch_stats(C.Structure):
         ("pairs", C.c_int64),
         ("fused_passes", C.c_int32),
         ("series_replays", C.c_int32),
+        ("pass_entries", C.c_int64),
     ]
 
 

@@ -120,6 +120,12 @@ struct sr_ctx {
 
   double* xs = nullptr;    // PartialSim vectors (column mode): (K_ps + 1) pairs x node_cap
   double* xd = nullptr;    // PartialSim: two pair vectors x_t / d (d: row weight of Q)
+  // Fused passes: the nodes a pass reaches (bitmap, ascending list, and per pass of a batch
+  // the list's length, read on the device by the pass and on the host for statistics).
+  uint32_t* d_act_bits = nullptr;
+  int32_t* d_act = nullptr;
+  int64_t* d_act_cnt = nullptr;
+  int64_t act_cnt_cap = 0;
   int corr_slots = 0;      // fused batches: slots per chunk at most (2 batch_chunk + 32)
   double* corr = nullptr;  // correction vectors, 2 corr_slots x p_rows
   double* corr_w = nullptr;  // their weights, 2 corr_slots x 64
@@ -1069,6 +1075,9 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)dfree(ctx->d_bs_pairs);
   (void)dfree(ctx->d_bs_flags);
   (void)dfree(ctx->d_bs_items);
+  (void)dfree(ctx->d_act_bits);
+  (void)dfree(ctx->d_act);
+  (void)dfree(ctx->d_act_cnt);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp, ctx->ylast,
                   ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd, ctx->corr,
                   ctx->corr_w};
@@ -2219,6 +2228,25 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   }
   int q = 0;  // deferred blocks in the current chunk
   int passes = 0;
+  std::vector<int> pass_blocks;  // deferred blocks of each dense fused pass
+  if (fused && !ctx->bstore) {
+    // per pass: the reached-node list's length (at most one pass per plan block, plus one)
+    if (!ctx->d_act) {
+      if (dalloc(&ctx->d_act, ctx->node_cap) != hipSuccess ||
+          dalloc(&ctx->d_act_bits, (int64_t)ctx->W) != hipSuccess)
+        return SR_ENOMEM;
+    }
+    const int64_t need = (int64_t)plan.size() + 1;
+    if (ctx->act_cnt_cap < need) {
+      HC(hipStreamSynchronize(ctx->stream));
+      (void)dfree(ctx->d_act_cnt);
+      ctx->d_act_cnt = nullptr;
+      ctx->act_cnt_cap = 0;
+      const int64_t c = std::max<int64_t>(256, 2 * need);
+      if (dalloc(&ctx->d_act_cnt, c) != hipSuccess) return SR_ENOMEM;
+      ctx->act_cnt_cap = c;
+    }
+  }
   const int64_t replays0 = ctx->graph_replays;
   auto flush = [&]() -> sr_status {
     if (q == 0) return SR_OK;
@@ -2231,11 +2259,20 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
       q = 0;
       return SR_OK;
     }
+    // the nodes the pass reaches: those with a nonzero panel row in one of its deferred
+    // blocks; every other row and column of the pass's update is an exact zero
+    const int64_t gstride = ctx->p_rows * ctx->pld;
+    const int32_t words = (int32_t)((n_new + 31) / 32);
+    int64_t* cnt_dev = ctx->d_act_cnt + passes;
+    HC(hipMemsetAsync(ctx->d_act_bits, 0, (size_t)words * 4, ctx->stream));
+    HC(launch_pass_rows(ctx->Pb, ctx->pld, gstride, q, 2 * (ctx->cfg.K + 1), n_new,
+                        ctx->d_act_bits, ctx->stream));
+    HC(launch_bits_to_list(ctx->d_act_bits, n_new, words, ctx->d_act, cnt_dev, ctx->stream));
     LowRankArgs la{};
     la.S = ctx->S;
     la.P = ctx->Pb;
     la.pld = ctx->pld;
-    la.gstride = ctx->p_rows * ctx->pld;
+    la.gstride = gstride;
     la.p_rows = ctx->p_rows;
     la.r = q * ctx->pld;
     la.rows = nullptr;
@@ -2243,7 +2280,10 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     la.ncols = n_new;
     la.fused = 1;
     la.variant = ctx->gemm_variant;
+    la.act = ctx->d_act;
+    la.act_n = cnt_dev;
     HC(run_lowrank(ctx, la));
+    pass_blocks.push_back(q);
     ++passes;
     q = 0;
     return SR_OK;
@@ -2358,7 +2398,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
         r = lowrank_block(ctx, b.case_id, b.op, b.I, b.j, n_new, nullptr, fused ? &ft : nullptr,
                           dev_of[bi]);
         ++lowrank;
-        if (!ctx->bstore) pairs += n_new * n_new;
+        if (!ctx->bstore && !fused) pairs += n_new * n_new;
         if (r == SR_OK && incremental) {
           // this block's terms for the chunk's later slots
           const int s0 = slot_of[bi] + 1, s1 = chunk_base[chunk_of[bi] + 1];
@@ -2386,6 +2426,16 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   if (stats) {
     HC(hipStreamSynchronize(ctx->stream));
     memset(stats, 0, sizeof(*stats));
+    int64_t entries = 0;
+    if (!pass_blocks.empty()) {
+      // each block of a dense fused pass updates the square of the pass's reached nodes
+      std::vector<int64_t> cnts(pass_blocks.size());
+      HC(hipMemcpy(cnts.data(), ctx->d_act_cnt, cnts.size() * 8, hipMemcpyDeviceToHost));
+      for (size_t p = 0; p < cnts.size(); ++p) {
+        pairs += (int64_t)pass_blocks[p] * cnts[p] * cnts[p];
+        entries += (int64_t)pass_blocks[p] * (cnts[p] * (cnts[p] + 1) / 2);
+      }
+    }
     stats->edges_in = cnt;
     stats->edges_net = net_edges;
     stats->blocks = (int64_t)plan.size();
@@ -2395,6 +2445,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     stats->pairs = pairs;
     stats->fused_passes = passes;
     stats->series_replays = (int32_t)(ctx->graph_replays - replays0);
+    stats->pass_entries = entries;
   }
   return SR_OK;
 }

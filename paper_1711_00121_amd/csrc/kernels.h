@@ -274,6 +274,11 @@ struct LowRankArgs {
                       // batch panel); column c of row a is at (c / pld) gstride + a pld + c % pld
   double* acc_out;    // launch_lowrank_acc: float64 output, ld_out doubles per row
   int32_t fused;      // 1: a fused batch pass, always the symmetric GEMM (even at r = 32)
+  // Fused passes: when set, the pass covers only the nodes act[0 .. *act_n) (ascending; the
+  // nodes with a nonzero panel row in the pass, see launch_pass_rows): the others' rows and
+  // columns of the update are exact zeros. The count is read on the device.
+  const int32_t* act;
+  const int64_t* act_n;
   int32_t variant;    // fused GEMM: tile variant (0 .. kGemmVariants - 1): float64 matrix
                       // cores with panel columns per LDS chunk and LDS pitch (16, 18),
                       // (16, 20), (32, 34), (32, 36); kGemmF32: float32 matrix cores
@@ -281,6 +286,11 @@ struct LowRankArgs {
 constexpr int kGemmF32 = 4;
 constexpr int kGemmVariants = 5;
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
+// The nodes a fused pass reaches: bit a of bm (ceil(n / 32) words, zeroed by the caller) is set
+// when row a of any of the q panel segments (gstride doubles apart, pld per row) has a nonzero
+// entry among its first w columns.
+hipError_t launch_pass_rows(const double* P, int pld, int64_t gstride, int q, int w, int64_t n,
+                            uint32_t* bm, hipStream_t s);
 // Column mode, batches: acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1] for list
 // positions p < nrows and nodes a < ncols (the deferred blocks' Delta S[a][rows[p]], eq (71)),
 // on FP64 matrix cores. P is block-major (gstride); r and pld multiples of 16; P holds at least

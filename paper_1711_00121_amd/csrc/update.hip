@@ -330,6 +330,7 @@ constexpr int64_t kRectGroup = 8;
 constexpr int kSym = 0;   // fused pass into the dense S (upper triangle of tiles, mirrored)
 constexpr int kRect = 1;  // column-mode batches: accumulate into a float64 output
 constexpr int kBlk = 2;   // fused pass into the block store
+constexpr int kSymAct = 3;  // kSym over the nodes of an active list (LowRankArgs::act)
 
 // kRect (column mode, batches): a rectangular product accumulated into a float64 output,
 //     acc_out[p][a] += sum_{c < r} P[rows[p]][c] P[a][c ^ 1]   (p < nrows, a < ncols),
@@ -354,7 +355,19 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
   const int64_t t = (w % NXCD) * per + w / NXCD;
   int64_t I, J;
   [[maybe_unused]] int32_t bp = 0, bq = 0;
-  if constexpr (MODE == kBlk) {
+  [[maybe_unused]] int64_t cnt = 0;
+  if constexpr (MODE == kSymAct) {
+    // the triangle of the list's tiles, dealt to the XCDs as in kSym (the grid is sized for
+    // the whole node range; workgroups past the list's share return)
+    cnt = *g.act_n;
+    const int64_t Ta = (cnt + GT - 1) / GT;
+    const int64_t tiles = Ta * (Ta + 1) / 2;
+    const int64_t pa = (tiles + NXCD - 1) / NXCD;
+    if (w / NXCD >= pa) return;
+    const int64_t ta = (w % NXCD) * pa + w / NXCD;
+    if (ta >= tiles) return;
+    tri_tile(ta, Ta, I, J);
+  } else if constexpr (MODE == kBlk) {
     if (t >= T) return;  // T: the number of listed tiles
     const BsItem it = items[t];
     bp = it.p;
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
   // kRect: the A rows of this thread, gathered through the list; kBlk: the A and B rows,
   // gathered through the two blocks' member lists
   constexpr bool GA = MODE != kSym;
-  constexpr bool GB = MODE == kBlk;
+  constexpr bool GB = MODE == kBlk || MODE == kSymAct;
   int64_t arow[GA ? GL : 1], brow[GB ? GL : 1];
   [[maybe_unused]] int64_t na = 0, nb = 0;
   if constexpr (MODE == kRect) {
@@ -400,6 +413,13 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
     for (int u = 0; u < GL; ++u) {
       const int64_t p = r0 + lrow + GR * u;
       arow[u] = (int64_t)g.rows[p < g.nrows ? p : g.nrows - 1] * g.pld + lcol;
+    }
+  } else if constexpr (MODE == kSymAct) {
+#pragma unroll
+    for (int u = 0; u < GL; ++u) {
+      const int64_t p = r0 + lrow + GR * u, q = c0 + lrow + GR * u;
+      arow[u] = (int64_t)g.act[p < cnt ? p : cnt - 1] * g.pld + lcol;
+      brow[u] = (int64_t)g.act[q < cnt ? q : cnt - 1] * g.pld + lcol;
     }
   } else if constexpr (MODE == kBlk) {
     const int32_t* ma = bs.mem + bs.mem_off[bp];
@@ -542,20 +562,35 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
   // cores may round differently; there only a <= b is stored, with its mirror, so S stays
   // exactly symmetric. Loads are unconditional from clamped addresses; out-of-range entries
   // are not stored.
+  // (kSymAct: positions in the list; the entries are those of the listed nodes, and since the
+  // list ascends, position order is node order for the diagonal rule.)
   const bool diag = I == J;
+  const int64_t lim_r = MODE == kSymAct ? cnt : g.nrows;
+  const int64_t lim_c = MODE == kSymAct ? cnt : g.ncols;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     Raw<PREC> x[4][4], y[4][4];
     int on[4][4];
+    int64_t an[4], bn[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t p = r0 + wr * 64 + s * 16 + v * 4 + lk;
+      an[v] = MODE == kSymAct ? (int64_t)g.act[p < cnt ? p : 0] : p;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t p = c0 + wc * 64 + q * 16 + l16;
+      bn[q] = MODE == kSymAct ? (int64_t)g.act[p < cnt ? p : 0] : p;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
-        const int64_t b = c0 + wc * 64 + q * 16 + l16;
-        on[q][v] = a < g.nrows && b < g.ncols;
-        const int64_t da = on[q][v] ? a * g.S.ld + b : 0;
-        const int64_t ma = on[q][v] ? b * g.S.ld + a : 0;
+        const int64_t pr = r0 + wr * 64 + s * 16 + v * 4 + lk;
+        const int64_t pc = c0 + wc * 64 + q * 16 + l16;
+        on[q][v] = pr < lim_r && pc < lim_c;
+        const int64_t da = on[q][v] ? an[v] * g.S.ld + bn[q] : 0;
+        const int64_t ma = on[q][v] ? bn[q] * g.S.ld + an[v] : 0;
         sload<PREC>(g.S, da, x[q][v]);
         sload<PREC>(g.S, ma, y[q][v]);
       }
@@ -564,11 +599,11 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (!on[q][v]) continue;
-        const int64_t a = r0 + wr * 64 + s * 16 + v * 4 + lk;
-        const int64_t b = c0 + wc * 64 + q * 16 + l16;
+        const int64_t pr = r0 + wr * 64 + s * 16 + v * 4 + lk;
+        const int64_t pc = c0 + wc * 64 + q * 16 + l16;
         const double d = acc[s][q][v];
-        if (!diag || a <= b) sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + d);
-        if (!diag || a < b) sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(y[q][v]) + d);
+        if (!diag || pr <= pc) sput<PREC>(g.S, an[v] * g.S.ld + bn[q], sval<PREC>(x[q][v]) + d);
+        if (!diag || pr < pc) sput<PREC>(g.S, bn[q] * g.S.ld + an[v], sval<PREC>(y[q][v]) + d);
       }
   }
 }
@@ -585,7 +620,7 @@ constexpr int GCF = 32;
 constexpr int GPF = GCF + 1;
 typedef float fl4 __attribute__((ext_vector_type(4)));
 
-template <int PREC>
+template <int PREC, bool ACT = false>
 __global__ __launch_bounds__(NT, 2) void lowrank_gemm_f32_kernel(LowRankArgs g, int64_t T,
                                                               int64_t per) {
   constexpr int GL = GT * (GCF / 2) / NT;  // double2 loads per thread per side per chunk (8)
@@ -593,10 +628,23 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_f32_kernel(LowRankArgs g, 
   __shared__ float As[2][GT * GPF];
   __shared__ float Bs[2][GT * GPF];
   const int64_t w = blockIdx.x;
-  const int64_t t = (w % NXCD) * per + w / NXCD;
-  if (t >= T * (T + 1) / 2) return;
   int64_t I, J;
-  tri_tile(t, T, I, J);
+  [[maybe_unused]] int64_t cnt = 0;
+  if constexpr (ACT) {
+    // tiles of the active list, as in lowrank_gemm_kernel's kSymAct mode
+    cnt = *g.act_n;
+    const int64_t Ta = (cnt + GT - 1) / GT;
+    const int64_t tiles = Ta * (Ta + 1) / 2;
+    const int64_t pa = (tiles + NXCD - 1) / NXCD;
+    if (w / NXCD >= pa) return;
+    const int64_t ta = (w % NXCD) * pa + w / NXCD;
+    if (ta >= tiles) return;
+    tri_tile(ta, Ta, I, J);
+  } else {
+    const int64_t t = (w % NXCD) * per + w / NXCD;
+    if (t >= T * (T + 1) / 2) return;
+    tri_tile(t, T, I, J);
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -609,13 +657,28 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_f32_kernel(LowRankArgs g, 
   const double* pa = g.P + (r0 + lrow) * (int64_t)g.pld + lcol;
   const double* pb = g.P + (c0 + lrow) * (int64_t)g.pld + lcol;
   const int64_t ustep = GR * (int64_t)g.pld;
+  // ACT: the rows of this thread, gathered through the list
+  int64_t arow[ACT ? GL : 1], brow[ACT ? GL : 1];
+  if constexpr (ACT) {
+#pragma unroll
+    for (int u = 0; u < GL; ++u) {
+      const int64_t p = r0 + lrow + GR * u, q = c0 + lrow + GR * u;
+      arow[u] = (int64_t)g.act[p < cnt ? p : cnt - 1] * g.pld + lcol;
+      brow[u] = (int64_t)g.act[q < cnt ? q : cnt - 1] * g.pld + lcol;
+    }
+  }
   double2 ra[GL], rb[GL];
   auto load = [&](int ch) {
     const int64_t cb = (int64_t)((ch * GCF) / g.pld) * g.gstride + (ch * GCF) % g.pld;
 #pragma unroll
     for (int u = 0; u < GL; ++u) {
-      ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
-      rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
+      if constexpr (ACT) {
+        ra[u] = *reinterpret_cast<const double2*>(g.P + arow[u] + cb);
+        rb[u] = *reinterpret_cast<const double2*>(g.P + brow[u] + cb);
+      } else {
+        ra[u] = *reinterpret_cast<const double2*>(pa + u * ustep + cb);
+        rb[u] = *reinterpret_cast<const double2*>(pb + u * ustep + cb);
+      }
     }
   };
   auto store = [&](int buf) {
@@ -657,21 +720,35 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_f32_kernel(LowRankArgs g, 
     store(buf ^ 1);
     __syncthreads();
   }
-  // epilogue as lowrank_gemm_kernel's, rows 4 lk + v of each 16 x 16 block
+  // epilogue as lowrank_gemm_kernel's, rows 4 lk + v of each 16 x 16 block (ACT: list
+  // positions, translated to the listed nodes)
   const bool diag = I == J;
+  const int64_t lim_r = ACT ? cnt : g.nrows;
+  const int64_t lim_c = ACT ? cnt : g.ncols;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     Raw<PREC> x[4][4], y[4][4];
     int on[4][4];
+    int64_t an[4], bn[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t p = r0 + wr * 64 + s * 16 + 4 * lk + v;
+      an[v] = ACT ? (int64_t)g.act[p < cnt ? p : 0] : p;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t p = c0 + wc * 64 + q * 16 + l16;
+      bn[q] = ACT ? (int64_t)g.act[p < cnt ? p : 0] : p;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t a = r0 + wr * 64 + s * 16 + 4 * lk + v;
-        const int64_t b = c0 + wc * 64 + q * 16 + l16;
-        on[q][v] = a < g.nrows && b < g.ncols;
-        const int64_t da = on[q][v] ? a * g.S.ld + b : 0;
-        const int64_t ma = on[q][v] ? b * g.S.ld + a : 0;
+        const int64_t pr = r0 + wr * 64 + s * 16 + 4 * lk + v;
+        const int64_t pc = c0 + wc * 64 + q * 16 + l16;
+        on[q][v] = pr < lim_r && pc < lim_c;
+        const int64_t da = on[q][v] ? an[v] * g.S.ld + bn[q] : 0;
+        const int64_t ma = on[q][v] ? bn[q] * g.S.ld + an[v] : 0;
         sload<PREC>(g.S, da, x[q][v]);
         sload<PREC>(g.S, ma, y[q][v]);
       }
@@ -680,11 +757,11 @@ __global__ __launch_bounds__(NT, 2) void lowrank_gemm_f32_kernel(LowRankArgs g, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (!on[q][v]) continue;
-        const int64_t a = r0 + wr * 64 + s * 16 + 4 * lk + v;
-        const int64_t b = c0 + wc * 64 + q * 16 + l16;
+        const int64_t pr = r0 + wr * 64 + s * 16 + 4 * lk + v;
+        const int64_t pc = c0 + wc * 64 + q * 16 + l16;
         const double d = (double)acc[s][q][v];
-        if (!diag || a <= b) sput<PREC>(g.S, a * g.S.ld + b, sval<PREC>(x[q][v]) + d);
-        if (!diag || a < b) sput<PREC>(g.S, b * g.S.ld + a, sval<PREC>(y[q][v]) + d);
+        if (!diag || pr <= pc) sput<PREC>(g.S, an[v] * g.S.ld + bn[q], sval<PREC>(x[q][v]) + d);
+        if (!diag || pr < pc) sput<PREC>(g.S, bn[q] * g.S.ld + an[v], sval<PREC>(y[q][v]) + d);
       }
   }
 }
@@ -1017,7 +1094,7 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   if (a.variant < 0 || a.variant >= kGemmVariants) return hipErrorInvalidValue;
   const int gc = a.variant < 2 ? 16 : 32;  // the float32 variant stages 32 columns too
   if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr ||
-      a.nrows != a.ncols || a.r % gc != 0 || a.pld % gc != 0)
+      a.nrows != a.ncols || a.r % gc != 0 || a.pld % gc != 0 || (a.act && !a.act_n))
     return hipErrorInvalidValue;
   const int64_t T = (a.nrows + GT - 1) / GT;
   if (a.p_rows < T * GT) return hipErrorInvalidValue;
@@ -1026,6 +1103,18 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   const unsigned grid = (unsigned)(per * NXCD);
   auto go = [&](auto prec) {
     constexpr int P = decltype(prec)::value;
+    if (a.act) {
+      switch (a.variant) {
+        case kGemmF32: lowrank_gemm_f32_kernel<P, true><<<grid, NT, 0, s>>>(a, T, per); break;
+        case 0: lowrank_gemm_kernel<P, kSymAct, 16, 18, 2><<<grid, NT, 0, s>>>(a, T, per); break;
+        case 1: lowrank_gemm_kernel<P, kSymAct, 16, 20, 2><<<grid, NT, 0, s>>>(a, T, per); break;
+        case 2: lowrank_gemm_kernel<P, kSymAct, 32, 34, 1><<<grid, NT, 0, s>>>(a, T, per); break;
+        default:
+          lowrank_gemm_kernel<P, kSymAct, 32, 36, 1><<<grid, NT, 0, s>>>(a, T, per);
+          break;
+      }
+      return;
+    }
     switch (a.variant) {
       case kGemmF32: lowrank_gemm_f32_kernel<P><<<grid, NT, 0, s>>>(a, T, per); break;
       case 0: lowrank_gemm_kernel<P, kSym, 16, 18, 2><<<grid, NT, 0, s>>>(a, T, per); break;
@@ -1040,6 +1129,37 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
     go(std::integral_constant<int, PREC_HILO>{});
   else
     go(std::integral_constant<int, PREC_FP32>{});
+  return hipGetLastError();
+}
+
+// One thread per (node, panel segment): a nonzero among the row's first w entries sets the
+// node's bit; a wave's 64 bits go out as two atomics (nodes of a wave share two words).
+__global__ __launch_bounds__(256) void pass_rows_kernel(const double* __restrict__ P, int pld,
+                                                        int64_t gstride, int w, int64_t n,
+                                                        uint32_t* __restrict__ bm) {
+  const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool nz = false;
+  if (a < n) {
+    const double* row = P + (int64_t)blockIdx.y * gstride + a * pld;
+    for (int c = 0; c < w; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(row + c);
+      nz |= v.x != 0.0 || v.y != 0.0;
+    }
+  }
+  const uint64_t m = __ballot(nz);
+  const int lane = threadIdx.x & 63;
+  if ((lane == 0 || lane == 32) && a < n) {
+    const uint32_t bits = (uint32_t)(lane == 0 ? m : (m >> 32));
+    if (bits) atomicOr(bm + (a >> 5), bits);
+  }
+}
+
+hipError_t launch_pass_rows(const double* P, int pld, int64_t gstride, int q, int w, int64_t n,
+                            uint32_t* bm, hipStream_t s) {
+  if (n <= 0 || q <= 0) return hipSuccess;
+  if (q > 65535 || w > pld || w % 2 != 0 || pld % 2 != 0) return hipErrorInvalidValue;
+  pass_rows_kernel<<<dim3((unsigned)((n + 255) / 256), (unsigned)q), 256, 0, s>>>(P, pld, gstride,
+                                                                                  w, n, bm);
   return hipGetLastError();
 }
 

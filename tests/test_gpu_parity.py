@@ -613,8 +613,40 @@ def test_fused_batches_match_oracle(prec, chunk):
             tr.apply(i, j, 1)
         tr.n = nn
         assert st["fused_passes"] == -(-st["lowrank_blocks"] // chunk)
+        # a pass covers the nodes with a nonzero panel row in one of its blocks: at most all
+        assert 0 < st["pass_entries"] <= st["lowrank_blocks"] * nn * (nn + 1) // 2
         S15 = ctx15.S().cpu().numpy()
         # every fused pass, one block or many, writes (a, b) and (b, a) from one sum
         assert np.array_equal(S15, S15.T)
         assert maxabs(S15, S_or) < (1e-12 if prec == "fp64" else 1e-9)
         assert maxabs(ctx40.S().cpu().numpy(), tr.exact(C)) < TOL
+
+
+def test_fused_passes_cover_the_reached_nodes_only():
+    """Nodes without in-edges never enter a block's series (their S rows stay (1 - C) e_a), so
+    a fused pass skips them: with half the nodes given no in-edges, the passes cover fewer
+    entries than the whole square, and S still matches the oracle's Inc-bSR and stays exactly
+    symmetric; the rows of the skipped nodes are unchanged."""
+    n = 400
+    s, d = W.chung_lu(n, 2400, seed=71)
+    keep = d < n // 2  # nodes n/2 .. n-1 keep only their out-edges
+    s, d = s[keep], d[keep]
+    tr = EdgeTracker(n, s, d)
+    bi, bj, bo = (np.asarray(x) for x in _existing_batch(n, s, d, seed=72, n_ins=60, n_del=20,
+                                                          shared=10))
+    ok = bj < n // 2  # insert and delete only into the first half
+    bi, bj, bo = bi[ok], bj[ok], bo[ok]
+    ctx = ctx_for(n, s, d, s_prec="fp64", fused_batch=True, batch_chunk=4, K=15)
+    S0 = ctx.S().cpu().numpy()
+    st = ctx.apply_batch(bi, bj, bo, stats=True)
+    S = ctx.S().cpu().numpy()
+    S_or, _ = OI.inc_bsr(n, s.astype(np.int64), d.astype(np.int64),
+                         O.fixed_point(Gr.transition_matrix(n, s, d), C), bi, bj, bo, C, 15)
+    full = st["lowrank_blocks"] * n * (n + 1) // 2
+    print(f"pass entries {st['pass_entries']} of {full}", flush=True)
+    assert st["pass_entries"] < full * 0.6
+    assert maxabs(S, S_or) < 1e-12
+    assert np.array_equal(S, S.T)
+    sinkless = np.setdiff1d(np.arange(n // 2, n), np.asarray(tr.arrays()[1]))
+    assert np.array_equal(S[sinkless], S0[sinkless])
+    ctx.close()
