@@ -983,16 +983,17 @@ def traffic(kernel, workload):
     text = open(path).read()
     m_src = re.search(r"Source: `([^`]+)`", text)
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    m_w = re.search(r"^workload:\s*(.+?)\s*$", text, flags=re.M)
-    if not (m_src and m_sha and m_b and m_w) or m_w.group(1) != workload:
+    # one section per run configuration: the bytes line, then its workload line
+    found = dict((w.strip(), float(b)) for b, w in re.findall(
+        r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)\s*\nworkload:\s*(.+?)\s*$", text, flags=re.M))
+    if not (m_src and m_sha) or workload not in found:
         return None
     src = os.path.join(ROOT, m_src.group(1))
     if not os.path.exists(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
         return None
-    return float(m_b.group(1))
+    return found[workload]
 
 
 def host_cpu():
