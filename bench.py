@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 C = 0.6
-# the oracle's all-core leg uses at most this many host threads (a GPU machine's CPU share)
+# the oracle's all-core leg uses at most this many host threads (one GPU's share of a host)
 MAX_ORACLE_WORKERS = 16
 ORACLE_POOL = None
 
