@@ -375,8 +375,9 @@ sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t re
  * as SR_UPDATE_FP32) over `blocks` deferred blocks, and the incremental
  * corrections one deferred block makes for blocks / 2 later slots of its chunk: *gemm_ms and
  * *corr_ms are the mean of `reps` launches after one warm-up. The pass runs on a zero panel,
- * so S keeps its values. Dense mode; allocates a zero panel of n x blocks 2(K+1) (rounded up
- * to 32) doubles for the call; synchronises. */
+ * so S keeps its values, through the reached-node form of apply_batch's passes with every
+ * node listed. Dense mode; allocates a zero panel of n x blocks 2(K+1) (rounded up to 32)
+ * doubles and the node list for the call; synchronises. */
 sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t reps,
                         double* gemm_ms, double* corr_ms);
 

@@ -3037,6 +3037,8 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
   hipStream_t s = ctx->stream;
   double* Z = nullptr;  // a zero panel: the timed passes add exact zeros to S
   int32_t* tab = nullptr;
+  int32_t* act = nullptr;  // every node listed: the passes' reached-node code path
+  int64_t* act_n = nullptr;
   double *cv = nullptr, *cw = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int slots = std::max(1, blocks / 2);
@@ -3044,6 +3046,8 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
     (void)hipStreamSynchronize(s);
     (void)dfree(Z);
     (void)dfree(tab);
+    (void)dfree(act);
+    (void)dfree(act_n);
     (void)dfree(cv);
     (void)dfree(cw);
     if (e0) (void)hipEventDestroy(e0);
@@ -3052,8 +3056,19 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
   };
   if (dalloc(&Z, ctx->p_rows * cols) != hipSuccess || dalloc(&tab, 2 * slots + 1) != hipSuccess ||
       dalloc(&cv, 2 * (int64_t)slots * ctx->p_rows) != hipSuccess ||
-      dalloc(&cw, 2 * (int64_t)slots * pld) != hipSuccess)
+      dalloc(&cw, 2 * (int64_t)slots * pld) != hipSuccess || dalloc(&act, n) != hipSuccess ||
+      dalloc(&act_n, 1) != hipSuccess)
     return done(SR_ENOMEM);
+  {
+    std::vector<int32_t> ids(n);
+    for (int64_t a = 0; a < n; ++a) ids[a] = (int32_t)a;
+    const int64_t cnt = n;
+    if (hipMemcpy(act, ids.data(), (size_t)n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(act_n, &cnt, 8, hipMemcpyHostToDevice) != hipSuccess) {
+      ctx->poisoned = true;
+      return done(SR_EHIP);
+    }
+  }
   if (hipMemsetAsync(Z, 0, (size_t)ctx->p_rows * cols * 8, s) != hipSuccess ||
       hipMemsetAsync(tab, 0, (size_t)(2 * slots + 1) * 4, s) != hipSuccess ||
       hipMemsetAsync(cv, 0, (size_t)2 * slots * ctx->p_rows * 8, s) != hipSuccess ||
@@ -3072,6 +3087,8 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
   la.ncols = n;
   la.fused = 1;
   la.variant = variant;
+  la.act = act;
+  la.act_n = act_n;
   // one deferred block's corrections for `slots` later slots of its chunk (zero weights)
   CorrSlots cs{};
   cs.rstart = tab;
