@@ -194,8 +194,10 @@ sr_status sr_partition(int64_t n, int64_t m, const int32_t* src, const int32_t* 
  * float64) and placed on the diagonal of the store, then the edges across blocks are applied,
  * in the caller's order, as one apply_batch of insertions. The result is S of the whole graph
  * up to the K-term truncation of each block of the batch. cfg: as init_simrank, mode must be
- * SR_DENSE (SR_EMODE otherwise), edge_cap 0 means 2 m + 1024. Unweighted only. stats: NULL,
- * or the batch's statistics. On any error nothing is returned (*out = NULL). */
+ * SR_DENSE (SR_EMODE otherwise), edge_cap 0 means 2 m + 1024; with cfg->block_store = 1 the
+ * store is the block pairs (see sr_config; at most 4096 distinct labels, SR_ECAPACITY
+ * otherwise). Unweighted only. stats: NULL, or the batch's statistics. On any error nothing
+ * is returned (*out = NULL). */
 sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
                                    const int32_t* dst, const int32_t* part,
                                    const sr_config* cfg, void* hip_stream,
@@ -336,7 +338,8 @@ sr_status sr_get_config(sr_ctx* ctx, sr_config* out);
 
 /* Bytes of the context's store of S: the dense n x n store (node_cap rows of its leading
  * dimension), or with block_store the sub-matrices of the block pairs held (pairs: their
- * count; 0 for a dense store); 0 in column mode. bytes, pairs: NULL or filled. */
+ * count; 0 for a dense store); 0 in column mode. bytes, pairs: NULL or filled. SR_EINVAL
+ * for an invalid context. */
 sr_status sr_store_bytes(sr_ctx* ctx, int64_t* bytes, int64_t* pairs);
 
 /* Device memory the library holds now, over all contexts of the process (S, panels, graph
