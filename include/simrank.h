@@ -195,7 +195,7 @@ sr_status sr_partition(int64_t n, int64_t m, const int32_t* src, const int32_t* 
  * in the caller's order, as one apply_batch of insertions. The result is S of the whole graph
  * up to the K-term truncation of each block of the batch. cfg: as init_simrank, mode must be
  * SR_DENSE (SR_EMODE otherwise), edge_cap 0 means 2 m + 1024; with cfg->block_store = 1 the
- * store is the block pairs (see sr_config; at most 4096 distinct labels, SR_ECAPACITY
+ * store is the block pairs (see sr_config; labels must be below 4096, SR_ECAPACITY
  * otherwise). Unweighted only. stats: NULL, or the batch's statistics. On any error nothing
  * is returned (*out = NULL). */
 sr_status init_simrank_partitioned(sr_ctx** out, int64_t n, int64_t m, const int32_t* src,
