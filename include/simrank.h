@@ -85,7 +85,8 @@ typedef struct sr_config {
   double init_tol;       /* fixed-point step tolerance of the initial S (max-abs)           */
   int32_t init_max_iter; /* iteration cap of the initial fixed point                        */
   int32_t batch_chunk;   /* low-rank blocks per fused pass of apply_batch, or per
-                            accumulate pass of apply_batch_columns; 0: the mode's default,
+                            accumulate pass of apply_batch_columns (at most 65,535; more is
+                            SR_EINVAL, as in sr_set_tuning); 0: the mode's default,
                             64 in dense mode, ceil(512 / (2 (K + 1))) in column mode
                             (passes bounded by arithmetic, not by the output's traffic, with
                             a panel of at most 512 + 2 (K + 1) columns of n doubles)       */
@@ -384,9 +385,10 @@ sr_status sr_profile_read(sr_ctx* ctx, double* ms, int64_t* launches, int32_t re
 sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t reps,
                         double* gemm_ms, double* corr_ms);
 
-/* Tuning: sets the context's batch_chunk (blocks per fused pass) and the fused GEMM's tile
- * variant (as sr_time_fused). A new chunk frees the batch panel and correction buffers, which
- * the next batch allocates again (synchronises). SR_ERANGE for an unknown variant. */
+/* Tuning: sets the context's batch_chunk (blocks per fused pass, 1 .. 65,535, else SR_EINVAL)
+ * and the fused GEMM's tile variant (as sr_time_fused). A new chunk frees the batch panel and
+ * correction buffers, which the next batch allocates again (synchronises). SR_ERANGE for an
+ * unknown variant. */
 sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant);
 
 /* Diagnostics: runs one v_mfma_f64_16x16x4_f64 on a single wave with lane l supplying

@@ -26,6 +26,8 @@ static __device__ __align__(256) int32_t scratch[kScratchIds];
 
 // Panel columns one column-mode accumulate pass covers by default (see init_impl).
 constexpr int kColumnPanelCols = 512;
+// Deferred blocks per fused pass at most: the per-pass kernels take one grid row per block.
+constexpr int32_t kMaxChunk = 65535;
 
 // Rows longer than kLight entries, kept in sync with the host mirror; the traversal kernels
 // process them in chunks (see graph.hip).
@@ -1326,6 +1328,7 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
   if (!(cfg.C > 0.0 && cfg.C < 1.0) || cfg.K < 0 || cfg.K > 200 || cfg.K_ps < 0 ||
       cfg.s_prec < 0 || cfg.s_prec > 2 || (cfg.mode != SR_DENSE && cfg.mode != SR_COLUMN) ||
       cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0 ||
+      cfg.batch_chunk > kMaxChunk ||
       cfg.update_prec < 0 || cfg.update_prec > 1 || cfg.block_store < 0 ||
       cfg.block_store > 1 || (cfg.split_rows != 0 && cfg.split_rows < kMedium))
     return SR_EINVAL;
@@ -3123,7 +3126,7 @@ sr_status sr_time_fused(sr_ctx* ctx, int32_t variant, int32_t blocks, int32_t re
 }
 
 sr_status sr_set_tuning(sr_ctx* ctx, int32_t batch_chunk, int32_t variant) {
-  if (!valid_ctx(ctx) || batch_chunk < 1) return SR_EINVAL;
+  if (!valid_ctx(ctx) || batch_chunk < 1 || batch_chunk > kMaxChunk) return SR_EINVAL;
   if (ctx->poisoned) return SR_EHIP;
   if (variant < 0 || variant >= kGemmVariants) return SR_ERANGE;
   if (batch_chunk != ctx->cfg.batch_chunk) {

@@ -64,6 +64,24 @@ def test_null_context_arguments_are_rejected_without_gpu():
     assert L.sr_get_config(None, None) == _lib.SR_EINVAL
 
 
+def test_chunk_bound_is_refused_before_any_gpu_work():
+    """batch_chunk above 65,535 (one grid row per deferred block in the per-pass kernels) is
+    a validation error of the configuration, reported before the device is touched."""
+    import ctypes as C
+    import numpy as np
+    from paper_1711_00121_amd import _lib
+    L = lib()
+    cfg = _lib.sr_config()
+    assert L.sr_default_config(C.byref(cfg)) == _lib.SR_OK
+    cfg.batch_chunk = 65536
+    src = np.asarray([0, 1], dtype=np.int32)
+    dst = np.asarray([1, 2], dtype=np.int32)
+    h = C.c_void_p()
+    st = L.init_simrank(C.byref(h), 3, 2, src.ctypes.data_as(C.POINTER(C.c_int32)),
+                        dst.ctypes.data_as(C.POINTER(C.c_int32)), None, C.byref(cfg), None, None)
+    assert st == _lib.SR_EINVAL and not h.value
+
+
 def test_device_bytes_without_contexts():
     """No context allocates on a host without a GPU: the library holds nothing."""
     from paper_1711_00121_amd import device_bytes
