@@ -40,7 +40,7 @@ def block_pairs(S, lab):
     return out
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("hilo", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("hilo", 1e-6), ("fp32", 1e-6)])
 @pytest.mark.parametrize("p_cross", [0.001, 0.03])
 def test_block_store_matches_oracle(prec, tol, p_cross):
     """n = 1200 over 16 blocks of scattered ids; with few cross edges (0.1% planted) the
@@ -72,6 +72,8 @@ def test_block_store_matches_oracle(prec, tol, p_cross):
     assert err < tol
     assert gap < (1e-12 if prec == "fp64" else 1e-6)
     assert npairs >= len(need)
+    # float32 entries (4 B) where the other stores keep 8 B
+    assert dbytes == n * ((n + 63) // 64 * 64) * (4 if prec == "fp32" else 8)
     if p_cross < 0.01:
         assert npairs < parts * (parts + 1) // 2 and nbytes < 0.75 * n * n * 8
     ctx.close()

@@ -622,7 +622,8 @@ def test_fused_batches_match_oracle(prec, chunk):
         assert maxabs(ctx40.S().cpu().numpy(), tr.exact(C)) < TOL
 
 
-def test_fused_passes_cover_the_reached_nodes_only():
+@pytest.mark.parametrize("update_prec", ["fp64", "fp32"])
+def test_fused_passes_cover_the_reached_nodes_only(update_prec):
     """Nodes without in-edges never enter a block's series (their S rows stay (1 - C) e_a), so
     a fused pass skips them: with half the nodes given no in-edges, the passes cover fewer
     entries than the whole square, and S still matches the oracle's Inc-bSR and stays exactly
@@ -636,7 +637,8 @@ def test_fused_passes_cover_the_reached_nodes_only():
                                                           shared=10))
     ok = bj < n // 2  # insert and delete only into the first half
     bi, bj, bo = bi[ok], bj[ok], bo[ok]
-    ctx = ctx_for(n, s, d, s_prec="fp64", fused_batch=True, batch_chunk=4, K=15)
+    ctx = ctx_for(n, s, d, s_prec="fp64", fused_batch=True, batch_chunk=4, K=15,
+                  update_prec=update_prec)
     S0 = ctx.S().cpu().numpy()
     st = ctx.apply_batch(bi, bj, bo, stats=True)
     S = ctx.S().cpu().numpy()
@@ -645,7 +647,8 @@ def test_fused_passes_cover_the_reached_nodes_only():
     full = st["lowrank_blocks"] * n * (n + 1) // 2
     print(f"pass entries {st['pass_entries']} of {full}", flush=True)
     assert st["pass_entries"] < full * 0.6
-    assert maxabs(S, S_or) < 1e-12
+    # float32 matrix cores: products of the rounded panel, summed in float32 per pass
+    assert maxabs(S, S_or) < (1e-12 if update_prec == "fp64" else 1e-6)
     assert np.array_equal(S, S.T)
     sinkless = np.setdiff1d(np.arange(n // 2, n), np.asarray(tr.arrays()[1]))
     assert np.array_equal(S[sinkless], S0[sinkless])
