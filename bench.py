@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="plain launches instead of replaying captured series chains")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--no-tile-skip", action="store_true",
+                    help="fused passes run every k-step of every tile (the same S bit for bit)")
     ap.add_argument("--split-rows", type=int, default=0,
                     help="graph rows above this many entries are traversed in chunks "
                          "(0: the library default)")
@@ -168,7 +170,8 @@ def run_batch(args):
                   split_rows=args.split_rows,
                   edge_cap=m + sum(len(b[0]) for b in batches) + 1024,
                   fused_batch=not args.no_fused, batch_chunk=args.chunk or 64,
-                  graphs=not args.no_graphs, update_prec=args.update_prec)
+                  graphs=not args.no_graphs, update_prec=args.update_prec,
+                  tile_skip=not args.no_tile_skip)
     torch.cuda.synchronize()
     log(f"bench: init (S by fixed point on device) {time.perf_counter() - t0:.1f}s")
 
@@ -190,7 +193,7 @@ def run_batch(args):
     ctx.profile(True)
     ctx.profile_read(reset=True)
     edges_in = edges_net = pairs = lowrank = passes = replays = 0
-    flops = 0.0
+    flops = dense_flops = 0.0
     # net edges per Table 2 case (C0 insertions and deletions apart), from the batch plans
     mix = {"C0+": 0, "C0-": 0, "C1": 0, "C2": 0, "C3": 0}
     plan_s = 0.0
@@ -212,10 +215,12 @@ def run_batch(args):
         replays += st["series_replays"]
         nt = float(st["n_after"])
         # Delta S is symmetric: a fused pass's work is, per low-rank block, the distinct
-        # entries (a <= b) over the nodes the pass reaches, at 2 (K + 1) multiply-adds each;
-        # without fused passes a block covers all n (n + 1) / 2
+        # entries (a <= b) over the nodes the pass reaches, at 2 (K + 1) multiply-adds each,
+        # less the k-steps (4 multiply-adds per entry) that tiles skip where the block's xi
+        # factors vanish; without fused passes a block covers all n (n + 1) / 2
         if st["fused_passes"]:
-            flops += float(st["pass_entries"]) * 4 * (K + 1)
+            flops += float(st["pass_entries"]) * 4 * (K + 1) - 8.0 * st["pass_skipped"]
+            dense_flops += float(st["pass_entries"]) * 4 * (K + 1)
         else:
             flops += nt * (nt + 1.0) * 2 * (K + 1) * st["lowrank_blocks"]
         log(f"bench: step {k}: {len(bi)} edges ({st['edges_net']} net), {st['blocks']} blocks "
@@ -335,7 +340,9 @@ def run_batch(args):
                 "launches": launches, "avg_ms": round(kern_ms / max(launches, 1), 3),
                 "algorithmic": "r (r + 1) / 2 distinct entries x 4 (K + 1) flop per low-rank "
                                "block, r the nodes its fused pass reaches (nonzero panel "
-                               "rows)"}
+                               "rows), less 8 flop per entry of each k-step a tile skips "
+                               "(the block's xi factors vanish on both of its row ranges)",
+                "skipped_fraction": round(1.0 - flops / dense_flops, 4) if dense_flops else 0.0}
     else:
         roof = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
                         "16 B per pair-update (S value + compensation, read + write)",
@@ -356,7 +363,8 @@ def run_batch(args):
                             "max_batch": args.max_batch, "batch_chunk": chunk,
                             "gemm_variant": tuning["variant"] if tuning else 0,
                             "graphs": not args.no_graphs, "update_prec": args.update_prec,
-                            "fused": not args.no_fused, "n_first": n_first, "n_last": n_last,
+                            "fused": not args.no_fused, "tile_skip": not args.no_tile_skip,
+                            "n_first": n_first, "n_last": n_last,
                             "m_last": m_last})
     out.update({
         "edge_updates_per_s": edge_rate, "edges_net": edges_net, "edges_in": edges_in,
@@ -670,7 +678,7 @@ def run_forest(args):
     out["fixed_point_init_s"] = t_fixed
     out["max_abs_vs_fixed_point"] = diff
     pld = 2 * (K + 1)
-    flops = float(st["pass_entries"]) * 2 * pld * args.steps
+    flops = (float(st["pass_entries"]) * 2 * pld - 8.0 * st["pass_skipped"]) * args.steps
     achieved = flops / (kern_ms / 1e3) / 1e12
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -766,7 +774,7 @@ def run_partitioned(args):
         # 2 (K + 1) multiply-adds for half of them (the pass writes mirrored entries once)
         flops = float(st["pairs"]) * pld * args.steps
     else:
-        flops = float(st["pass_entries"]) * 2 * pld * args.steps
+        flops = (float(st["pass_entries"]) * 2 * pld - 8.0 * st["pass_skipped"]) * args.steps
     achieved = flops / (kern_ms / 1e3) / 1e12 if kern_ms > 0 else 0.0
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2),
                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

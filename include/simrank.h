@@ -112,6 +112,12 @@ typedef struct sr_config {
                             insertions and deletions between existing nodes (fused passes
                             into the reached pairs); other updates, backward and
                             query_topk_noalloc return SR_EMODE. 0: one dense store          */
+  int32_t tile_skip;     /* 1: a dense fused pass skips, per 128 x 128 tile of the square of
+                            its reached nodes, the k-steps (panel columns 4 g .. 4 g + 3) of
+                            each block whose xi_2g and xi_2g+1 vanish on both of the tile's
+                            row ranges (xi_k lives on the nodes k out-steps from the sink,
+                            Theorem 4's A_k); those products are exact zeros, so S is bit for
+                            bit the same as with 0, every k-step of every tile               */
 } sr_config;
 
 /* Per-update statistics (filled when a non-null pointer is passed; the call then
@@ -145,11 +151,16 @@ typedef struct sr_batch_stats {
   int64_t pass_entries;   /* dense fused passes: distinct entries (a <= b) of S that their
                              GEMMs computed, summed over the passes' low-rank blocks (a
                              pass covers the square of the nodes its blocks reach)          */
+  int64_t pass_skipped;   /* of those, entry k-steps skipped by tile_skip: summed over the
+                             blocks and their k-steps (4 panel columns, 8 flop per entry),
+                             the distinct entries of the tiles that skipped the k-step; the
+                             passes' arithmetic is 8 (pass_entries ceil((K + 1) / 2) -
+                             pass_skipped) flop                                            */
 } sr_batch_stats;
 
 /* Fills *cfg with defaults: C = 0.6, K = 15, K_ps = 30, SR_S_FP64, SR_DENSE,
  * SR_GAMMA_CLOSED, prune = 1, capacities 0 (derived), init_tol = 1e-15, init_max_iter = 400,
- * batch_chunk = 0 (the mode's default), fused_batch = 1, graphs = 1. */
+ * batch_chunk = 0 (the mode's default), fused_batch = 1, graphs = 1, tile_skip = 1. */
 sr_status sr_default_config(sr_config* cfg);
 
 /* Creates a context for the digraph with n nodes and m edges src[e] -> dst[e] (host arrays,

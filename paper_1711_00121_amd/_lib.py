@@ -41,6 +41,7 @@ class sr_config(C.Structure):
         ("graphs", C.c_int32),
         ("update_prec", C.c_int32),
         ("block_store", C.c_int32),
+        ("tile_skip", C.c_int32),
     ]
 
 
@@ -70,6 +71,7 @@ class sr_batch_stats(C.Structure):
         ("fused_passes", C.c_int32),
         ("series_replays", C.c_int32),
         ("pass_entries", C.c_int64),
+        ("pass_skipped", C.c_int64),
     ]
 
 

@@ -128,6 +128,12 @@ struct sr_ctx {
   int32_t* d_act = nullptr;
   int64_t* d_act_cnt = nullptr;
   int64_t act_cnt_cap = 0;
+  // Tile skipping (cfg.tile_skip): per pass, the k-steps' tile flags of its blocks, and per
+  // low-rank block of a batch and counted k-step the positions of the tiles that skip it.
+  uint32_t* d_tflags = nullptr;
+  int64_t tflags_cap = 0;
+  int32_t* d_skip = nullptr;
+  int64_t skip_cap = 0;
   int corr_slots = 0;      // fused batches: slots per chunk at most (2 batch_chunk + 32)
   double* corr = nullptr;  // correction vectors, 2 corr_slots x p_rows
   double* corr_w = nullptr;  // their weights, 2 corr_slots x 64
@@ -1051,6 +1057,7 @@ sr_status sr_default_config(sr_config* cfg) {
   cfg->fused_batch = 1;
   cfg->split_rows = kSplitRows;
   cfg->graphs = 1;
+  cfg->tile_skip = 1;
   return SR_OK;
 }
 
@@ -1080,6 +1087,8 @@ sr_status sr_destroy(sr_ctx* ctx) {
   (void)dfree(ctx->d_act_bits);
   (void)dfree(ctx->d_act);
   (void)dfree(ctx->d_act_cnt);
+  (void)dfree(ctx->d_tflags);
+  (void)dfree(ctx->d_skip);
   double* dd[] = {ctx->SI, ctx->Sj, ctx->QSI, ctx->zbuf, ctx->Qz, ctx->zsum, ctx->ytmp, ctx->ylast,
                   ctx->P, ctx->pairs, ctx->Pb, ctx->wts, ctx->xs, ctx->xd, ctx->corr,
                   ctx->corr_w};
@@ -1330,7 +1339,8 @@ static sr_status init_impl(sr_ctx** out, int64_t n, int64_t m, const int32_t* sr
       cfg.gamma_form < 0 || cfg.gamma_form > 1 || cfg.batch_chunk < 0 ||
       cfg.batch_chunk > kMaxChunk ||
       cfg.update_prec < 0 || cfg.update_prec > 1 || cfg.block_store < 0 ||
-      cfg.block_store > 1 || (cfg.split_rows != 0 && cfg.split_rows < kMedium))
+      cfg.block_store > 1 || (cfg.split_rows != 0 && cfg.split_rows < kMedium) ||
+      cfg.tile_skip < 0 || cfg.tile_skip > 1)
     return SR_EINVAL;
   if (cfg.block_store && (!block_part || cfg.mode != SR_DENSE)) return SR_EMODE;
   if (cfg.split_rows == 0) cfg.split_rows = kSplitRows;
@@ -2250,6 +2260,40 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
       ctx->act_cnt_cap = c;
     }
   }
+  // Tile skipping (float64 matrix cores): flags of one pass (chunk blocks x tiles of the node
+  // range) and, per low-rank block of the batch, the skipped positions of its counted k-steps.
+  const int steps_all = ctx->pld / 4;
+  const int steps_used = (ctx->cfg.K + 2) / 2;  // k-steps holding series columns
+  const bool tskip = fused && !ctx->bstore && ctx->cfg.tile_skip != 0 &&
+                     ctx->gemm_variant != kGemmF32 && steps_all <= 32;
+  int64_t tf_ld = 0;
+  int64_t skip_blocks = 0;  // low-rank blocks of the batch's dense passes so far
+  if (tskip) {
+    tf_ld = (n_new + kTileRows - 1) / kTileRows;
+    const int64_t nf = (int64_t)chunk * tf_ld;
+    int64_t nlow = 0;
+    for (const Block& b : plan) nlow += (b.case_id == 0 || b.case_id == 2);
+    const int64_t ns = std::max<int64_t>(1, nlow * steps_used);
+    if (ctx->tflags_cap < nf || ctx->skip_cap < ns) {
+      HC(hipStreamSynchronize(ctx->stream));
+      if (ctx->tflags_cap < nf) {
+        (void)dfree(ctx->d_tflags);
+        ctx->d_tflags = nullptr;
+        ctx->tflags_cap = 0;
+        if (dalloc(&ctx->d_tflags, nf) != hipSuccess) return SR_ENOMEM;
+        ctx->tflags_cap = nf;
+      }
+      if (ctx->skip_cap < ns) {
+        (void)dfree(ctx->d_skip);
+        ctx->d_skip = nullptr;
+        ctx->skip_cap = 0;
+        const int64_t c = std::max<int64_t>(4096, 2 * ns);
+        if (dalloc(&ctx->d_skip, c) != hipSuccess) return SR_ENOMEM;
+        ctx->skip_cap = c;
+      }
+    }
+    HC(hipMemsetAsync(ctx->d_skip, 0, (size_t)ns * 4, ctx->stream));
+  }
   const int64_t replays0 = ctx->graph_replays;
   auto flush = [&]() -> sr_status {
     if (q == 0) return SR_OK;
@@ -2271,6 +2315,10 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     HC(launch_pass_rows(ctx->Pb, ctx->pld, gstride, q, 2 * (ctx->cfg.K + 1), n_new,
                         ctx->d_act_bits, ctx->stream));
     HC(launch_bits_to_list(ctx->d_act_bits, n_new, words, ctx->d_act, cnt_dev, ctx->stream));
+    if (tskip)
+      HC(launch_tile_flags(ctx->Pb, ctx->pld, gstride, q, ctx->d_act, cnt_dev, n_new,
+                           ctx->d_tflags, tf_ld, ctx->d_skip + skip_blocks * steps_used,
+                           steps_used, ctx->stream));
     LowRankArgs la{};
     la.S = ctx->S;
     la.P = ctx->Pb;
@@ -2285,6 +2333,11 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     la.variant = ctx->gemm_variant;
     la.act = ctx->d_act;
     la.act_n = cnt_dev;
+    if (tskip) {
+      la.tflags = ctx->d_tflags;
+      la.tf_ld = tf_ld;
+      skip_blocks += q;
+    }
     HC(run_lowrank(ctx, la));
     pass_blocks.push_back(q);
     ++passes;
@@ -2429,7 +2482,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
   if (stats) {
     HC(hipStreamSynchronize(ctx->stream));
     memset(stats, 0, sizeof(*stats));
-    int64_t entries = 0;
+    int64_t entries = 0, skipped = 0;
     if (!pass_blocks.empty()) {
       // each block of a dense fused pass updates the square of the pass's reached nodes
       std::vector<int64_t> cnts(pass_blocks.size());
@@ -2438,6 +2491,13 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
         pairs += (int64_t)pass_blocks[p] * cnts[p] * cnts[p];
         entries += (int64_t)pass_blocks[p] * (cnts[p] * (cnts[p] + 1) / 2);
       }
+    }
+    if (tskip && skip_blocks > 0) {
+      // a k-step skipped on the tiles of u positions (rows and columns both among them) is
+      // skipped on the u (u + 1) / 2 distinct entries of their triangle
+      std::vector<int32_t> u((size_t)(skip_blocks * steps_used));
+      HC(hipMemcpy(u.data(), ctx->d_skip, u.size() * 4, hipMemcpyDeviceToHost));
+      for (int32_t x : u) skipped += (int64_t)x * (x + 1) / 2;
     }
     stats->edges_in = cnt;
     stats->edges_net = net_edges;
@@ -2449,6 +2509,7 @@ sr_status apply_batch(sr_ctx* ctx, int64_t cnt, const int32_t* bi, const int32_t
     stats->fused_passes = passes;
     stats->series_replays = (int32_t)(ctx->graph_replays - replays0);
     stats->pass_entries = entries;
+    stats->pass_skipped = skipped;
   }
   return SR_OK;
 }

@@ -283,10 +283,28 @@ struct LowRankArgs {
   int32_t variant;    // fused GEMM: tile variant (0 .. kGemmVariants - 1): float64 matrix
                       // cores with panel columns per LDS chunk and LDS pitch (16, 18),
                       // (16, 20), (32, 34), (32, 36); kGemmF32: float32 matrix cores
+  // Fused passes over an active list, float64 matrix cores: when set, tflags[b tf_ld + t]
+  // (launch_tile_flags) has bit g set when block b's columns 4 g and 4 g + 2 (xi_2g, xi_2g+1)
+  // hold a nonzero on list positions 128 t .. 128 t + 127. The tile (I, J) then skips block
+  // b's k-step g (its panel columns 4 g .. 4 g + 3) when neither tile has the bit: each of its
+  // products has a zero xi factor.
+  const uint32_t* tflags;
+  int64_t tf_ld;
 };
 constexpr int kGemmF32 = 4;
 constexpr int kGemmVariants = 5;
+constexpr int kTileRows = 128;  // rows (list positions) of a fused-pass tile
 hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s);
+// Tile flags of a fused pass over the active list act[0 .. *act_n) (see LowRankArgs::tflags):
+// for each of the q panel segments (gstride doubles apart, pld per row, pld / 4 <= 32 k-steps)
+// and each tile t < ceil(*act_n / 128), flags[b tf_ld + t] gets bit g when xi_2g or xi_2g+1
+// (columns 4 g, 4 g + 2) is nonzero on one of the tile's positions; for the first `steps`
+// k-steps, skip[b steps + g] (zeroed by the caller) gains the positions of the tiles whose bit
+// g is clear. n_max bounds *act_n; tf_ld >= ceil(n_max / 128).
+hipError_t launch_tile_flags(const double* P, int pld, int64_t gstride, int q,
+                             const int32_t* act, const int64_t* act_n, int64_t n_max,
+                             uint32_t* flags, int64_t tf_ld, int32_t* skip, int steps,
+                             hipStream_t s);
 // The nodes a fused pass reaches: bit a of bm (ceil(n / 32) words, zeroed by the caller) is set
 // when row a of any of the q panel segments (gstride doubles apart, pld per row) has a nonzero
 // entry among its first w columns.

@@ -12,7 +12,10 @@
 //  - lowrank_cols_kernel, columns of Delta S for the column-by-column method (r <= 32, float32
 //    output): bound by FP64 matrix throughput and the output writes.
 //  - lowrank_gemm_kernel, fused batches (r = 32 B): bound by FP64 matrix throughput. Only
-//    the upper triangle of tiles is computed (the update is symmetric).
+//    the upper triangle of tiles is computed (the update is symmetric). xi_k vanishes outside
+//    the nodes k out-steps from the block's sink (the A_k of Theorem 4), so over a pass's
+//    reached nodes a tile skips the early k-steps of the blocks whose xi columns are zero on
+//    both of its row ranges (tile_flags_kernel marks them).
 #include "kernels.h"
 
 namespace sr {
@@ -466,6 +469,17 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[s][q] = dbl4{0.0, 0.0, 0.0, 0.0};
 
+  // kSymAct with tile flags: the k-steps of a block whose xi factors vanish on both tiles are
+  // skipped (exact zeros, so the sums are bit for bit those of the full loop)
+  [[maybe_unused]] const uint32_t* tfI = nullptr;
+  [[maybe_unused]] const uint32_t* tfJ = nullptr;
+  if constexpr (MODE == kSymAct) {
+    if (g.tflags) {
+      tfI = g.tflags + I;
+      tfJ = g.tflags + J;
+    }
+  }
+
   load(0);
   store(0);
   __syncthreads();
@@ -473,8 +487,15 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
     const int buf = ch & 1;
     // the last chunk reloads itself (uniform, harmless) so the loop body has no branch
     load(ch + 1 < nch ? ch + 1 : ch);
-#pragma unroll
-    for (int k4 = 0; k4 < GCt; k4 += 4) {
+    uint32_t live = ~0u;  // bit u: k-step u of this chunk runs
+    if constexpr (MODE == kSymAct) {
+      if (tfI) {
+        const int64_t o = (int64_t)((ch * GCt) / g.pld) * g.tf_ld;
+        live = (tfI[o] | tfJ[o]) >> (((ch * GCt) % g.pld) / 4);
+        live = __builtin_amdgcn_readfirstlane(live);
+      }
+    }
+    auto step = [&](int k4) {
       const int c = k4 + lk;
       double av[4], bv[4];
 #pragma unroll
@@ -486,7 +507,12 @@ __global__ __launch_bounds__(NT, WPC) void lowrank_gemm_kernel(LowRankArgs g, in
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           acc[s][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[q], acc[s][q], 0, 0, 0);
-    }
+    };
+    // (a second, branch-free copy of the loop for chunks with every k-step live spilled
+    // accumulators to scratch inside the loop)
+#pragma unroll
+    for (int k4 = 0; k4 < GCt; k4 += 4)
+      if ((live >> (k4 / 4)) & 1u) step(k4);
     // keep the staging stores (and their wait for the global loads) after the MFMAs
     __builtin_amdgcn_sched_barrier(0);
     store(buf ^ 1);
@@ -1094,7 +1120,8 @@ hipError_t launch_lowrank(const LowRankArgs& a, hipStream_t s) {
   if (a.variant < 0 || a.variant >= kGemmVariants) return hipErrorInvalidValue;
   const int gc = a.variant < 2 ? 16 : 32;  // the float32 variant stages 32 columns too
   if (a.rows != nullptr || a.nrows_dev != nullptr || a.Ahat != nullptr || a.out != nullptr ||
-      a.nrows != a.ncols || a.r % gc != 0 || a.pld % gc != 0 || (a.act && !a.act_n))
+      a.nrows != a.ncols || a.r % gc != 0 || a.pld % gc != 0 || (a.act && !a.act_n) ||
+      (a.tflags && (!a.act || a.pld / 4 > 32 || a.tf_ld < (a.nrows + GT - 1) / GT)))
     return hipErrorInvalidValue;
   const int64_t T = (a.nrows + GT - 1) / GT;
   if (a.p_rows < T * GT) return hipErrorInvalidValue;
@@ -1160,6 +1187,59 @@ hipError_t launch_pass_rows(const double* P, int pld, int64_t gstride, int q, in
   if (q > 65535 || w > pld || w % 2 != 0 || pld % 2 != 0) return hipErrorInvalidValue;
   pass_rows_kernel<<<dim3((unsigned)((n + 255) / 256), (unsigned)q), 256, 0, s>>>(P, pld, gstride,
                                                                                   w, n, bm);
+  return hipGetLastError();
+}
+
+// One workgroup per (tile, panel segment), one thread per list position: the thread's bits
+// (k-steps whose xi columns are nonzero on its row) are OR-ed over the tile in LDS.
+static_assert(GT == kTileRows, "fused-pass tiles and tile flags share their row count");
+__global__ __launch_bounds__(kTileRows) void tile_flags_kernel(const double* __restrict__ P,
+                                                               int pld, int64_t gstride,
+                                                               const int32_t* __restrict__ act,
+                                                               const int64_t* __restrict__ act_n,
+                                                               uint32_t* __restrict__ flags,
+                                                               int64_t tf_ld,
+                                                               int32_t* __restrict__ skip,
+                                                               int steps) {
+  __shared__ uint32_t tile_bits;
+  const int64_t cnt = *act_n;
+  const int64_t t = blockIdx.x;
+  const int64_t p0 = t * kTileRows;
+  if (p0 >= cnt) return;  // uniform: past the list's tiles
+  if (threadIdx.x == 0) tile_bits = 0;
+  __syncthreads();
+  const int64_t p = p0 + threadIdx.x;
+  uint32_t bits = 0;
+  if (p < cnt) {
+    const double* row = P + (int64_t)blockIdx.y * gstride + (int64_t)act[p] * pld;
+    for (int c = 0; c < pld; c += 4) {
+      const double2 v0 = *reinterpret_cast<const double2*>(row + c);      // xi_2g, eta_2g
+      const double2 v1 = *reinterpret_cast<const double2*>(row + c + 2);  // xi_2g+1, eta_2g+1
+      if (v0.x != 0.0 || v1.x != 0.0) bits |= 1u << (c / 4);
+    }
+  }
+  if (bits) atomicOr(&tile_bits, bits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t b = tile_bits;
+    flags[(int64_t)blockIdx.y * tf_ld + t] = b;
+    const int32_t size = (int32_t)(cnt - p0 < kTileRows ? cnt - p0 : kTileRows);
+    for (int g = 0; g < steps; ++g)
+      if (!((b >> g) & 1u)) atomicAdd(skip + (int64_t)blockIdx.y * steps + g, size);
+  }
+}
+
+hipError_t launch_tile_flags(const double* P, int pld, int64_t gstride, int q,
+                             const int32_t* act, const int64_t* act_n, int64_t n_max,
+                             uint32_t* flags, int64_t tf_ld, int32_t* skip, int steps,
+                             hipStream_t s) {
+  if (n_max <= 0 || q <= 0) return hipSuccess;
+  const int64_t tiles = (n_max + kTileRows - 1) / kTileRows;
+  if (q > 65535 || pld % 4 != 0 || pld / 4 > 32 || steps < 1 || steps > pld / 4 ||
+      tf_ld < tiles || !act || !act_n || !flags || !skip)
+    return hipErrorInvalidValue;
+  tile_flags_kernel<<<dim3((unsigned)tiles, (unsigned)q), kTileRows, 0, s>>>(
+      P, pld, gstride, act, act_n, flags, tf_ld, skip, steps);
   return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ def default_config(**kw):
             v = _GAMMA[v] if isinstance(v, str) else v
         elif k == "update_prec":
             v = _UPDATE[v] if isinstance(v, str) else v
-        elif k in ("prune", "fused_batch", "profile", "graphs", "block_store"):
+        elif k in ("prune", "fused_batch", "profile", "graphs", "block_store", "tile_skip"):
             v = int(bool(v))
         setattr(cfg, k, v)
     return cfg
@@ -74,7 +74,8 @@ class Context:
     ``sr_config``: C, K, K_ps, s_prec ('fp64' | 'hilo' | 'fp32'), mode ('dense' | 'column'),
     gamma_form ('closed' | 'direct'), prune, node_cap, edge_cap, init_tol, init_max_iter,
     batch_chunk, fused_batch, split_rows, profile, graphs, update_prec ('fp64' | 'fp32'),
-    block_store (partitioned contexts: S kept per pair of blocks, Example 1.1).
+    block_store (partitioned contexts: S kept per pair of blocks, Example 1.1), tile_skip
+    (fused passes skip the k-steps whose xi factors vanish on a tile; the same S bit for bit).
     """
 
     def __init__(self, n, src, dst, weight=None, S0=None, stream=None, init="fixed_point",

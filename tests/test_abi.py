@@ -49,7 +49,7 @@ def test_default_config_and_strerror():
     assert L.sr_default_config(ctypes.byref(cfg)) == 0
     assert cfg.C == 0.6 and cfg.K == 15 and cfg.K_ps == 30 and cfg.prune == 1
     assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 0 and cfg.split_rows == 4096
-    assert cfg.profile == 0 and cfg.graphs == 1
+    assert cfg.profile == 0 and cfg.graphs == 1 and cfg.tile_skip == 1 and cfg.block_store == 0
     assert L.sr_strerror(-3) == b"edge exists"
     assert L.sr_default_config(None) == _lib.SR_EINVAL
 
@@ -65,21 +65,25 @@ def test_null_context_arguments_are_rejected_without_gpu():
 
 
 def test_chunk_bound_is_refused_before_any_gpu_work():
-    """batch_chunk above 65,535 (one grid row per deferred block in the per-pass kernels) is
-    a validation error of the configuration, reported before the device is touched."""
+    """batch_chunk above 65,535 (one grid row per deferred block in the per-pass kernels) and a
+    tile_skip other than 0 or 1 are validation errors of the configuration, reported before the
+    device is touched."""
     import ctypes as C
     import numpy as np
     from paper_1711_00121_amd import _lib
     L = lib()
     cfg = _lib.sr_config()
     assert L.sr_default_config(C.byref(cfg)) == _lib.SR_OK
-    cfg.batch_chunk = 65536
     src = np.asarray([0, 1], dtype=np.int32)
     dst = np.asarray([1, 2], dtype=np.int32)
-    h = C.c_void_p()
-    st = L.init_simrank(C.byref(h), 3, 2, src.ctypes.data_as(C.POINTER(C.c_int32)),
-                        dst.ctypes.data_as(C.POINTER(C.c_int32)), None, C.byref(cfg), None, None)
-    assert st == _lib.SR_EINVAL and not h.value
+    for field, bad in (("batch_chunk", 65536), ("tile_skip", 2), ("tile_skip", -1)):
+        assert L.sr_default_config(C.byref(cfg)) == _lib.SR_OK
+        setattr(cfg, field, bad)
+        h = C.c_void_p()
+        st = L.init_simrank(C.byref(h), 3, 2, src.ctypes.data_as(C.POINTER(C.c_int32)),
+                            dst.ctypes.data_as(C.POINTER(C.c_int32)), None, C.byref(cfg), None,
+                            None)
+        assert st == _lib.SR_EINVAL and not h.value, (field, bad)
 
 
 def test_device_bytes_without_contexts():

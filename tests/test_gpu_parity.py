@@ -653,3 +653,42 @@ def test_fused_passes_cover_the_reached_nodes_only(update_prec):
     sinkless = np.setdiff1d(np.arange(n // 2, n), np.asarray(tr.arrays()[1]))
     assert np.array_equal(S[sinkless], S0[sinkless])
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "hilo"])
+@pytest.mark.parametrize("K", [15, 10])
+def test_tile_skip_is_bit_exact(prec, K):
+    """xi_k vanishes outside the nodes k out-steps from a block's sink, so a fused pass skips,
+    per 128 x 128 tile, the k-steps whose xi factors are zero on both of the tile's row ranges.
+    The skipped products are exact zeros: two contexts, tile skipping on and off, take the same
+    two batches at n = 3000 (the reached nodes span ~17 tiles and a ragged tail; chunks of 8
+    blocks) and hold the same S bit for bit, after each batch. At K = 10 the panel's last
+    columns are zero padding (22 of 32), skipped too, and not counted as skipped work."""
+    n = 3000
+    s, d = W.chung_lu(n, 24000, seed=81)
+    kw = dict(s_prec=prec, fused_batch=True, batch_chunk=8, K=K, edge_cap=24000 + 2000)
+    on = ctx_for(n, s, d, **kw)
+    off = ctx_for(n, s, d, tile_skip=False, **kw)
+    tr = EdgeTracker(n, s, d)
+    steps = (K + 2) // 2
+    for b in range(2):
+        cs, cd = tr.arrays()
+        bi, bj, bo = (np.asarray(x) for x in _existing_batch(n, cs, cd, seed=82 + b, n_ins=150,
+                                                              n_del=50, shared=20))
+        sa = on.apply_batch(bi, bj, bo, stats=True)
+        sb = off.apply_batch(bi, bj, bo, stats=True)
+        plus, minus = OI.net_update(bi, bj, bo)
+        for (i, j) in minus:
+            tr.apply(i, j, -1)
+        for (i, j) in plus:
+            tr.apply(i, j, 1)
+        frac = sa["pass_skipped"] / max(sa["pass_entries"] * steps, 1)
+        print(f"K={K} {prec} batch {b}: {sa['fused_passes']} passes, skipped {frac:.3f} of "
+              f"the entry k-steps", flush=True)
+        assert sa["pass_entries"] == sb["pass_entries"] and sa["pairs"] == sb["pairs"]
+        assert sb["pass_skipped"] == 0 and 0 < sa["pass_skipped"] < sa["pass_entries"] * steps
+        Sa, Sb = on.S().cpu().numpy(), off.S().cpu().numpy()
+        assert np.array_equal(Sa.view(np.uint64), Sb.view(np.uint64))
+        assert np.array_equal(Sa, Sa.T)
+    on.close()
+    off.close()
