@@ -95,7 +95,7 @@ typedef struct sr_config {
   int32_t split_rows;    /* graph rows (in- or out-lists) with more entries are traversed in
                             chunks of 4096 entries, one workgroup each, whose partial sums a
                             second small launch adds; rows of 2049 .. split_rows entries take
-                            one workgroup. 0 means 4096; otherwise at least 2048             */
+                            one workgroup. 0 means 8192; otherwise at least 2048             */
   int32_t profile;       /* 1: time the S-update launches from creation on (as sr_profile(1)),
                             so that those inside init_simrank_tree are counted too          */
   int32_t graphs;        /* 1: fused batches capture each block's K-step series chain as a HIP

@@ -52,12 +52,15 @@ struct IdList {
 // rows (at most kMedium entries) are handled by one wave each, "heavy" rows (up to a split
 // threshold, kSplitRows by default) by a workgroup, and "huge" rows are cut into chunks of
 // kChunk entries, one workgroup per chunk, whose partial sums a second small launch adds up
-// in chunk order. The second launch costs a few microseconds; splitting at one chunk's worth
-// measured +3% on batches at n = 58k-92k (the hubs' rows trail every series step otherwise),
-// +1% on the n = 1M column workloads and no change on the n = 20k stream.
+// in chunk order. The second launch costs a few microseconds, about what a workgroup takes for
+// one or two more rounds of a row's loads, so only long rows gain from it: splitting above two
+// chunks' worth measured +3% on batches at n = 58k-92k (the hubs' rows, up to ~34k entries,
+// trail every series step otherwise), the same as splitting above one chunk, while at
+// n = 20k, whose one row above a chunk holds 5.5k entries, splitting it cost 10% of the
+// forest-seeded pipeline.
 constexpr int kLight = 64;
 constexpr int kMedium = 2048;
-constexpr int kSplitRows = 4096;
+constexpr int kSplitRows = 8192;
 constexpr int kChunk = 4096;
 struct HeavyArgs {
   const int32_t* med;    // medium row ids (device), ascending

@@ -48,7 +48,7 @@ def test_default_config_and_strerror():
     cfg = _lib.sr_config()
     assert L.sr_default_config(ctypes.byref(cfg)) == 0
     assert cfg.C == 0.6 and cfg.K == 15 and cfg.K_ps == 30 and cfg.prune == 1
-    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 0 and cfg.split_rows == 4096
+    assert cfg.init_tol == 1e-15 and cfg.batch_chunk == 0 and cfg.split_rows == 8192
     assert cfg.profile == 0 and cfg.graphs == 1 and cfg.tile_skip == 1 and cfg.block_store == 0
     assert L.sr_strerror(-3) == b"edge exists"
     assert L.sr_default_config(None) == _lib.SR_EINVAL
