@@ -103,3 +103,61 @@ def test_aff_pair_count_formula():
         Ah = np.unique(rng.integers(0, n, 12))
         Bh = np.unique(rng.integers(0, n, 17))
         assert I.aff_pair_count(Ah, Bh) == int(I.aff_pairs(Ah, Bh, n).sum())
+
+
+def test_xi_lives_on_the_sinks_k_step_out_walks():
+    """xi_0 = C e_j and xi_{k+1} = C Qt xi_k with Qt = Q + u v^T the new graph's transition
+    matrix, so xi_k is zero outside W_k, the nodes reached from the sink j by a walk of exactly
+    k out-steps in the new graph (W_0 = {j}, W_{k+1} = out_new(W_k)), computed here by boolean
+    steps on the edge list. The fused pass's tile skipping rests on this sparsity. The series
+    run on the new graph's Q (as the device runs it) is supported on W_k exactly and equals the
+    oracle's series; the oracle's own form, old Q plus the rank-one term, is too on insertions,
+    while on deletions the deleted edge's term in row j cancels only to rounding, leaving
+    residues below 1e-15 of the vector's size that walk on from j. Insertion and deletion
+    blocks on random graphs; on insertions the first steps fill W_k (all terms nonnegative)."""
+    rng = np.random.default_rng(2024)
+    K = 6
+    for trial in range(30):
+        n = int(rng.integers(12, 40))
+        s, d = rand_graph(rng, n, 0.12)
+        if len(s) < 3:
+            continue
+        es = set(zip(s.tolist(), d.tolist()))
+        op = 1 if trial % 2 == 0 else -1
+        if op > 0:
+            j = int(rng.integers(n))
+            cand = [i for i in range(n) if i != j and (i, j) not in es]
+            I_ = sorted(rng.choice(cand, size=min(3, len(cand)), replace=False).tolist())
+        else:
+            j = int(d[rng.integers(len(d))])
+            srcs = sorted(int(a) for a, b in es if b == j)
+            I_ = srcs[:max(1, len(srcs) // 2)]
+        Q = Gr.transition_matrix(n, s, d)
+        deg = np.bincount(d, minlength=n)
+        S = O.fixed_point(Q, C)
+        _, info = I.inc_block(Q, S, deg, I_, j, C, K, op)
+        new = es | {(i, j) for i in I_} if op > 0 else es - {(i, j) for i in I_}
+        out = [[] for _ in range(n)]
+        for a, b in new:
+            out[a].append(b)
+        ns, nd = zip(*sorted(new)) if new else ((), ())
+        Qn = Gr.transition_matrix(n, np.asarray(ns, np.int64), np.asarray(nd, np.int64))
+        xn = np.zeros(n)
+        xn[j] = C
+        W = {j}
+        for k in range(K + 1):
+            Xi = info["Xi"][:, k]
+            scale = max(float(np.max(np.abs(Xi))), 1e-300)
+            nz = set(np.nonzero(xn)[0].tolist())
+            assert nz <= W, (trial, k, sorted(nz - W))
+            assert np.max(np.abs(xn - Xi)) <= 1e-12 * scale, (trial, k)
+            out_w = np.ones(n, dtype=bool)
+            out_w[list(W)] = False
+            if op > 0:
+                assert not np.any(Xi[out_w]), (trial, k)
+                if k <= 2:
+                    assert nz == W, (trial, k)
+            else:
+                assert np.max(np.abs(Xi[out_w]), initial=0.0) <= 1e-15 * scale, (trial, k)
+            W = {b for a in W for b in out[a]}
+            xn = C * (Qn @ xn)
