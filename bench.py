@@ -342,11 +342,7 @@ def run_batch(args):
                                "block, r the nodes its fused pass reaches (nonzero panel "
                                "rows), less 8 flop per entry of each k-step a tile skips "
                                "(the block's xi factors vanish on both of its row ranges)",
-                "skipped_fraction": round(1.0 - flops / dense_flops, 4) if dense_flops else 0.0,
-                # the same passes over all 4 (K + 1) flop per entry, the skipped zero products
-                # counted as done (not a hardware rate: it can exceed the peak)
-                "frac_all_steps": round(dense_flops / (kern_ms / 1e3) / 1e12 / peak, 4)
-                                  if dense_flops else None}
+                "skipped_fraction": round(1.0 - flops / dense_flops, 4) if dense_flops else 0.0}
     else:
         roof = hbm_roof(16.0 * pairs, kern_ms, "lowrank_strip_kernel", launches,
                         "16 B per pair-update (S value + compensation, read + write)",
